@@ -1,0 +1,279 @@
+"""Pins of the oracle against facts that do not come from the oracle itself:
+exact rational arithmetic, integer exactness, closed forms, transpose
+identities, the bilinearity of the gradient, library rounding routines and the
+paper's printed performance-model values."""
+import json
+import math
+import os
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _exact_matmul(A, B):
+    m, k = A.shape
+    n = B.shape[1]
+    return [[sum((Fraction(float(A[i, j])) * Fraction(float(B[j, p]))
+                  for j in range(k)), Fraction(0)) for p in range(n)]
+            for i in range(m)]
+
+
+# --------------------------------------------------------------- brute force
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_matches_exact_rationals(seed):
+    """Every (m,k,n) in 1..5 plus random larger shapes: the oracle's double
+    result is within the sequential-summation bound of the exact rational
+    result (|C - C_exact| <= gamma_k * (|A||B|), Higham, Accuracy and
+    Stability of Numerical Algorithms, eq. 3.13)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(m, k, n) for m in range(1, 6) for k in range(1, 6)
+              for n in range(1, 6)] if seed == 0 else \
+        [tuple(int(x) for x in rng.integers(1, 20, 3)) for _ in range(40)]
+    u = 2.0 ** -53
+    for (m, k, n) in shapes:
+        A = rng.uniform(-1, 1, (m, k))
+        B = rng.uniform(-1, 1, (k, n))
+        C = oracle.matmul(np.asfortranarray(A), np.asfortranarray(B))
+        E = _exact_matmul(A, B)
+        absAB = np.abs(A) @ np.abs(B)
+        gamma = k * u / (1 - k * u)
+        for i in range(m):
+            for p in range(n):
+                err = abs(Fraction(float(C[i, p])) - E[i][p])
+                assert err <= Fraction(gamma * absAB[i, p] * 1.0000001), (m, k, n, i, p)
+
+
+def test_dropped_term_would_be_caught():
+    """A sanity check of the pin itself: leaving out one product moves the
+    result far outside the rounding bound."""
+    rng = np.random.default_rng(11)
+    A = rng.uniform(-1, 1, (4, 7))
+    B = rng.uniform(-1, 1, (7, 3))
+    C = oracle.matmul(A, B)
+    C_bad = oracle.matmul(A[:, :6], B[:6, :])
+    E = np.array([[float(x) for x in row] for row in _exact_matmul(A, B)])
+    assert np.abs(C - E).max() < 1e-14
+    assert np.abs(C_bad - E).max() > 1e-6
+
+
+# ---------------------------------------------------------------- integers
+@pytest.mark.parametrize("m,k,n", [(33, 70, 5), (1, 1, 1), (64, 257, 16), (7, 1, 32)])
+def test_integer_inputs_bit_exact(m, k, n):
+    """Integer-valued inputs with |a|,|b| <= 2^10 keep every partial sum below
+    2^53, so the double result equals the integer result exactly."""
+    rng = np.random.default_rng(m * 1000 + k)
+    Ai = rng.integers(-1024, 1025, (m, k))
+    Bi = rng.integers(-1024, 1025, (k, n))
+    C = oracle.matmul(np.asfortranarray(Ai.astype(np.float64)),
+                      np.asfortranarray(Bi.astype(np.float64)))
+    ref = [[sum(int(Ai[i, j]) * int(Bi[j, p]) for j in range(k)) for p in range(n)]
+           for i in range(m)]
+    assert np.array_equal(C, np.array(ref, dtype=np.float64))
+
+
+# ------------------------------------------------------------- closed forms
+def test_ones_column_gives_row_sums():
+    rng = np.random.default_rng(3)
+    m, k = 50, 301
+    A = np.asfortranarray(rng.uniform(-1, 1, (m, k)))
+    C = oracle.matmul(A, np.ones((k, 1)))
+    for i in range(m):
+        exact = math.fsum(A[i, :])
+        assert abs(C[i, 0] - exact) <= k * 2.0 ** -53 * np.abs(A[i, :]).sum()
+
+
+def test_unit_vectors_identity_permutation_scaling_zero():
+    rng = np.random.default_rng(4)
+    m, k = 37, 9
+    A = np.asfortranarray(rng.uniform(-1, 1, (m, k)))
+    for j in range(k):
+        e = np.zeros((k, 1))
+        e[j, 0] = 1.0
+        assert np.array_equal(oracle.matmul(A, e)[:, 0], A[:, j])
+    assert np.array_equal(oracle.matmul(A, np.eye(k)), A)
+    perm = rng.permutation(k)
+    P = np.eye(k)[:, perm]
+    assert np.array_equal(oracle.matmul(A, P), A[:, perm])
+    assert np.array_equal(oracle.matmul(A, 8.0 * np.eye(k)), 8.0 * A)
+    assert np.array_equal(oracle.matmul(np.zeros((m, k)), rng.uniform(-1, 1, (k, 4))),
+                          np.zeros((m, 4)))
+
+
+def test_empty_inner_dimension_gives_zeros():
+    C = oracle.matmul(np.zeros((5, 0)), np.zeros((0, 3)))
+    assert C.shape == (5, 3) and np.all(C == 0)
+
+
+def test_linearity_in_B():
+    rng = np.random.default_rng(5)
+    A = rng.uniform(-1, 1, (20, 40))
+    B1 = rng.uniform(-1, 1, (40, 3))
+    B2 = rng.uniform(-1, 1, (40, 3))
+    lhs = oracle.matmul(A, B1 + B2)
+    rhs = oracle.matmul(A, B1) + oracle.matmul(A, B2)
+    assert np.abs(lhs - rhs).max() < 1e-13
+
+
+# --------------------------------------------------------------- transposes
+def test_memory_order_and_transpose_identity():
+    """Row-major and column-major storage give identical bits, and
+    (A*B)^T = B^T*A^T with the same products in the same order."""
+    rng = np.random.default_rng(6)
+    A = rng.uniform(-1, 1, (31, 45))
+    B = rng.uniform(-1, 1, (45, 7))
+    C_f = oracle.matmul(np.asfortranarray(A), np.asfortranarray(B))
+    C_c = oracle.matmul(np.ascontiguousarray(A), np.ascontiguousarray(B))
+    assert np.array_equal(C_f, C_c)
+    Ct = oracle.matmul(B.T, A.T)
+    assert np.array_equal(Ct, C_f.T)
+
+
+# ---------------------------------------------------------------- gradients
+def test_grad_against_exact_rationals():
+    rng = np.random.default_rng(7)
+    m, k, n = 6, 5, 4
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (k, n))
+    dC = rng.normal(size=(m, n))
+    dA, dB = oracle.grad(A, B, dC)
+    for i in range(m):
+        for j in range(k):
+            e = sum(Fraction(float(dC[i, p])) * Fraction(float(B[j, p])) for p in range(n))
+            assert abs(Fraction(float(dA[i, j])) - e) < Fraction(1, 10 ** 14)
+    for j in range(k):
+        for p in range(n):
+            e = sum(Fraction(float(A[i, j])) * Fraction(float(dC[i, p])) for i in range(m))
+            assert abs(Fraction(float(dB[j, p])) - e) < Fraction(1, 10 ** 14)
+
+
+def test_grad_directional_derivative():
+    """L(A,B) = <dC, A*B> is bilinear, so the central difference
+    (L(A+eV) - L(A-eV)) / 2e equals <dA, V> up to rounding; likewise in B.
+    L is evaluated with numpy, independently of the oracle."""
+    rng = np.random.default_rng(8)
+    m, k, n = 300, 24, 16
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (k, n))
+    dC = rng.normal(size=(m, n))
+    dA, dB = oracle.grad(A, B, dC)
+
+    def L(A_, B_):
+        return float(np.sum(dC * (A_ @ B_)))
+
+    V = rng.normal(size=(m, k))
+    W = rng.normal(size=(k, n))
+    eps = 0.5
+    fdA = (L(A + eps * V, B) - L(A - eps * V, B)) / (2 * eps)
+    fdB = (L(A, B + eps * W) - L(A, B - eps * W)) / (2 * eps)
+    assert abs(fdA - np.sum(dA * V)) <= 1e-10 * (1 + abs(fdA))
+    assert abs(fdB - np.sum(dB * W)) <= 1e-10 * (1 + abs(fdB))
+
+
+# ----------------------------------------------------------------- rounding
+def _special_values():
+    vals = [0.0, -0.0, 1.0, -1.0, 3.0e38, -3.0e38, 1e-40, -1e-40, 65504.0,
+            65519.99, 65520.0, 2.0 ** -24, 2.0 ** -25, 3 * 2.0 ** -26, 2.0 ** -14,
+            1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11,
+            float("inf"), float("-inf"), 2.0 ** -133, 2.0 ** -134, 3 * 2.0 ** -135]
+    return np.array(vals, dtype=np.float32)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(9)
+    x = np.concatenate([
+        rng.uniform(-1, 1, 20000).astype(np.float32),
+        (rng.standard_normal(20000) * 10.0 ** rng.integers(-40, 38, 20000)).astype(np.float32),
+        _special_values()])
+    ours = oracle.round_fmt(x.astype(np.float64), oracle.BF16)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_f16_rounding_matches_numpy():
+    rng = np.random.default_rng(10)
+    x = np.concatenate([
+        rng.uniform(-1, 1, 20000).astype(np.float32),
+        (rng.standard_normal(20000) * 10.0 ** rng.integers(-9, 6, 20000)).astype(np.float32),
+        _special_values()])
+    ours = oracle.round_fmt(x.astype(np.float64), oracle.F16)
+    ref = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(ours, ref)
+
+
+@pytest.mark.parametrize("fmt", [oracle.BF16, oracle.F16])
+def test_encode_decode_all_patterns(fmt):
+    """decode is checked against the library's reinterpretation of all 2^16
+    patterns; encode(decode(h)) == h for every non-NaN pattern."""
+    pats = np.arange(65536, dtype=np.uint16)
+    dec = oracle.decode_plane(pats, fmt)
+    if fmt == oracle.BF16:
+        ref = torch.from_numpy(pats.view(np.int16)).view(torch.bfloat16).to(torch.float64).numpy()
+    else:
+        ref = pats.view(np.float16).astype(np.float64)
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(dec), nan)
+    assert np.array_equal(dec[~nan], ref[~nan])
+    for h in range(0, 65536, 7):
+        if not nan[h]:
+            assert oracle.encode(dec[h], fmt) == h
+
+
+def test_split_bf16_error_and_hi():
+    rng = np.random.default_rng(12)
+    a = rng.uniform(-1, 1, 50000).astype(np.float32)
+    hi, lo = oracle.split(a, oracle.BF16)
+    ref_hi = torch.from_numpy(a).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(hi, ref_hi)
+    v = oracle.decode_plane(hi, 0) + oracle.decode_plane(lo, 0)
+    assert np.all(np.abs(a.astype(np.float64) - v) <= 2.0 ** -16 * np.abs(a))
+    # the single form alone is within half a bfloat16 ulp
+    assert np.all(np.abs(a - oracle.decode_plane(hi, 0)) <= 2.0 ** -8 * np.abs(a))
+
+
+def test_split_f16_error_normal_range():
+    rng = np.random.default_rng(13)
+    a = rng.uniform(0.125, 1, 50000).astype(np.float32) * rng.choice([-1, 1], 50000).astype(np.float32)
+    hi, lo = oracle.split(a, oracle.F16)
+    assert np.array_equal(hi, a.astype(np.float16).view(np.uint16))
+    v = oracle.decode_plane(hi, 1) + oracle.decode_plane(lo, 1)
+    assert np.all(np.abs(a.astype(np.float64) - v) <= 2.0 ** -22 * np.abs(a))
+
+
+def test_split_integer_values_have_zero_lo():
+    a = np.arange(-256, 257, dtype=np.float32)
+    hi, lo = oracle.split(a, oracle.BF16)
+    assert np.all(oracle.decode_plane(lo, 0) == 0)
+    assert np.array_equal(oracle.decode_plane(hi, 0), a)
+
+
+# ------------------------------------------------------------ perf model
+def test_t2_threshold_reproduces_paper_values():
+    g = json.load(open(os.path.join(GOLDEN, "t2_threshold.json")))
+    bpe = g["bytes_per_element"]
+    by_name = {}
+    for row in g["gpus"]:
+        t2 = oracle.t2_threshold(row["peak_fp64_gflops"], row["peak_bw_gbs"], bpe)
+        by_name[row["gpu"]] = t2
+        assert abs(t2 - row["paper_t2_threshold"]) <= 0.1 * row["paper_t2_threshold"], row
+    for claim in g["regime_claims"]:
+        bound = "memory" if claim["n"] <= by_name[claim["gpu"]] else "compute"
+        assert bound == claim["bound"], claim
+
+
+def test_mi355x_ridge_is_far_above_32():
+    # 78.6 TFLOP/s FP64 vector, 8 TB/s HBM3E: every n <= 32 is memory-bound.
+    assert oracle.t2_threshold(78600, 8000, 8) > 32
+    assert oracle.t2_threshold(78600, 8000, 4) > 32   # FP32 FMA without packing
+
+
+def test_normwise_error():
+    assert oracle.normwise_error([[3.0, 4.0]], [[0.0, 0.0]]) == 5.0
+    assert oracle.normwise_error([[1.0, 1.0]], [[1.0, 1.0]]) == 0.0
+    assert abs(oracle.normwise_error([[1.1]], [[1.0]]) - 0.1) < 1e-12

@@ -1,0 +1,176 @@
+/*
+ * tsm2x.h -- C ABI of the MI355X (gfx950) tall-and-skinny matrix-multiply
+ * library.  It implements the two problem classes of TSM2X (Rivera, Chen,
+ * Xiong, Zhang, Song, Tao, "TSM2X: High-Performance Tall-and-Skinny
+ * Matrix-Matrix Multiplication on GPUs"):
+ *
+ *   TSM2R  C = A*B, A a large regular m-by-k matrix, B a skinny k-by-n
+ *          matrix, n <= 32 (Design of TSM2R, Algorithms 2-4).
+ *   TSM2L  C = A*B, A a tall-and-skinny m-by-k matrix with k <= 32, B a
+ *          small k-by-n matrix, n <= 32 (Design of TSM2L, Algorithm 6).
+ *
+ * plus the two products of the backward pass of C = A*B (for a scalar loss
+ * with upstream gradient dC): dA = dC*B^T and dB = A^T*dC, and the hi+lo
+ * low-precision storage form of A.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are column-major ("by convention", Design of TSM2R, Efficient
+ *    Off-Chip Memory Access): element (i,j) of X with leading dimension ldX
+ *    is X[i + j*ldX].  tsm2r_ex also accepts a row-major A.
+ *  - All matrix pointers are DEVICE pointers owned by the caller; the library
+ *    never frees or retains them.  `stream` is a hipStream_t (NULL = the
+ *    null stream).  Every call is asynchronous on `stream`; a return value of
+ *    0 means the work was enqueued.
+ *  - The output is overwritten, never read (C := A*B, not C += A*B).
+ *  - m == 0 or n == 0 (or, for the gradients, an empty output) is a no-op.
+ *    k == 0 writes zeros.
+ *  - Results are deterministic: a repeated call on the same inputs gives the
+ *    same bits (fixed reduction orders, no floating-point atomics).
+ *  - Arguments are checked on the host before any HIP call.  An invalid
+ *    argument returns -i, i being its 1-based position (LAPACK style).
+ *    Positive codes are TSM_ERR_*; tsm2x_error_string() describes them.
+ *
+ * Workspace
+ * ---------
+ *  Kernels that split a reduction across workgroups need a workspace of
+ *  tsm2x_workspace_size() bytes.  The *_ws entry points take it from the
+ *  caller: it must be device memory, 256-byte aligned, and zero-filled
+ *  before its first use (the library leaves it in that state after every
+ *  call, so the same buffer can be reused).  The other entry points use a
+ *  grow-only per-device buffer owned by the library (allocated with hipMalloc
+ *  on first need, released by tsm2x_finalize).  Two calls that share one
+ *  workspace must not run concurrently (e.g. on two streams).
+ */
+#ifndef TSM2X_H
+#define TSM2X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage types.
+ *   TSM_F64        A, B, C double.
+ *   TSM_F32        A, B, C float.
+ *   TSM_BF16 / TSM_F16
+ *                  A is one plane of bfloat16 / binary16 values (the "hi"
+ *                  plane of tsm2x_split); B and C are float.
+ *   TSM_BF16_SPLIT / TSM_F16_SPLIT
+ *                  A is two planes, hi then lo, each lda*k elements, the lo
+ *                  plane starting at element lda*k after the hi plane.  The
+ *                  represented value is hi + lo.  B and C are float.        */
+typedef enum {
+    TSM_F64 = 0,
+    TSM_F32 = 1,
+    TSM_BF16 = 2,
+    TSM_F16 = 3,
+    TSM_BF16_SPLIT = 4,
+    TSM_F16_SPLIT = 5
+} tsm_dtype;
+
+typedef enum { TSM_COL_MAJOR = 0, TSM_ROW_MAJOR = 1 } tsm_order;
+
+/* Operations, for tsm2x_workspace_size. */
+typedef enum {
+    TSM_OP_TSM2R = 0,
+    TSM_OP_TSM2L = 1,
+    TSM_OP_GRAD_A = 2,
+    TSM_OP_GRAD_B = 3,
+    TSM_OP_TSM2R_ROWMAJOR = 4
+} tsm_op;
+
+enum {
+    TSM_SUCCESS = 0,
+    TSM_ERR_UNSUPPORTED = 1, /* valid arguments outside the supported shapes/types */
+    TSM_ERR_HIP = 2,         /* a HIP call failed; see tsm2x_last_hip_error()   */
+    TSM_ERR_WORKSPACE = 3,   /* caller workspace too small or misaligned         */
+    TSM_ERR_ALLOC = 4        /* the library's workspace could not be allocated   */
+};
+
+/* TSM2R: C = A*B, A m-by-k (lda >= max(1,m)), B k-by-n (ldb >= max(1,k)),
+ * C m-by-n (ldc >= max(1,m)), n <= 32.  A is streamed from memory once
+ * (outer-product form of Algorithm 2 with the on-chip B tile of
+ * Algorithms 3-4); the k range is split across wavefronts and workgroups and
+ * the partial sums are added in double precision in a fixed order.
+ * dtype: any tsm_dtype.  Errors: -1..-11 for arguments 1..11,
+ * TSM_ERR_UNSUPPORTED if n > 32. */
+int tsm2r(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+          const void* B, int64_t ldb, void* C, int64_t ldc, int dtype,
+          void* stream);
+
+/* TSM2R with a caller workspace (ws, ws_bytes; see "Workspace") and the
+ * storage order of A.  order == TSM_ROW_MAJOR: element (i,j) of A is
+ * A[i*lda + j], lda >= max(1,k); supported for TSM_F64 and TSM_F32.
+ * Arguments: 1 order, 2 m, 3 k, 4 n, 5 A, 6 lda, 7 B, 8 ldb, 9 C, 10 ldc,
+ * 11 dtype, 12 ws, 13 ws_bytes, 14 stream.  ws may be NULL when
+ * tsm2x_workspace_size() is 0. */
+int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A,
+             int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc,
+             int dtype, void* ws, size_t ws_bytes, void* stream);
+
+/* TSM2L: C = A*B, A m-by-k with k <= 32, B k-by-n with n <= 32 (Algorithm 6:
+ * horizontal tiles of A processed by a persistent grid; B is held on chip
+ * whole, so C is written exactly once and never re-read).
+ * dtype: TSM_F64 or TSM_F32.  Errors as tsm2r; TSM_ERR_UNSUPPORTED if
+ * k > 32 or n > 32. */
+int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+          const void* B, int64_t ldb, void* C, int64_t ldc, int dtype,
+          void* stream);
+
+/* Gradient with respect to A of L = <dC, A*B>:  dA = dC * B^T.
+ * dC m-by-n (lddc >= max(1,m)), B k-by-n (ldb >= max(1,k)),
+ * dA m-by-k (ldda >= max(1,m)); n <= 32, any k.  Each dC row is read once;
+ * dA is written once.  dtype: TSM_F64 or TSM_F32 (dC, B, dA all of it).
+ * Arguments: 1 m, 2 k, 3 n, 4 dC, 5 lddc, 6 B, 7 ldb, 8 dA, 9 ldda,
+ * 10 dtype, 11 stream. */
+int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc,
+               const void* B, int64_t ldb, void* dA, int64_t ldda, int dtype,
+               void* stream);
+
+/* Gradient with respect to B of L = <dC, A*B>:  dB = A^T * dC.
+ * A m-by-k (lda >= max(1,m)), dC m-by-n (lddc >= max(1,m)),
+ * dB k-by-n (lddb >= max(1,k)); n <= 32, any m and k.  The reduction over
+ * m is split across wavefronts and workgroups and finished in double
+ * precision in a fixed order.
+ * dtype: TSM_F64, TSM_F32 (A, dC, dB all of it), or a 16-bit form of A as in
+ * tsm2r (dC and dB float).
+ * Arguments: 1 m, 2 k, 3 n, 4 A, 5 lda, 6 dC, 7 lddc, 8 dB, 9 lddb,
+ * 10 dtype, 11 ws, 12 ws_bytes, 13 stream (ws may be NULL: library buffer). */
+int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+               const void* dC, int64_t lddc, void* dB, int64_t lddb,
+               int dtype, void* ws, size_t ws_bytes, void* stream);
+
+/* Low-precision storage form of A: from a float m-by-k matrix A (lda),
+ * write hi = RNE(a) and, if lo != NULL, lo = RNE(a - hi) (a - hi is exact in
+ * float) as bfloat16 (fmt 0) or binary16 (fmt 1) planes of leading dimension
+ * ldh (>= max(1,m)).  RNE = round to nearest, ties to even; NaN stays NaN;
+ * values beyond the binary16 range become +-inf.
+ * Arguments: 1 m, 2 k, 3 A, 4 lda, 5 hi, 6 lo, 7 ldh, 8 fmt, 9 stream. */
+int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi,
+                void* lo, int64_t ldh, int fmt, void* stream);
+
+/* Bytes of workspace the call (op, m, k, n, dtype) needs; 0 if none. */
+size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n,
+                            int dtype);
+
+/* Static description of an error code (never NULL). */
+const char* tsm2x_error_string(int code);
+
+/* Message of the last HIP failure seen by this thread ("" if none). */
+const char* tsm2x_last_hip_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int tsm2x_version(void);
+
+/* Release the library-owned workspaces of every device.  No call may be in
+ * flight. */
+void tsm2x_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSM2X_H */

@@ -1,0 +1,77 @@
+"""ctypes view of libtsm2x.so (the C ABI of include/tsm2x.h).
+
+Argument marshalling only: every product runs in the library's HIP kernels.
+If the library has not been built, loading raises immediately; there is no
+fallback implementation."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsm2x.so")
+
+F64, F32, BF16, F16, BF16_SPLIT, F16_SPLIT = range(6)
+COL_MAJOR, ROW_MAJOR = 0, 1
+OP_TSM2R, OP_TSM2L, OP_GRAD_A, OP_GRAD_B, OP_TSM2R_ROWMAJOR = range(5)
+
+_lock = threading.Lock()
+_lib = None
+
+
+class TSMError(RuntimeError):
+    def __init__(self, fn: str, code: int, lib):
+        msg = lib.tsm2x_error_string(code).decode()
+        if code == 2:
+            msg += ": " + lib.tsm2x_last_hip_error().decode()
+        super().__init__("%s returned %d (%s)" % (fn, code, msg))
+        self.code = code
+
+
+def lib():
+    """The loaded library (raises if libtsm2x.so is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    "libtsm2x.so is not built (run paper_2002_03258_amd/build.py "
+                    "or __graft_entry__.build()); there is no fallback path")
+            L = ctypes.CDLL(LIB_PATH)
+            i64, vp, i32, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+            mm = [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp]
+            L.tsm2r.argtypes = mm
+            L.tsm2l.argtypes = mm
+            L.tsm2r_ex.argtypes = [i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
+            L.tsm_grad_a.argtypes = mm
+            L.tsm_grad_b.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
+            L.tsm2x_split.argtypes = [i64, i64, vp, i64, vp, vp, i64, i32, vp]
+            L.tsm2x_workspace_size.argtypes = [i32, i64, i64, i64, i32]
+            L.tsm2x_workspace_size.restype = sz
+            L.tsm2x_error_string.argtypes = [i32]
+            L.tsm2x_error_string.restype = ctypes.c_char_p
+            L.tsm2x_last_hip_error.argtypes = []
+            L.tsm2x_last_hip_error.restype = ctypes.c_char_p
+            L.tsm2x_version.argtypes = []
+            L.tsm2x_finalize.argtypes = []
+            L.tsm2x_finalize.restype = None
+            for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm_grad_a", "tsm_grad_b",
+                      "tsm2x_split", "tsm2x_version"):
+                getattr(L, f).restype = i32
+            _lib = L
+    return _lib
+
+
+def call(fn: str, *args) -> None:
+    L = lib()
+    rc = getattr(L, fn)(*args)
+    if rc != 0:
+        raise TSMError(fn, rc, L)
+
+
+EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm_grad_a", "tsm_grad_b", "tsm2x_split",
+           "tsm2x_workspace_size", "tsm2x_error_string", "tsm2x_last_hip_error",
+           "tsm2x_version", "tsm2x_finalize")

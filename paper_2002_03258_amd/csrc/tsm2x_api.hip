@@ -1,0 +1,420 @@
+// C ABI of the tall-and-skinny product library (declared in include/tsm2x.h):
+// argument checking (host only, before any HIP call), launch planning,
+// workspace management and dispatch to the gfx950 kernels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdlib>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tsm2x.h"
+#include "tsm2x_internal.h"
+
+using namespace tsm;
+
+namespace {
+
+thread_local std::string g_last_hip;
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_hip = std::string(what) + ": " + hipGetErrorString(e);
+    return TSM_ERR_HIP;
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return TSM_SUCCESS;
+}
+
+struct DevState {
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int cus = 0;
+};
+std::mutex g_mu;
+std::vector<DevState> g_dev;
+
+DevState* dev_state(int* dev_out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (dev_out) *dev_out = dev;
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    return &g_dev[dev];
+}
+
+int cu_count() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState* d = dev_state(nullptr);
+    if (!d) return 256;
+    if (d->cus == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess || v <= 0)
+            v = 256;
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            v = 256;
+        d->cus = v > 0 ? v : 256;
+    }
+    return d->cus;
+}
+
+int64_t env_int(const char* name, int64_t dflt) {
+    const char* s = std::getenv(name);
+    if (!s || !*s) return dflt;
+    return std::strtoll(s, nullptr, 10);
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+[[maybe_unused]] inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool valid_dtype(int dt) { return dt >= TSM_F64 && dt <= TSM_F16_SPLIT; }
+bool plain_dtype(int dt) { return dt == TSM_F64 || dt == TSM_F32; }
+int esize(int dt) { return dt == TSM_F64 ? 8 : 4; }
+
+int pow2_ge(int64_t n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// ------------------------------------------------------------- plans
+struct NNPlan {
+    int np;
+    int64_t tiles;
+    int S;
+    int64_t kslice;
+    size_t ws;
+};
+
+NNPlan plan_nn(int64_t m, int64_t k, int64_t n, int dt, int cus) {
+    NNPlan P{};
+    const int es = esize(dt);
+    const int RL = 16 / es, TR = 64 * RL;
+    const int WK = 4;
+    P.np = pow2_ge(n < 1 ? 1 : n);
+    const int U = P.np <= 16 ? 8 : 4;
+    P.tiles = cdiv(m, TR);
+    const int64_t target = env_int("TSM2X_NN_TARGET_BLOCKS", (int64_t)cus * 4);
+    int64_t S = cdiv(target, P.tiles);
+    const int64_t s_len = cdiv(k, WK * 64);                       // >= 64 columns per wavefront
+    const int64_t s_cost = (k * es) / ((int64_t)P.np * 200);       // partials <= ~8 % of A
+    if (S > s_len) S = s_len;
+    if (S > s_cost) S = s_cost;
+    if (P.tiles > MAX_TICKETS) S = 1;
+    if (S < 1) S = 1;
+    int64_t ks = cdiv(k, S);
+    ks = cdiv(ks, WK * U) * (WK * U);
+    P.kslice = ks;
+    P.S = (int)cdiv(k, ks);
+    if (P.S < 1) P.S = 1;
+    P.ws = P.S > 1 ? TICKET_BYTES + (size_t)P.tiles * P.S * P.np * TR * 8 : 0;
+    return P;
+}
+
+struct RTPlan {
+    int kp;
+    int cpb;
+    int64_t bx, by;
+};
+
+RTPlan plan_rowtile(int64_t m, int64_t kin, int64_t nout, int dt, int cus) {
+    RTPlan P{};
+    const int es = esize(dt);
+    const int RL = 16 / es, TR = 64 * RL;
+    P.kp = kin <= 8 ? 8 : (kin <= 16 ? 16 : 32);
+    int64_t cpb = 16384 / (es * P.kp);
+    if (cpb > 256) cpb = 256;
+    if (cpb > nout) cpb = nout;
+    if (cpb < 1) cpb = 1;
+    P.cpb = (int)cpb;
+    P.by = cdiv(nout, cpb);
+    const int64_t ntiles = cdiv(m, TR);
+    int64_t bx = cdiv(ntiles, 4);
+    int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cus * 8) / P.by;
+    if (cap < 1) cap = 1;
+    if (bx > cap) bx = cap;
+    if (bx < 1) bx = 1;
+    P.bx = bx;
+    return P;
+}
+
+struct TNPlan {
+    int np;
+    int64_t groups;
+    int S;
+    int64_t rslice;
+    size_t ws;
+};
+
+TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
+    TNPlan P{};
+    const int es = esize(dt);
+    const int RL = 16 / es, TR = 64 * RL;
+    P.np = pow2_ge(n < 1 ? 1 : n);
+    const int CPB = 4 * TN_J(P.np);
+    P.groups = cdiv(ncols, CPB);
+    const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * 4);
+    int64_t S = cdiv(target, P.groups);
+    const int64_t s_len = R / ((int64_t)TR * 8);
+    if (S > s_len) S = s_len;
+    if (P.groups > MAX_TICKETS) S = 1;
+    if (S < 1) S = 1;
+    int64_t rs = cdiv(R, S);
+    rs = cdiv(rs, TR) * TR;
+    P.rslice = rs;
+    P.S = (int)cdiv(R, rs);
+    if (P.S < 1) P.S = 1;
+    P.ws = P.S > 1 ? TICKET_BYTES + (size_t)P.groups * P.S * CPB * P.np * 8 : 0;
+    return P;
+}
+
+// Workspace: caller's (checked) or the library's grow-only per-device buffer,
+// whose counter region starts zeroed.
+int get_ws(size_t need, void* user, size_t user_bytes, void** out) {
+    *out = nullptr;
+    if (need == 0) return TSM_SUCCESS;
+    if (user) {
+        if (user_bytes < need || ((uintptr_t)user & 255u)) return TSM_ERR_WORKSPACE;
+        *out = user;
+        return TSM_SUCCESS;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevState* d = dev_state(nullptr);
+    if (!d) return hip_fail(hipErrorInvalidDevice, "hipGetDevice");
+    if (d->ws_bytes < need) {
+        if (d->ws) {
+            hipError_t e = hipFree(d->ws);
+            d->ws = nullptr;
+            d->ws_bytes = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+        }
+        size_t bytes = need < ((size_t)1 << 20) ? ((size_t)1 << 20) : need;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            g_last_hip = std::string("hipMalloc(workspace): ") + hipGetErrorString(e);
+            return TSM_ERR_ALLOC;
+        }
+        e = hipMemset(p, 0, bytes);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            return hip_fail(e, "hipMemset(workspace)");
+        }
+        d->ws = p;
+        d->ws_bytes = bytes;
+    }
+    *out = d->ws;
+    return TSM_SUCCESS;
+}
+
+void split_ws(void* ws, double** part, unsigned** tickets) {
+    *tickets = (unsigned*)ws;
+    *part = (double*)((char*)ws + TICKET_BYTES);
+}
+
+// Validation of (m, k, n, A, lda, B, ldb, C, ldc, dtype) for C = A*B with
+// column-major (or, for `rowA`, row-major) A.  `base` is the position of m.
+int check_mm(int base, int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+             const void* B, int64_t ldb, const void* C, int64_t ldc, int dtype, bool rowA) {
+    if (m < 0) return -(base + 0);
+    if (k < 0) return -(base + 1);
+    if (n < 0) return -(base + 2);
+    if (!A && m > 0 && k > 0) return -(base + 3);
+    const int64_t mina = rowA ? (k > 1 ? k : 1) : (m > 1 ? m : 1);
+    if (lda < mina) return -(base + 4);
+    if (!B && k > 0 && n > 0) return -(base + 5);
+    if (ldb < (k > 1 ? k : 1)) return -(base + 6);
+    if (!C && m > 0 && n > 0) return -(base + 7);
+    if (ldc < (m > 1 ? m : 1)) return -(base + 8);
+    if (!valid_dtype(dtype)) return -(base + 9);
+    return TSM_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+             const void* B, int64_t ldb, void* C, int64_t ldc, int dtype, void* ws,
+             size_t ws_bytes, void* stream) {
+    if (order != TSM_COL_MAJOR && order != TSM_ROW_MAJOR) return -1;
+    const bool rowA = order == TSM_ROW_MAJOR;
+    int rc = check_mm(2, m, k, n, A, lda, B, ldb, C, ldc, dtype, rowA);
+    if (rc) return rc;
+    if (n > 32) return TSM_ERR_UNSUPPORTED;
+    if (!plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (m == 0 || n == 0) return TSM_SUCCESS;
+    hipStream_t st = (hipStream_t)stream;
+    if (k == 0) {
+        launch_fill_zero(m, n, C, ldc, dtype, st);
+        return check_launch("fill_zero");
+    }
+    const int cus = cu_count();
+    void* w = nullptr;
+    if (rowA) {
+        // A row-major m x k is the column-major k x m matrix X = A^T (ld lda):
+        // C = X^T * B, a reduction along the contiguous dimension.
+        TNPlan P = plan_tn(k, m, n, dtype, cus);
+        rc = get_ws(P.ws, ws, ws_bytes, &w);
+        if (rc) return rc;
+        LaunchTN L{};
+        L.R = k; L.ncols = m; L.n = n;
+        L.X = A; L.ldx = lda; L.Y = B; L.ldy = ldb; L.O = C; L.ldo = ldc;
+        L.np = P.np; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
+        if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+        if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
+        return check_launch("tn_kernel");
+    }
+    NNPlan P = plan_nn(m, k, n, dtype, cus);
+    rc = get_ws(P.ws, ws, ws_bytes, &w);
+    if (rc) return rc;
+    LaunchNN L{};
+    L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C; L.ldc = ldc;
+    L.np = P.np; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
+    if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+    if (launch_tsm2r_nn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
+    return check_launch("tsm2r_nn_kernel");
+}
+
+int tsm2r(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
+          int64_t ldb, void* C, int64_t ldc, int dtype, void* stream) {
+    int rc = check_mm(1, m, k, n, A, lda, B, ldb, C, ldc, dtype, false);
+    if (rc) return rc;
+    return tsm2r_ex(TSM_COL_MAJOR, m, k, n, A, lda, B, ldb, C, ldc, dtype, nullptr, 0, stream);
+}
+
+int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
+          int64_t ldb, void* C, int64_t ldc, int dtype, void* stream) {
+    int rc = check_mm(1, m, k, n, A, lda, B, ldb, C, ldc, dtype, false);
+    if (rc) return rc;
+    if (k > 32 || n > 32 || !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (m == 0 || n == 0) return TSM_SUCCESS;
+    hipStream_t st = (hipStream_t)stream;
+    if (k == 0) {
+        launch_fill_zero(m, n, C, ldc, dtype, st);
+        return check_launch("fill_zero");
+    }
+    RTPlan P = plan_rowtile(m, k, n, dtype, cu_count());
+    LaunchRT L{};
+    L.m = m; L.kin = (int)k; L.nout = n; L.X = A; L.ldx = lda; L.Y = B; L.ys_in = 1;
+    L.ys_out = ldb; L.O = C; L.ldo = ldc; L.kp = P.kp; L.cols_per_block = P.cpb;
+    L.blocks_x = P.bx; L.blocks_y = P.by;
+    if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
+    return check_launch("rowtile_kernel");
+}
+
+int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc, const void* B,
+               int64_t ldb, void* dA, int64_t ldda, int dtype, void* stream) {
+    if (m < 0) return -1;
+    if (k < 0) return -2;
+    if (n < 0) return -3;
+    if (!dC && m > 0 && n > 0) return -4;
+    if (lddc < (m > 1 ? m : 1)) return -5;
+    if (!B && k > 0 && n > 0) return -6;
+    if (ldb < (k > 1 ? k : 1)) return -7;
+    if (!dA && m > 0 && k > 0) return -8;
+    if (ldda < (m > 1 ? m : 1)) return -9;
+    if (!valid_dtype(dtype)) return -10;
+    if (n > 32 || !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (m == 0 || k == 0) return TSM_SUCCESS;
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        launch_fill_zero(m, k, dA, ldda, dtype, st);
+        return check_launch("fill_zero");
+    }
+    // dA = dC * B^T: X = dC (m x n), Y(p, j) = B[j + p*ldb].
+    RTPlan P = plan_rowtile(m, n, k, dtype, cu_count());
+    LaunchRT L{};
+    L.m = m; L.kin = (int)n; L.nout = k; L.X = dC; L.ldx = lddc; L.Y = B; L.ys_in = ldb;
+    L.ys_out = 1; L.O = dA; L.ldo = ldda; L.kp = P.kp; L.cols_per_block = P.cpb;
+    L.blocks_x = P.bx; L.blocks_y = P.by;
+    if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
+    return check_launch("rowtile_kernel");
+}
+
+int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* dC,
+               int64_t lddc, void* dB, int64_t lddb, int dtype, void* ws, size_t ws_bytes,
+               void* stream) {
+    if (m < 0) return -1;
+    if (k < 0) return -2;
+    if (n < 0) return -3;
+    if (!A && m > 0 && k > 0) return -4;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (!dC && m > 0 && n > 0) return -6;
+    if (lddc < (m > 1 ? m : 1)) return -7;
+    if (!dB && k > 0 && n > 0) return -8;
+    if (lddb < (k > 1 ? k : 1)) return -9;
+    if (!valid_dtype(dtype)) return -10;
+    if (n > 32 || !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (k == 0 || n == 0) return TSM_SUCCESS;
+    hipStream_t st = (hipStream_t)stream;
+    if (m == 0) {
+        launch_fill_zero(k, n, dB, lddb, dtype, st);
+        return check_launch("fill_zero");
+    }
+    // dB = A^T * dC: X = A (R = m rows, k columns), Y = dC.
+    TNPlan P = plan_tn(m, k, n, dtype, cu_count());
+    void* w = nullptr;
+    int rc = get_ws(P.ws, ws, ws_bytes, &w);
+    if (rc) return rc;
+    LaunchTN L{};
+    L.R = m; L.ncols = k; L.n = n; L.X = A; L.ldx = lda; L.Y = dC; L.ldy = lddc; L.O = dB;
+    L.ldo = lddb; L.np = P.np; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
+    if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+    if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
+    return check_launch("tn_kernel");
+}
+
+int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
+                int64_t ldh, int fmt, void* stream) {
+    (void)m; (void)k; (void)A; (void)lda; (void)hi; (void)lo; (void)ldh; (void)fmt; (void)stream;
+    return TSM_ERR_UNSUPPORTED;
+}
+
+size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n, int dtype) {
+    if (m <= 0 || k <= 0 || n <= 0 || n > 32 || !plain_dtype(dtype)) return 0;
+    const int cus = cu_count();
+    switch (op) {
+        case TSM_OP_TSM2R: return plan_nn(m, k, n, dtype, cus).ws;
+        case TSM_OP_TSM2R_ROWMAJOR: return plan_tn(k, m, n, dtype, cus).ws;
+        case TSM_OP_GRAD_B: return plan_tn(m, k, n, dtype, cus).ws;
+        default: return 0;
+    }
+}
+
+const char* tsm2x_error_string(int code) {
+    if (code < 0) return "invalid argument (the code is minus its 1-based position)";
+    switch (code) {
+        case TSM_SUCCESS: return "success";
+        case TSM_ERR_UNSUPPORTED: return "shape or storage type outside the supported range";
+        case TSM_ERR_HIP: return "a HIP runtime call failed (see tsm2x_last_hip_error)";
+        case TSM_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
+        case TSM_ERR_ALLOC: return "could not allocate the library workspace";
+        default: return "unknown error code";
+    }
+}
+
+const char* tsm2x_last_hip_error(void) { return g_last_hip.c_str(); }
+
+int tsm2x_version(void) { return 100; }
+
+void tsm2x_finalize(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (size_t d = 0; d < g_dev.size(); ++d) {
+        if (g_dev[d].ws) {
+            (void)hipSetDevice((int)d);
+            (void)hipFree(g_dev[d].ws);
+            g_dev[d].ws = nullptr;
+            g_dev[d].ws_bytes = 0;
+        }
+    }
+    (void)hipSetDevice(cur);
+}
+
+}  // extern "C"

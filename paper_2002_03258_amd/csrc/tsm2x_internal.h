@@ -1,0 +1,63 @@
+// Internal launch descriptors shared by the C-ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsm {
+
+enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3, DT_BF16_SPLIT = 4, DT_F16_SPLIT = 5 };
+
+// Output rows per wavefront of the tn kernel for NP padded output columns:
+// J*NP accumulators per lane, at most 64.
+// Every workspace starts with a fixed region of MAX_TICKETS zero-initialised
+// counters (re-armed to zero by the kernels that use them), followed by the
+// partial sums.  The layout does not depend on the call, so one workspace can
+// serve calls of any shape.  Calls whose split would need more counters run
+// without a split.
+constexpr int64_t MAX_TICKETS = 4096;
+constexpr size_t TICKET_BYTES = MAX_TICKETS * 4;
+
+constexpr int TN_J(int np) { return (64 / np) > 8 ? 8 : ((64 / np) < 1 ? 1 : 64 / np); }
+
+struct LaunchNN {           // tsm2r_nn: C = A*B, column-major A
+    int64_t m, k, n;
+    const void* A; int64_t lda;
+    const void* B; int64_t ldb;
+    void* C; int64_t ldc;
+    int np;                 // padded n
+    int64_t tiles;          // row tiles (gridDim.x)
+    int S;                  // k slices (gridDim.y)
+    int64_t kslice;         // columns per k slice
+    double* part;           // S > 1: partial sums
+    unsigned* tickets;      // S > 1: one counter per row tile
+};
+
+struct LaunchRT {           // rowtile: O = X*Y, X m x kin (kin <= 32)
+    int64_t m; int kin; int64_t nout;
+    const void* X; int64_t ldx;
+    const void* Y; int64_t ys_in, ys_out;
+    void* O; int64_t ldo;
+    int kp;                 // padded kin: 8, 16 or 32
+    int cols_per_block;
+    int64_t blocks_x, blocks_y;
+};
+
+struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
+    int64_t R, ncols, n;
+    const void* X; int64_t ldx;
+    const void* Y; int64_t ldy;
+    void* O; int64_t ldo;
+    int np;
+    int64_t groups;         // column groups (gridDim.x)
+    int S;                  // reduction slices (gridDim.y)
+    int64_t rslice;
+    double* part;
+    unsigned* tickets;
+};
+
+int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st);
+int launch_rowtile(const LaunchRT& L, int dtype, hipStream_t st);
+int launch_tn(const LaunchTN& L, int dtype, hipStream_t st);
+int launch_fill_zero(int64_t m, int64_t n, void* C, int64_t ldc, int dtype, hipStream_t st);
+
+}  // namespace tsm

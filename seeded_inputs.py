@@ -135,6 +135,17 @@ def matrix_rows(seed: int, stream: int, rows: int, cols: int, row_idx,
     return v.to(dtype)
 
 
+def matrix_cols(seed: int, stream: int, rows: int, cols: int, col_idx,
+                *, dtype=torch.float64, dist: str = "uniform",
+                r: int = 8) -> torch.Tensor:
+    """Only the listed columns of the matrix :func:`matrix` would produce, on
+    the CPU: shape (rows, len(col_idx))."""
+    ci = torch.as_tensor(col_idx, dtype=torch.int64).view(1, -1)
+    ri = torch.arange(rows, dtype=torch.int64).view(-1, 1)
+    v = values(seed, stream, ci * rows + ri, dist, r)
+    return v.to(dtype)
+
+
 def row_major(seed: int, stream: int, rows: int, cols: int, *,
               dtype=torch.float64, device="cpu", dist: str = "uniform"):
     """Row-major rows x cols matrix: logical (i, j) has index i * cols + j."""

@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every function tsm2x.h declares, and
+rejects invalid arguments on the host (no GPU calls are made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2002_03258_amd as tsm
+from paper_2002_03258_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)\s*\(",
+                                    src, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = declared_functions()
+    assert {"tsm2r", "tsm2l", "tsm2r_ex", "tsm_grad_a", "tsm_grad_b"} <= names
+    for nme in names:
+        assert hasattr(L, nme), nme
+    assert set(_lib.EXPORTS) <= names
+
+
+def test_version_and_error_strings():
+    L = _lib.lib()
+    assert L.tsm2x_version() >= 100
+    for code in (0, 1, 2, 3, 4, -5, 99):
+        assert len(L.tsm2x_error_string(code)) > 0
+
+
+NULL = None
+P = 4096  # a non-null dummy address: never dereferenced, validation fails first
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((-1, 4, 4, P, 4, P, 4, P, 4, 0, NULL), -1),
+    ((4, -1, 4, P, 4, P, 4, P, 4, 0, NULL), -2),
+    ((4, 4, -1, P, 4, P, 4, P, 4, 0, NULL), -3),
+    ((4, 4, 4, NULL, 4, P, 4, P, 4, 0, NULL), -4),
+    ((4, 4, 4, P, 3, P, 4, P, 4, 0, NULL), -5),
+    ((4, 4, 4, P, 4, NULL, 4, P, 4, 0, NULL), -6),
+    ((4, 4, 4, P, 4, P, 3, P, 4, 0, NULL), -7),
+    ((4, 4, 4, P, 4, P, 4, NULL, 4, 0, NULL), -8),
+    ((4, 4, 4, P, 4, P, 4, P, 3, 0, NULL), -9),
+    ((4, 4, 4, P, 4, P, 4, P, 4, 9, NULL), -10),
+    ((4, 4, 33, P, 4, P, 4, P, 4, 0, NULL), 1),
+])
+def test_tsm2r_argument_checks(args, expect):
+    assert _lib.lib().tsm2r(*args) == expect
+
+
+def test_tsm2l_limits_and_checks():
+    L = _lib.lib()
+    assert L.tsm2l(8, 33, 4, P, 8, P, 33, P, 8, 0, NULL) == 1
+    assert L.tsm2l(8, 4, 33, P, 8, P, 4, P, 8, 0, NULL) == 1
+    assert L.tsm2l(8, 4, 4, P, 7, P, 4, P, 8, 0, NULL) == -5
+
+
+def test_rowmajor_lda_check():
+    L = _lib.lib()
+    # row-major A needs lda >= k
+    assert L.tsm2r_ex(1, 8, 16, 4, P, 15, P, 16, P, 8, 0, NULL, 0, NULL) == -6
+    assert L.tsm2r_ex(2, 8, 16, 4, P, 16, P, 16, P, 8, 0, NULL, 0, NULL) == -1
+
+
+def test_grad_argument_checks():
+    L = _lib.lib()
+    assert L.tsm_grad_a(8, 4, 4, P, 7, P, 4, P, 8, 0, NULL) == -5
+    assert L.tsm_grad_a(8, 4, 4, P, 8, P, 3, P, 8, 0, NULL) == -7
+    assert L.tsm_grad_b(8, 4, 4, P, 8, P, 8, P, 3, 0, NULL, 0, NULL) == -9
+    assert L.tsm_grad_b(8, 4, 40, P, 8, P, 8, P, 4, 0, NULL, 0, NULL) == 1
+
+
+def test_empty_problems_are_noops_without_gpu():
+    L = _lib.lib()
+    assert L.tsm2r(0, 4, 4, NULL, 1, P, 4, NULL, 1, 0, NULL) == 0
+    assert L.tsm2r(4, 4, 0, P, 4, NULL, 4, NULL, 4, 0, NULL) == 0
+    assert L.tsm2l(0, 4, 4, NULL, 1, P, 4, NULL, 1, 1, NULL) == 0
+    assert L.tsm_grad_b(8, 0, 4, P, 8, P, 8, NULL, 1, 0, NULL, 0, NULL) == 0
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        tsm.tsm2r(torch.zeros(4, 4, dtype=torch.float64), torch.zeros(4, 2, dtype=torch.float64))

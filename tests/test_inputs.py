@@ -22,6 +22,11 @@ def test_matrix_rows_equal_full_generation():
         assert torch.equal(A[rows, :], R)
 
 
+def test_matrix_cols_equal_full_generation():
+    A = si.matrix(5, si.STREAM_A, 37, 11)
+    assert torch.equal(A[:, [0, 3, 10]], si.matrix_cols(5, si.STREAM_A, 37, 11, [0, 3, 10]))
+
+
 def test_padding_is_nan_and_values_independent_of_ld():
     A = si.matrix(6, si.STREAM_B, 9, 4, ld=13)
     assert A.stride() == (1, 13)

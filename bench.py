@@ -1,0 +1,347 @@
+"""Throughput benchmark of the TSM2R / TSM2L kernels on one MI355X.
+
+A step is one pass over the TSM2R workload grid of square A (m = k in
+{10240, 20480, 30720}) times B (k x n, n in {2, 4, 8, 16}) in FP64 and FP32:
+24 products C = A*B, inputs resident in HBM, iid uniform[-1, 1] from the
+seeded counter-based generator.  ``value`` is the achieved HBM throughput:
+algorithmic bytes (A read once, B read once, C written once) per second over
+the K timed steps.
+
+Besides the headline line the JSON carries:
+  roofline      the dominant kernel (largest total time in the step), its
+                algorithmic bytes per launch over its average launch duration
+                (HIP events on the stream it runs on) against 8 TB/s, and the
+                HBM traffic rocprofv3 counted for it (profiles/), or null;
+  cpu_baseline  the FP64 oracle timed on this host's cores on a row sample of
+                the largest workload;
+  rows          the other hot-path rows measured on their own workloads
+                (TSM2L grid, backward of C = A*B), each with GB/s, fraction of
+                8 TB/s and the normwise error of sampled outputs vs the oracle;
+  check         normwise errors of sampled rows of every product of the step.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       [--no-cpu-baseline] [--no-rows] [--profile-kernel | --profile-copy]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import paper_2002_03258_amd as tsm  # noqa: E402
+import seeded_inputs as si  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+R_SIZES = (10240, 20480, 30720)
+R_NS = (2, 4, 8, 16)
+R_DTYPES = (torch.float64, torch.float32)
+L_MS = (1 << 20, 1 << 22, 1 << 24)
+L_KS = (8, 16, 32)
+TOL = {torch.float64: 1e-13, torch.float32: 1e-5}
+KERNEL_SRC = os.path.join(ROOT, "paper_2002_03258_amd", "csrc", "tsm2x_kernels.hip")
+
+
+def es(dtype) -> int:
+    return 8 if dtype == torch.float64 else 4
+
+
+def nn_kernel_name(dtype, n) -> str:
+    t = "double" if dtype == torch.float64 else "float"
+    return "tsm2r_nn_kernel<%s, %d, 2, 4, true>" % (t, 1 if n <= 16 else 2)
+
+
+def src_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def make_r_inputs(dev):
+    seed = si.config_seed(1)
+    calls = []
+    for dtype in R_DTYPES:
+        for m in R_SIZES:
+            A = si.matrix(seed, si.STREAM_A, m, m, dtype=dtype, device=dev)
+            for n in R_NS:
+                B = si.matrix(seed + n, si.STREAM_B, m, n, dtype=dtype, device=dev)
+                C = tsm.empty_colmajor(m, n, dtype, dev)
+                calls.append(dict(dtype=dtype, m=m, k=m, n=n, A=A, B=B, C=C, seed=seed,
+                                  bytes=(m * m + m * n + m * n) * es(dtype),
+                                  kernel=nn_kernel_name(dtype, n)))
+    return calls
+
+
+def run_step(calls, evs=None):
+    for i, c in enumerate(calls):
+        if evs is not None:
+            evs[i][0].record()
+        tsm.tsm2r(c["A"], c["B"], out=c["C"])
+        if evs is not None:
+            evs[i][1].record()
+
+
+def check_calls(calls):
+    import oracle
+    worst = {}
+    for c in calls:
+        m, k, n, dtype = c["m"], c["k"], c["n"], c["dtype"]
+        rows = sorted(set([0, 1, m - 1] + list(np.random.default_rng(m + n).integers(0, m, 13))))
+        Ar = si.matrix_rows(c["seed"], si.STREAM_A, m, k, rows, dtype=dtype).double().numpy()
+        B = si.matrix(c["seed"] + n, si.STREAM_B, k, n, dtype=dtype).double().numpy()
+        e = oracle.normwise_error(c["C"][rows].double().cpu().numpy(), oracle.matmul(Ar, B))
+        key = str(dtype).replace("torch.", "")
+        worst[key] = max(worst.get(key, 0.0), e)
+    return {k: {"max_normwise_err": v, "tol": TOL[getattr(torch, k)],
+                "ok": v <= TOL[getattr(torch, k)]} for k, v in worst.items()}
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle on a row sample of the largest TSM2R workload."""
+    import oracle
+    m = k = R_SIZES[-1]
+    n = 16
+    seed = si.config_seed(1)
+    B = si.matrix(seed + n, si.STREAM_B, k, n).numpy()
+    rows = 64
+    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(rows))).numpy()
+    t0 = time.perf_counter()
+    oracle.matmul(Ar, B)
+    dt = time.perf_counter() - t0
+    rows = int(min(m, max(64, rows * seconds_target / max(dt, 1e-3))))
+    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(rows))).numpy()
+    t0 = time.perf_counter()
+    oracle.matmul(Ar, B)
+    dt = time.perf_counter() - t0
+    nbytes = (rows * k + k * n + rows * n) * 8
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": oracle.threads(),
+            "kind": "oracle", "seconds": dt,
+            "sample": "FP64 TSM2R C = A*B on the first %d of %d rows of A (k = %d, n = %d); "
+                      "algorithmic bytes of the sample over the oracle's time" % (rows, m, k, n)}
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken from another kernel source."""
+    path = os.path.join(ROOT, "profiles", "tsm2r_nn_f64_m30720_n16_counters.txt")
+    if not os.path.exists(path):
+        return None
+    info = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            key, val = line.split("=", 1)
+            info[key.strip()] = val.strip()
+    if info.get("kernel_source_sha256_16") != src_hash() or info.get("kernel") != kernel:
+        return None
+    try:
+        return float(info["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed(fn, reps=5, warmup=1, flush=None):
+    """Mean seconds of fn() over `reps` runs, each bracketed by HIP events;
+    `flush` (untimed) runs before each rep to evict the 256 MB MALL."""
+    for _ in range(warmup):
+        fn()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e0, e1 in evs:
+        if flush is not None:
+            flush()
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    return sum(e0.elapsed_time(e1) for e0, e1 in evs) / reps / 1e3
+
+
+def rows_tsm2l(dev):
+    import oracle
+    out = []
+    seed = si.config_seed(2)
+    for dtype in R_DTYPES:
+        tot_b, tot_t, worst = 0.0, 0.0, 0.0
+        for m in L_MS:
+            for k in L_KS:
+                A = si.matrix(seed + k, si.STREAM_A, m, k, dtype=dtype, device=dev)
+                B = si.matrix(seed + k, si.STREAM_B, k, k, dtype=dtype, device=dev)
+                C = tsm.empty_colmajor(m, k, dtype, dev)
+                flush = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+                t = timed(lambda: tsm.tsm2l(A, B, out=C), flush=flush.zero_)
+                nb = (2 * m * k + k * k) * es(dtype)
+                tot_b += nb
+                tot_t += t
+                rows = [0, m // 3, m - 1]
+                ref = oracle.matmul(si.matrix_rows(seed + k, si.STREAM_A, m, k, rows,
+                                                   dtype=dtype).double().numpy(),
+                                    si.matrix(seed + k, si.STREAM_B, k, k, dtype=dtype)
+                                    .double().numpy())
+                worst = max(worst, oracle.normwise_error(C[rows].double().cpu().numpy(), ref))
+                del A, B, C, flush
+        torch.cuda.empty_cache()
+        out.append({"row": "TSM2L forward (C = A*B, m in 2^20..2^24, k = n in 8..32)",
+                    "dtype": str(dtype).replace("torch.", ""), "GBps": tot_b / tot_t / 1e9,
+                    "frac_of_8TBps": tot_b / tot_t / 1e9 / PEAK_HBM_GBS,
+                    "max_normwise_err": worst, "tol": TOL[dtype]})
+    return out
+
+
+def rows_autograd(dev):
+    """Forward + backward of C = A*B on the two autograd shapes."""
+    import oracle
+    out = []
+    seed = si.config_seed(4)
+    for shape, (m, k, n) in (("TSM2L", (8388608, 16, 16)), ("TSM2R", (16384, 16384, 8))):
+        for dtype in R_DTYPES:
+            A = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
+            B = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype, device=dev)
+            dC = si.matrix(seed, si.STREAM_DC, m, n, dtype=dtype, device=dev, dist="normal")
+            C = tsm.empty_colmajor(m, n, dtype, dev)
+            dA = tsm.empty_colmajor(m, k, dtype, dev)
+            dB = tsm.empty_colmajor(k, n, dtype, dev)
+            fwd = (lambda: tsm.tsm2l(A, B, out=C)) if shape == "TSM2L" else \
+                (lambda: tsm.tsm2r(A, B, out=C))
+            s = es(dtype)
+            t_f = timed(fwd)
+            t_a = timed(lambda: tsm.grad_a(dC, B, out=dA))
+            t_b = timed(lambda: tsm.grad_b(A, dC, out=dB))
+            b_f = (m * k + k * n + m * n) * s
+            b_a = (m * n + k * n + m * k) * s
+            b_b = (m * k + m * n + k * n) * s
+            rows = [0, m // 2, m - 1]
+            Ar = si.matrix_rows(seed, si.STREAM_A, m, k, rows, dtype=dtype).double().numpy()
+            Bh = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype).double().numpy()
+            dCr = si.matrix_rows(seed, si.STREAM_DC, m, n, rows, dtype=dtype,
+                                 dist="normal").double().numpy()
+            e_f = oracle.normwise_error(C[rows].double().cpu().numpy(), oracle.matmul(Ar, Bh))
+            e_a = oracle.normwise_error(dA[rows].double().cpu().numpy(), oracle.matmul(dCr, Bh.T))
+            cols = [0, k // 2, k - 1]
+            if m * k <= (1 << 28):
+                Ac = si.matrix_cols(seed, si.STREAM_A, m, k, cols, dtype=dtype).double().numpy()
+                dCh = si.matrix(seed, si.STREAM_DC, m, n, dtype=dtype,
+                                dist="normal").double().numpy()
+                e_b = oracle.normwise_error(dB[cols].double().cpu().numpy(),
+                                            oracle.matmul(Ac.T, dCh))
+            else:
+                e_b = None
+            out.append({"row": "autograd fwd+bwd %s shape m=%d k=%d n=%d" % (shape, m, k, n),
+                        "dtype": str(dtype).replace("torch.", ""),
+                        "GBps": (b_f + b_a + b_b) / (t_f + t_a + t_b) / 1e9,
+                        "frac_of_8TBps": (b_f + b_a + b_b) / (t_f + t_a + t_b) / 1e9 / PEAK_HBM_GBS,
+                        "fwd_GBps": b_f / t_f / 1e9, "grad_a_GBps": b_a / t_a / 1e9,
+                        "grad_b_GBps": b_b / t_b / 1e9,
+                        "err": {"C": e_f, "dA": e_a, "dB": e_b}, "tol": TOL[dtype]})
+            del A, B, dC, C, dA, dB
+            torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--profile-kernel", action="store_true",
+                    help="only launch the dominant kernel 5 times (for rocprofv3 counters)")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="only run a 1 GiB device copy 5 times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(the kernels run on one device's share of the work)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+
+    if args.profile_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied 5 x %d bytes" % src.numel(), flush=True)
+        return
+    if args.profile_kernel:
+        m = R_SIZES[-1]
+        seed = si.config_seed(1)
+        A = si.matrix(seed, si.STREAM_A, m, m, device=dev)
+        B = si.matrix(seed + 16, si.STREAM_B, m, 16, device=dev)
+        C = tsm.empty_colmajor(m, 16, torch.float64, dev)
+        for _ in range(5):
+            tsm.tsm2r(A, B, out=C)
+        torch.cuda.synchronize()
+        print("launched %s 5 times" % nn_kernel_name(torch.float64, 16), flush=True)
+        return
+
+    t_setup = time.perf_counter()
+    calls = make_r_inputs(dev)
+    torch.cuda.synchronize()
+    print("inputs ready in %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        run_step(calls)
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in calls] for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for s in range(args.steps):
+        run_step(calls, evs[s])
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    step_bytes = sum(c["bytes"] for c in calls)
+    value = step_bytes * args.steps / (total_ms / 1e3) / 1e9
+
+    per_kernel = {}
+    for s in range(args.steps):
+        for i, c in enumerate(calls):
+            d = per_kernel.setdefault(c["kernel"], {"t": 0.0, "b": 0.0, "n": 0})
+            d["t"] += evs[s][i][0].elapsed_time(evs[s][i][1]) / 1e3
+            d["b"] += c["bytes"]
+            d["n"] += 1
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["t"])
+    d = per_kernel[dom]
+    achieved = d["b"] / d["t"] / 1e9
+    per_launch = d["b"] / d["n"]
+    traffic = traffic_for(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                "avg_launch_us": d["t"] / d["n"] * 1e6, "launches": d["n"],
+                "algorithmic_bytes_per_launch": per_launch,
+                "traffic": traffic}
+    line = {
+        "metric": "achieved HBM GB/s (% peak), TSM2R/TSM2L fp64 vs bf16-split fwd+bwd at tol",
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic (seeded counter-based uniform[-1,1])",
+        "config": {"workload": "TSM2R plain FP64 and FP32: square A m=k in {10240,20480,30720}, "
+                               "B k x n with n in {2,4,8,16}, column-major (24 products per step)",
+                   "bytes_per_step": step_bytes, "frac_of_8TBps": value / PEAK_HBM_GBS},
+        "roofline": roofline,
+    }
+    if not args.no_check:
+        line["check"] = check_calls(calls)
+    del calls
+    torch.cuda.empty_cache()
+    if not args.no_rows:
+        line["rows"] = rows_tsm2l(dev) + rows_autograd(dev)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,8 +114,8 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A,
 /* TSM2L: C = A*B, A m-by-k with k <= 32, B k-by-n with n <= 32 (Algorithm 6:
  * horizontal tiles of A processed by a persistent grid; B is held on chip
  * whole, so C is written exactly once and never re-read).
- * dtype: TSM_F64 or TSM_F32.  Errors as tsm2r; TSM_ERR_UNSUPPORTED if
- * k > 32 or n > 32. */
+ * dtype: any tsm_dtype (16-bit forms of A as in tsm2r, B and C float).
+ * Errors as tsm2r; TSM_ERR_UNSUPPORTED if k > 32 or n > 32. */
 int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
           const void* B, int64_t ldb, void* C, int64_t ldc, int dtype,
           void* stream);

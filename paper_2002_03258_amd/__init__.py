@@ -14,8 +14,8 @@ from . import _lib
 from ._lib import (BF16, BF16_SPLIT, COL_MAJOR, F16, F16_SPLIT, F32, F64,
                    ROW_MAJOR, TSMError)
 
-__all__ = ["tsm2r", "tsm2l", "grad_a", "grad_b", "colmajor", "empty_colmajor",
-           "workspace_size", "TSMError", "F64", "F32", "BF16", "F16",
+__all__ = ["tsm2r", "tsm2l", "grad_a", "grad_b", "split", "SplitA", "colmajor",
+           "empty_colmajor", "workspace_size", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
            "BF16_SPLIT", "F16_SPLIT"]
 
 _DT = {torch.float64: F64, torch.float32: F32}
@@ -51,10 +51,76 @@ def _check_device(*ts):
             raise ValueError("tensors must be on a GPU device")
 
 
-def tsm2r(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
+class SplitA:
+    """Low-precision storage form of a float matrix A (m x k): a hi plane
+    and optionally a lo plane of bfloat16 or binary16 values, hi + lo ~ A.
+    ``planes`` is one device buffer of shape (nplanes, k, ld); plane p holds
+    the column-major m x k matrix ``planes[p].t()[:m]``."""
+
+    def __init__(self, planes: torch.Tensor, m: int, k: int, fmt: str, has_lo: bool):
+        self.planes, self.m, self.k, self.fmt, self.has_lo = planes, m, k, fmt, has_lo
+        self.ld = planes.shape[2]
+
+    @property
+    def hi(self) -> torch.Tensor:
+        return self.planes[0].t()[: self.m]
+
+    @property
+    def lo(self) -> torch.Tensor | None:
+        return self.planes[1].t()[: self.m] if self.has_lo else None
+
+    @property
+    def dtype_code(self) -> int:
+        if self.fmt == "bf16":
+            return BF16_SPLIT if self.has_lo else BF16
+        return F16_SPLIT if self.has_lo else F16
+
+    @property
+    def shape(self):
+        return (self.m, self.k)
+
+    @property
+    def device(self):
+        return self.planes.device
+
+    def nbytes(self) -> int:
+        return self.m * self.k * 2 * (2 if self.has_lo else 1)
+
+
+def split(A: torch.Tensor, fmt: str = "bf16", lo: bool = True) -> SplitA:
+    """hi = RNE(A), lo = RNE(A - hi) in bfloat16 ("bf16") or binary16 ("f16"),
+    computed on the GPU by the library's split kernel."""
+    _check_device(A)
+    if A.dtype != torch.float32:
+        raise ValueError("split expects a float32 matrix")
+    A = colmajor(A)
+    m, k = A.shape
+    ld = max(8, (m + 7) // 8 * 8)
+    tdt = torch.bfloat16 if fmt == "bf16" else torch.float16
+    planes = torch.empty((2 if lo else 1, k, ld), dtype=tdt, device=A.device)
+    lo_ptr = planes[1].data_ptr() if lo else None
+    _lib.call("tsm2x_split", m, k, A.data_ptr(), _ld(A), planes[0].data_ptr(), lo_ptr, ld,
+              0 if fmt == "bf16" else 1, _stream())
+    return SplitA(planes, m, k, fmt, lo)
+
+
+def tsm2r(A, B: torch.Tensor, out: torch.Tensor | None = None,
           workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """C = A*B for a large A (m x k, column- or row-major) and a skinny B
-    (k x n, n <= 32) -- TSM2R."""
+    """C = A*B for a large A (m x k, column- or row-major, or a SplitA) and a
+    skinny B (k x n, n <= 32) -- TSM2R.  For a SplitA, B and C are float32."""
+    if isinstance(A, SplitA):
+        _check_device(A.planes, B)
+        m, k = A.shape
+        n = B.shape[1]
+        if B.dtype != torch.float32:
+            raise ValueError("B must be float32 for the low-precision forms of A")
+        B = colmajor(B)
+        C = out if out is not None else empty_colmajor(m, n, torch.float32, B.device)
+        ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
+            if workspace is not None else (None, 0)
+        _lib.call("tsm2r_ex", COL_MAJOR, m, k, n, A.planes.data_ptr(), A.ld, B.data_ptr(),
+                  _ld(B), C.data_ptr(), _ld(C), A.dtype_code, ws, wsb, _stream())
+        return C
     _check_device(A, B)
     dt = _DT[A.dtype]
     m, k = A.shape
@@ -74,9 +140,18 @@ def tsm2r(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
     return C
 
 
-def tsm2l(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """C = A*B for a tall-and-skinny A (m x k, k <= 32) and a small B
-    (k x n, n <= 32) -- TSM2L."""
+def tsm2l(A, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A*B for a tall-and-skinny A (m x k, k <= 32, or a SplitA) and a
+    small B (k x n, n <= 32) -- TSM2L."""
+    if isinstance(A, SplitA):
+        _check_device(A.planes, B)
+        m, k = A.shape
+        n = B.shape[1]
+        B = colmajor(B)
+        C = out if out is not None else empty_colmajor(m, n, torch.float32, B.device)
+        _lib.call("tsm2l", m, k, n, A.planes.data_ptr(), A.ld, B.data_ptr(), _ld(B),
+                  C.data_ptr(), _ld(C), A.dtype_code, _stream())
+        return C
     _check_device(A, B)
     dt = _DT[A.dtype]
     A = colmajor(A)
@@ -103,9 +178,20 @@ def grad_a(dC: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -
     return dA
 
 
-def grad_b(A: torch.Tensor, dC: torch.Tensor, out: torch.Tensor | None = None,
+def grad_b(A, dC: torch.Tensor, out: torch.Tensor | None = None,
            workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """dB = A^T*dC (A m x k, dC m x n, n <= 32)."""
+    """dB = A^T*dC (A m x k or a SplitA, dC m x n, n <= 32)."""
+    if isinstance(A, SplitA):
+        _check_device(A.planes, dC)
+        m, k = A.shape
+        dC = colmajor(dC)
+        n = dC.shape[1]
+        dB = out if out is not None else empty_colmajor(k, n, torch.float32, dC.device)
+        ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
+            if workspace is not None else (None, 0)
+        _lib.call("tsm_grad_b", m, k, n, A.planes.data_ptr(), A.ld, dC.data_ptr(), _ld(dC),
+                  dB.data_ptr(), _ld(dB), A.dtype_code, ws, wsb, _stream())
+        return dB
     _check_device(A, dC)
     dt = _DT[A.dtype]
     A = colmajor(A)
@@ -122,3 +208,6 @@ def grad_b(A: torch.Tensor, dC: torch.Tensor, out: torch.Tensor | None = None,
 
 def workspace_size(op: int, m: int, k: int, n: int, dtype: int) -> int:
     return int(_lib.lib().tsm2x_workspace_size(op, m, k, n, dtype))
+
+
+from .autograd import TSMMatmul, matmul  # noqa: E402,F401

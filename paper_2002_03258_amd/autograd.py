@@ -1,0 +1,72 @@
+"""C = A*B as a torch.autograd.Function backed by the library's kernels.
+
+Forward: TSM2R (large A) or TSM2L (tall A with k <= 32).  Backward of the
+scalar loss with upstream gradient dC:  dA = dC*B^T (rowtile kernel, a TSM2L
+shape) and dB = A^T*dC (tn kernel, a reduction along m split across
+workgroups and finished in double).
+
+Modes:
+  "f64", "f32"            A, B, C and both gradients in that precision.
+  "bf16", "bf16_split",   A is float32 and is stored for the product as
+  "f16", "f16_split"      bfloat16/binary16 hi (and lo) planes, split once in
+                          the forward and kept for the backward; B, C, dA and
+                          dB are float32.  dA = dC*B^T involves only float
+                          data and runs in float.
+"""
+from __future__ import annotations
+
+import torch
+
+_LOWP = {"bf16": ("bf16", False), "bf16_split": ("bf16", True),
+         "f16": ("f16", False), "f16_split": ("f16", True)}
+
+
+def _kind(A_shape, kind: str) -> str:
+    if kind in ("R", "L"):
+        return kind
+    m, k = A_shape
+    return "L" if k <= 32 and m >= 64 * k else "R"
+
+
+class TSMMatmul(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A: torch.Tensor, B: torch.Tensor, mode: str = "f32", kind: str = "auto"):
+        from . import split, tsm2l, tsm2r
+        kd = _kind(tuple(A.shape), kind)
+        if mode in _LOWP:
+            if A.dtype != torch.float32 or B.dtype != torch.float32:
+                raise ValueError("low-precision modes take float32 A and B")
+            fmt, lo = _LOWP[mode]
+            Aop = split(A, fmt, lo)
+        else:
+            want = torch.float64 if mode == "f64" else torch.float32
+            if A.dtype != want or B.dtype != want:
+                raise ValueError("mode %s needs %s A and B" % (mode, want))
+            Aop = A
+        C = tsm2l(Aop, B) if kd == "L" else tsm2r(Aop, B)
+        ctx.save_for_backward(B)
+        ctx.Aop = Aop            # the tensor A or its stored planes
+        ctx.lowp = mode in _LOWP
+        return C
+
+    @staticmethod
+    def backward(ctx, dC: torch.Tensor):
+        from . import grad_a, grad_b
+        (B,) = ctx.saved_tensors
+        dA = dB = None
+        dC = dC.to(B.dtype)
+        if ctx.needs_input_grad[0]:
+            dA = grad_a(dC, B)
+        if ctx.needs_input_grad[1]:
+            dB = grad_b(ctx.Aop, dC)
+        ctx.Aop = None
+        return dA, dB, None, None
+
+
+def matmul(A: torch.Tensor, B: torch.Tensor, mode: str | None = None,
+           kind: str = "auto") -> torch.Tensor:
+    """Differentiable C = A*B.  mode defaults to the dtype of A ("f64" or
+    "f32"); kind "R" (TSM2R), "L" (TSM2L) or "auto" (by shape)."""
+    if mode is None:
+        mode = "f64" if A.dtype == torch.float64 else "f32"
+    return TSMMatmul.apply(A, B, mode, kind)

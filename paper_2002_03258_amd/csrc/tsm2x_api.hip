@@ -75,6 +75,10 @@ bool valid_dtype(int dt) { return dt >= TSM_F64 && dt <= TSM_F16_SPLIT; }
 bool plain_dtype(int dt) { return dt == TSM_F64 || dt == TSM_F32; }
 int esize(int dt) { return dt == TSM_F64 ? 8 : 4; }
 
+bool vec_ok(const void* p, int64_t ld, int es) {
+    return ((uintptr_t)p & 15u) == 0 && ((ld * es) % 16) == 0;
+}
+
 int pow2_ge(int64_t n) {
     int p = 1;
     while (p < n) p <<= 1;
@@ -82,93 +86,75 @@ int pow2_ge(int64_t n) {
 }
 
 // ------------------------------------------------------------- plans
-struct NNPlan {
-    int np;
-    int64_t tiles;
-    int S;
-    int64_t kslice;
-    size_t ws;
-};
-
-NNPlan plan_nn(int64_t m, int64_t k, int64_t n, int dt, int cus) {
-    NNPlan P{};
-    const int es = esize(dt);
-    const int RL = 16 / es, TR = 64 * RL;
-    const int WK = 4;
-    P.np = pow2_ge(n < 1 ? 1 : n);
-    const int U = P.np <= 16 ? 8 : 4;
-    P.tiles = cdiv(m, TR);
-    const int64_t target = env_int("TSM2X_NN_TARGET_BLOCKS", (int64_t)cus * 4);
-    int64_t S = cdiv(target, P.tiles);
-    const int64_t s_len = cdiv(k, WK * 64);                       // >= 64 columns per wavefront
-    const int64_t s_cost = (k * es) / ((int64_t)P.np * 200);       // partials <= ~8 % of A
-    if (S > s_len) S = s_len;
-    if (S > s_cost) S = s_cost;
-    if (P.tiles > MAX_TICKETS) S = 1;
-    if (S < 1) S = 1;
-    int64_t ks = cdiv(k, S);
-    ks = cdiv(ks, WK * U) * (WK * U);
-    P.kslice = ks;
-    P.S = (int)cdiv(k, ks);
-    if (P.S < 1) P.S = 1;
-    P.ws = P.S > 1 ? TICKET_BYTES + (size_t)P.tiles * P.S * P.np * TR * 8 : 0;
-    return P;
-}
-
 struct RTPlan {
     int kp;
-    int cpb;
+    int64_t cpb;
     int64_t bx, by;
 };
 
+// rowtile: a wavefront owns 16*RL*RG rows; one pass covers up to 32 output
+// columns.  For nout <= 32 a persistent grid of about 8 workgroups per CU
+// walks the row tiles; wider outputs are also split into column ranges.
 RTPlan plan_rowtile(int64_t m, int64_t kin, int64_t nout, int dt, int cus) {
     RTPlan P{};
     const int es = esize(dt);
-    const int RL = 16 / es, TR = 64 * RL;
+    const int RL = 16 / es;
     P.kp = kin <= 8 ? 8 : (kin <= 16 ? 16 : 32);
-    int64_t cpb = 16384 / (es * P.kp);
-    if (cpb > 256) cpb = 256;
-    if (cpb > nout) cpb = nout;
-    if (cpb < 1) cpb = 1;
-    P.cpb = (int)cpb;
-    P.by = cdiv(nout, cpb);
+    const int RG = (P.kp == 32 && nout > 16) ? 1 : 2;
+    const int64_t TR = 16 * RL * RG;
     const int64_t ntiles = cdiv(m, TR);
-    int64_t bx = cdiv(ntiles, 4);
-    int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cus * 8) / P.by;
-    if (cap < 1) cap = 1;
-    if (bx > cap) bx = cap;
+    const int64_t wblocks = cdiv(ntiles, 4);
+    const int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cus * 8);
+    if (nout <= 32) {
+        P.cpb = nout;
+        P.by = 1;
+    } else {
+        // enough column ranges to fill the machine, each a multiple of 32
+        int64_t by = cdiv(cap, wblocks);
+        if (by < 1) by = 1;
+        int64_t cpb = cdiv(nout, by);
+        cpb = cdiv(cpb, 32) * 32;
+        if (cpb < 32) cpb = 32;
+        P.cpb = cpb;
+        P.by = cdiv(nout, cpb);
+    }
+    int64_t bx = wblocks;
+    int64_t lim = cap / P.by;
+    if (lim < 1) lim = 1;
+    if (bx > lim) bx = lim;
     if (bx < 1) bx = 1;
     P.bx = bx;
     return P;
 }
 
 struct TNPlan {
-    int np;
     int64_t groups;
     int S;
     int64_t rslice;
     size_t ws;
 };
 
+// tn: one workgroup per 16 output rows (columns of X) and slice of R; the
+// WK = 4 wavefronts split the slice.
 TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     TNPlan P{};
-    const int es = esize(dt);
-    const int RL = 16 / es, TR = 64 * RL;
-    P.np = pow2_ge(n < 1 ? 1 : n);
-    const int CPB = 4 * TN_J(P.np);
-    P.groups = cdiv(ncols, CPB);
+    // rows per wavefront step: 4 * RL * RG for the float kernels (RG = 2),
+    // 32 * RG for the 16-bit form
+    const int64_t RB = plain_dtype(dt) ? 4 * (16 / esize(dt)) * 2 : 64;
+    const int NT16 = n <= 16 ? 1 : 2;
+    P.groups = cdiv(ncols, 16);
     const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * 4);
     int64_t S = cdiv(target, P.groups);
-    const int64_t s_len = R / ((int64_t)TR * 8);
+    const int64_t s_len = R / (RB * 4 * 8);   // >= 8 steps per wavefront
     if (S > s_len) S = s_len;
     if (P.groups > MAX_TICKETS) S = 1;
     if (S < 1) S = 1;
     int64_t rs = cdiv(R, S);
-    rs = cdiv(rs, TR) * TR;
+    rs = cdiv(rs, RB * 4) * (RB * 4);
     P.rslice = rs;
     P.S = (int)cdiv(R, rs);
     if (P.S < 1) P.S = 1;
-    P.ws = P.S > 1 ? TICKET_BYTES + (size_t)P.groups * P.S * CPB * P.np * 8 : 0;
+    P.ws = P.S > 1 ? TICKET_BYTES + (size_t)P.groups * P.S * 256 * NT16 * 8 : 0;
     return P;
 }
 
@@ -246,15 +232,29 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
     int rc = check_mm(2, m, k, n, A, lda, B, ldb, C, ldc, dtype, rowA);
     if (rc) return rc;
     if (n > 32) return TSM_ERR_UNSUPPORTED;
-    if (!plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (rowA && !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
     if (m == 0 || n == 0) return TSM_SUCCESS;
     hipStream_t st = (hipStream_t)stream;
     if (k == 0) {
-        launch_fill_zero(m, n, C, ldc, dtype, st);
+        launch_fill_zero(m, n, C, ldc, plain_dtype(dtype) ? dtype : TSM_F32, st);
         return check_launch("fill_zero");
     }
     const int cus = cu_count();
     void* w = nullptr;
+    if (!plain_dtype(dtype)) {
+        // A: 16-bit hi plane (and lo plane lda*k elements after it); B, C float
+        NNPlan P{};
+        plan_tsm2r_lp(m, k, n, dtype, cus, vec_ok(A, lda, 2), &P);
+        rc = get_ws(P.ws, ws, ws_bytes, &w);
+        if (rc) return rc;
+        LaunchNN L{};
+        L.fn = P.fn;
+        L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C;
+        L.ldc = ldc; L.np = P.np; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
+        if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+        if (launch_tsm2r_lp(L, dtype, st)) return check_launch("tsm2r_lp_kernel");
+        return check_launch("tsm2r_lp_kernel");
+    }
     if (rowA) {
         // A row-major m x k is the column-major k x m matrix X = A^T (ld lda):
         // C = X^T * B, a reduction along the contiguous dimension.
@@ -264,15 +264,17 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
         LaunchTN L{};
         L.R = k; L.ncols = m; L.n = n;
         L.X = A; L.ldx = lda; L.Y = B; L.ldy = ldb; L.O = C; L.ldo = ldc;
-        L.np = P.np; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
+        L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
         if (P.S > 1) split_ws(w, &L.part, &L.tickets);
         if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_kernel");
     }
-    NNPlan P = plan_nn(m, k, n, dtype, cus);
+    NNPlan P{};
+    if (plan_tsm2r(m, k, n, dtype, cus, vec_ok(A, lda, esize(dtype)), &P)) return TSM_ERR_UNSUPPORTED;
     rc = get_ws(P.ws, ws, ws_bytes, &w);
     if (rc) return rc;
     LaunchNN L{};
+    L.fn = P.fn;
     L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C; L.ldc = ldc;
     L.np = P.np; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
     if (P.S > 1) split_ws(w, &L.part, &L.tickets);
@@ -291,17 +293,26 @@ int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const voi
           int64_t ldb, void* C, int64_t ldc, int dtype, void* stream) {
     int rc = check_mm(1, m, k, n, A, lda, B, ldb, C, ldc, dtype, false);
     if (rc) return rc;
-    if (k > 32 || n > 32 || !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (k > 32 || n > 32) return TSM_ERR_UNSUPPORTED;
     if (m == 0 || n == 0) return TSM_SUCCESS;
     hipStream_t st = (hipStream_t)stream;
     if (k == 0) {
-        launch_fill_zero(m, n, C, ldc, dtype, st);
+        launch_fill_zero(m, n, C, ldc, plain_dtype(dtype) ? dtype : TSM_F32, st);
         return check_launch("fill_zero");
+    }
+    if (!plain_dtype(dtype)) {
+        // 128-row tiles walked by a persistent grid of about 8 workgroups per CU
+        int64_t blocks = cdiv(cdiv(m, 128), 4);
+        const int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cu_count() * 8);
+        if (blocks > cap) blocks = cap;
+        if (blocks < 1) blocks = 1;
+        launch_tsm2l_lp(m, k, n, A, lda, (const float*)B, ldb, (float*)C, ldc, dtype, blocks, st);
+        return check_launch("tsm2l_lp_kernel");
     }
     RTPlan P = plan_rowtile(m, k, n, dtype, cu_count());
     LaunchRT L{};
     L.m = m; L.kin = (int)k; L.nout = n; L.X = A; L.ldx = lda; L.Y = B; L.ys_in = 1;
-    L.ys_out = ldb; L.O = C; L.ldo = ldc; L.kp = P.kp; L.cols_per_block = P.cpb;
+    L.ys_out = ldb; L.O = C; L.ldo = ldc; L.kp = P.kp; L.cols_per_block = (int)P.cpb;
     L.blocks_x = P.bx; L.blocks_y = P.by;
     if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("rowtile_kernel");
@@ -330,7 +341,7 @@ int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc, co
     RTPlan P = plan_rowtile(m, n, k, dtype, cu_count());
     LaunchRT L{};
     L.m = m; L.kin = (int)n; L.nout = k; L.X = dC; L.ldx = lddc; L.Y = B; L.ys_in = ldb;
-    L.ys_out = 1; L.O = dA; L.ldo = ldda; L.kp = P.kp; L.cols_per_block = P.cpb;
+    L.ys_out = 1; L.O = dA; L.ldo = ldda; L.kp = P.kp; L.cols_per_block = (int)P.cpb;
     L.blocks_x = P.bx; L.blocks_y = P.by;
     if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("rowtile_kernel");
@@ -349,11 +360,11 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     if (!dB && k > 0 && n > 0) return -8;
     if (lddb < (k > 1 ? k : 1)) return -9;
     if (!valid_dtype(dtype)) return -10;
-    if (n > 32 || !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (n > 32) return TSM_ERR_UNSUPPORTED;
     if (k == 0 || n == 0) return TSM_SUCCESS;
     hipStream_t st = (hipStream_t)stream;
     if (m == 0) {
-        launch_fill_zero(k, n, dB, lddb, dtype, st);
+        launch_fill_zero(k, n, dB, lddb, plain_dtype(dtype) ? dtype : TSM_F32, st);
         return check_launch("fill_zero");
     }
     // dB = A^T * dC: X = A (R = m rows, k columns), Y = dC.
@@ -363,23 +374,46 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     if (rc) return rc;
     LaunchTN L{};
     L.R = m; L.ncols = k; L.n = n; L.X = A; L.ldx = lda; L.Y = dC; L.ldy = lddc; L.O = dB;
-    L.ldo = lddb; L.np = P.np; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
+    L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
     if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+    if (!plain_dtype(dtype)) {
+        if (launch_tn_lp(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
+        return check_launch("tn_lp_kernel");
+    }
     if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("tn_kernel");
 }
 
 int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
                 int64_t ldh, int fmt, void* stream) {
-    (void)m; (void)k; (void)A; (void)lda; (void)hi; (void)lo; (void)ldh; (void)fmt; (void)stream;
-    return TSM_ERR_UNSUPPORTED;
+    if (m < 0) return -1;
+    if (k < 0) return -2;
+    if (!A && m > 0 && k > 0) return -3;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (!hi && m > 0 && k > 0) return -5;
+    if (ldh < (m > 1 ? m : 1)) return -7;
+    if (fmt != 0 && fmt != 1) return -8;
+    if (m == 0 || k == 0) return TSM_SUCCESS;
+    launch_split(m, k, A, lda, hi, lo, ldh, fmt, (hipStream_t)stream);
+    return check_launch("split_kernel");
 }
 
 size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n, int dtype) {
-    if (m <= 0 || k <= 0 || n <= 0 || n > 32 || !plain_dtype(dtype)) return 0;
+    if (m <= 0 || k <= 0 || n <= 0 || n > 32 || !valid_dtype(dtype)) return 0;
     const int cus = cu_count();
+    if (!plain_dtype(dtype)) {
+        if (op == TSM_OP_GRAD_B) return plan_tn(m, k, n, dtype, cus).ws;
+        if (op != TSM_OP_TSM2R) return 0;
+        NNPlan P{};
+        plan_tsm2r_lp(m, k, n, dtype, cus, true, &P);
+        return P.ws;
+    }
     switch (op) {
-        case TSM_OP_TSM2R: return plan_nn(m, k, n, dtype, cus).ws;
+        case TSM_OP_TSM2R: {
+            NNPlan P{};
+            // the aligned and unaligned instances share their tiling
+            return plan_tsm2r(m, k, n, dtype, cus, true, &P) ? 0 : P.ws;
+        }
         case TSM_OP_TSM2R_ROWMAJOR: return plan_tn(k, m, n, dtype, cus).ws;
         case TSM_OP_GRAD_B: return plan_tn(m, k, n, dtype, cus).ws;
         default: return 0;

@@ -17,9 +17,23 @@ enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3, DT_BF16_SPLIT = 4, DT_F1
 constexpr int64_t MAX_TICKETS = 4096;
 constexpr size_t TICKET_BYTES = MAX_TICKETS * 4;
 
-constexpr int TN_J(int np) { return (64 / np) > 8 ? 8 : ((64 / np) < 1 ? 1 : 64 / np); }
+struct NNPlan {             // TSM2R launch plan (column-major A)
+    const void* fn;         // kernel instance
+    int np;                 // padded n
+    int tile_rows;
+    int64_t tiles;          // row tiles (gridDim.x)
+    int S;                  // k slices (gridDim.y)
+    int64_t kslice;         // columns per k slice
+    size_t ws;              // workspace bytes (0 when S == 1)
+};
+
+// Plan of tsm2r for (m, k, n, dtype) on a device with `cus` compute units;
+// `vec`: A is 16-byte aligned with a 16-byte multiple leading dimension.
+// Returns nonzero if no kernel instance covers the request.
+int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P);
 
 struct LaunchNN {           // tsm2r_nn: C = A*B, column-major A
+    const void* fn;
     int64_t m, k, n;
     const void* A; int64_t lda;
     const void* B; int64_t ldb;
@@ -47,15 +61,25 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
     const void* X; int64_t ldx;
     const void* Y; int64_t ldy;
     void* O; int64_t ldo;
-    int np;
-    int64_t groups;         // column groups (gridDim.x)
+    int64_t groups;         // 16-column tiles of the output (gridDim.x)
     int S;                  // reduction slices (gridDim.y)
     int64_t rslice;
     double* part;
     unsigned* tickets;
 };
 
+// Low-precision storage forms of A (bf16 / f16, single or split planes).
+int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P);
+int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st);
+int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
+                 int64_t ldh, int fmt, hipStream_t st);
+int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
+                    int64_t ldb, float* C, int64_t ldc, int dtype, int64_t blocks,
+                    hipStream_t st);
+
 int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st);
+struct LaunchTN;
+int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st);
 int launch_rowtile(const LaunchRT& L, int dtype, hipStream_t st);
 int launch_tn(const LaunchTN& L, int dtype, hipStream_t st);
 int launch_fill_zero(int64_t m, int64_t n, void* C, int64_t ldc, int dtype, hipStream_t st);

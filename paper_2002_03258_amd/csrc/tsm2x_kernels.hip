@@ -31,399 +31,374 @@
 #include <stdint.h>
 
 #include "tsm2x_internal.h"
+#include "tsm2x_device.h"
 
 namespace tsm {
 
-constexpr int WAVE = 64;
-
-template <typename T, int N>
-struct VecOf {
-    typedef T type __attribute__((ext_vector_type(N)));
-};
-
-// RL consecutive elements starting at p: one 16-byte non-temporal load when
-// the caller has checked alignment (VEC) and bounds (FULL); otherwise
-// element-wise loads guarded by `valid` elements remaining.
-template <typename T, int RL, bool VEC>
-__device__ __forceinline__ void load_run(const T* __restrict__ p, int64_t valid,
-                                         bool full, T (&out)[RL]) {
-    if (VEC && full) {
-        typedef typename VecOf<T, RL>::type V;
-        V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-#pragma unroll
-        for (int r = 0; r < RL; ++r) out[r] = v[r];
-    } else {
-#pragma unroll
-        for (int r = 0; r < RL; ++r) out[r] = (r < valid) ? p[r] : T(0);
-    }
-}
-
-template <typename T, int RL, bool VEC>
-__device__ __forceinline__ void store_run(T* __restrict__ p, int64_t valid,
-                                          bool full, const T (&v)[RL]) {
-    if (VEC && full) {
-        typedef typename VecOf<T, RL>::type V;
-        V x;
-#pragma unroll
-        for (int r = 0; r < RL; ++r) x[r] = v[r];
-        __builtin_nontemporal_store(x, reinterpret_cast<V*>(p));
-    } else {
-#pragma unroll
-        for (int r = 0; r < RL; ++r)
-            if (r < valid) p[r] = v[r];
-    }
-}
-
-// Ticket protocol of the split reductions: every workgroup of a group
-// publishes its double-precision partial, then takes a ticket; the one that
-// draws the last ticket sums all partials in slice order and re-arms the
-// counter for the next launch.
-__device__ __forceinline__ bool take_last_ticket(unsigned* __restrict__ ticket,
-                                                 int nslices) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(ticket, 1u);
-        s_last = (prev == (unsigned)(nslices - 1)) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        return true;
-    }
-    return false;
-}
-
-__device__ __forceinline__ void rearm_ticket(unsigned* __restrict__ ticket) {
-    if (threadIdx.x == 0) atomicExch(ticket, 0u);
-}
-
 // --------------------------------------------------------------------------
-// tsm2r_nn
+// tsm2r_nn: C = A*B, A column-major m x k (k large), n <= 16*NT16.
+//
+// Outer-product form of the Design of TSM2R (Algorithm 2) on the matrix
+// cores: C^T = B^T * A^T.  S is a 16 x 4 block of B^T (lane l: B[j, 16t+rl]),
+// T a 4 x 16 block of A^T.  A 16-column group at j0 is consumed in steps
+// st = 0..3 with columns j = j0 + 4*kk + st; a lane's four B values of a
+// group, B[j0+4kk .. j0+4kk+3, 16t+rl], are contiguous in B's column.  The
+// next group's A and B are loaded while the current one is multiplied (the
+// prefetching of Algorithm 4).  Lane l ends up with
+// C[row0 + 16*RL*g + RL*rl + q, 16t + mrow(kk, r)] in acc[g][q][t][r].
+//
+// The k range is split across the WK wavefronts of a workgroup and across
+// workgroups; the partial sums are added in double precision in a fixed
+// order, the last workgroup of a row tile to arrive doing the final sum.
 // --------------------------------------------------------------------------
-template <typename T, int NP>
-struct NNShape {
-    static constexpr int RL = 16 / (int)sizeof(T);        // rows per lane
-    static constexpr int TR = WAVE * RL;                  // rows per tile
-    static constexpr int KC0 = 4096 / (NP * (int)sizeof(T));
-    static constexpr int KC = KC0 < 64 ? KC0 : 64;        // B rows per chunk per wave
-    static constexpr int PG0 = 16 / RL;                   // reduction column group
-    static constexpr int PG = PG0 < NP ? PG0 : NP;
-};
-
-template <typename T, int NP, int WK, int U, bool VEC>
+template <typename T, int NT16, int RG, int WK, bool VEC>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
     int64_t m, int64_t k, int n, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
     int64_t kslice, double* __restrict__ part, unsigned* __restrict__ tickets) {
-    typedef NNShape<T, NP> S_;
-    constexpr int RL = S_::RL, TR = S_::TR, KC = S_::KC, PG = S_::PG;
-    constexpr int NT = WAVE * WK;
-    constexpr int VPT = (KC * NP) / WAVE;   // staged B values per thread
-    static_assert((KC * NP) % WAVE == 0, "B chunk must split evenly");
-    static_assert(2 * WK * KC * NP * (int)sizeof(T) <= 32768, "LDS budget");
+    typedef Mfma<T> M;
+    typedef typename M::acc Acc;
+    constexpr int RL = 16 / (int)sizeof(T);
+    constexpr int TR = 16 * RL * RG;     // rows per tile
+    constexpr int NP = 16 * NT16;
+    constexpr int PG = 4;
     static_assert(WK * PG * TR * 8 <= 32768, "LDS budget");
-    __shared__ __align__(16) unsigned char smem[32768];
-    T* bst = reinterpret_cast<T*>(smem);   // [2][WK][KC][NP]
+    __shared__ __align__(16) unsigned char smem[WK * PG * TR * 8];
 
     const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
     const int64_t tile = blockIdx.x;
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t row0 = tile * TR;
-    const int64_t lrow = row0 + (int64_t)lane * RL;
     const bool full = (row0 + TR <= m);
-    const int64_t rvalid = m - lrow;   // rows this lane may touch (if < RL)
     const int64_t kb0 = (int64_t)s * kslice;
     const int64_t kb1 = (kb0 + kslice < k) ? kb0 + kslice : k;
     const int64_t lw = kslice / WK;
     const int64_t wk0 = kb0 + w * lw;
     const int64_t wk1 = (wk0 + lw < kb1) ? wk0 + lw : kb1;
-    const int nchunks = (int)((lw + KC - 1) / KC);
 
-    T acc[RL][NP];
+    Acc acc[RG][RL][NT16];
 #pragma unroll
-    for (int r = 0; r < RL; ++r)
+    for (int g = 0; g < RG; ++g)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) acc[r][p] = T(0);
+        for (int q = 0; q < RL; ++q)
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) acc[g][q][t] = Acc{0, 0, 0, 0};
 
-    T breg[VPT];
-    auto fetchB = [&](int c) {
+    auto loadA = [&](int64_t j0, T (&av)[4][RG][RL]) {
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            const int v = threadIdx.x + i * NT;
-            const int jj = v % KC, p = (v / KC) % NP, ww = v / (KC * NP);
-            const int64_t wb = kb0 + ww * lw;
-            const int64_t wend = (wb + lw < kb1) ? wb + lw : kb1;
-            const int64_t j = wb + (int64_t)c * KC + jj;
-            breg[i] = (p < n && j < wend) ? B[j + p * ldb] : T(0);
-        }
-    };
-    auto storeB = [&](int buf) {
+        for (int st = 0; st < 4; ++st) {
+            const int64_t j = j0 + 4 * kk + st;
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            const int v = threadIdx.x + i * NT;
-            const int jj = v % KC, p = (v / KC) % NP, ww = v / (KC * NP);
-            bst[((buf * WK + ww) * KC + jj) * NP + p] = breg[i];
-        }
-    };
-
-    // One column of A times one broadcast row of B (from LDS).
-    auto fma_col = [&](const T (&a)[RL], const T* __restrict__ brow) {
-        T b[NP];
+            for (int g = 0; g < RG; ++g) {
+                const int64_t r = row0 + 16 * RL * g + RL * rl;
+                if (j < wk1)
+                    load_run<T, RL, VEC>(A + r + j * lda, m - r, full, av[st][g]);
+                else
 #pragma unroll
-        for (int p = 0; p < NP; ++p) b[p] = brow[p];
-#pragma unroll
-        for (int r = 0; r < RL; ++r)
-#pragma unroll
-            for (int p = 0; p < NP; ++p) acc[r][p] = __builtin_fma(a[r], b[p], acc[r][p]);
-    };
-
-    fetchB(0);
-    storeB(0);
-    __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nchunks) fetchB(c + 1);
-        const int64_t c0 = wk0 + (int64_t)c * KC;
-        const int64_t c1 = (c0 + KC < wk1) ? c0 + KC : wk1;
-        if (c0 < c1) {
-            const T* __restrict__ bs = bst + (buf * WK + w) * KC * NP;
-            const T* __restrict__ Ap = A + lrow + c0 * lda;
-            const int ncol = (int)(c1 - c0);
-            const int ng = ncol / U;
-            if (ng > 0) {
-                T a[U][RL];
-#pragma unroll
-                for (int u = 0; u < U; ++u) load_run<T, RL, VEC>(Ap + u * lda, rvalid, full, a[u]);
-                for (int g = 0; g < ng; ++g) {
-                    T an[U][RL];
-                    if (g + 1 < ng) {
-#pragma unroll
-                        for (int u = 0; u < U; ++u)
-                            load_run<T, RL, VEC>(Ap + ((g + 1) * U + u) * lda, rvalid, full, an[u]);
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) fma_col(a[u], bs + (g * U + u) * NP);
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-#pragma unroll
-                        for (int r = 0; r < RL; ++r) a[u][r] = an[u][r];
-                }
-            }
-            for (int j = ng * U; j < ncol; ++j) {
-                T a1[RL];
-                load_run<T, RL, VEC>(Ap + j * lda, rvalid, full, a1);
-                fma_col(a1, bs + j * NP);
+                    for (int q = 0; q < RL; ++q) av[st][g][q] = T(0);
             }
         }
-        if (c + 1 < nchunks) storeB(buf ^ 1);
-        __syncthreads();
-    }
-
-    // Sum the WK wavefronts' partials (double, wave order), PG columns at a time.
-    double* red = reinterpret_cast<double*>(smem);   // [WK][PG][TR]
+    };
+    auto loadB = [&](int64_t j0, T (&bv)[NT16][4]) {
 #pragma unroll
-    for (int pg = 0; pg < NP; pg += PG) {
-        if (pg < n) {
-            __syncthreads();
+        for (int t = 0; t < NT16; ++t) {
+            const int p = 16 * t + rl;
 #pragma unroll
-            for (int pp = 0; pp < PG; ++pp)
-#pragma unroll
-                for (int r = 0; r < RL; ++r)
-                    red[(w * PG + pp) * TR + lane * RL + r] = (double)acc[r][pg + pp];
-            __syncthreads();
-            for (int e = threadIdx.x; e < PG * TR; e += NT) {
-                const int pp = e / TR, rr = e % TR;
-                const int p = pg + pp;
-                const int64_t row = row0 + rr;
-                double v = red[pp * TR + rr];
-#pragma unroll
-                for (int ww = 1; ww < WK; ++ww) v += red[(ww * PG + pp) * TR + rr];
-                if (p < n && row < m) {
-                    if (nsl == 1)
-                        C[row + p * ldc] = (T)v;
-                    else
-                        part[((tile * nsl + s) * NP + p) * TR + rr] = v;
-                }
+            for (int st = 0; st < 4; ++st) {
+                const int64_t j = j0 + 4 * kk + st;
+                bv[t][st] = (p < n && j < wk1) ? B[j + p * ldb] : T(0);
             }
         }
-    }
-    if (nsl == 1) return;
-    if (!take_last_ticket(tickets + tile, nsl)) return;
-    for (int e = threadIdx.x; e < n * TR; e += NT) {
-        const int p = e / TR, rr = e % TR;
-        const int64_t row = row0 + rr;
-        if (row < m) {
-            double v = 0.0;
-            for (int s2 = 0; s2 < nsl; ++s2) v += part[((tile * nsl + s2) * NP + p) * TR + rr];
-            C[row + p * ldc] = (T)v;
+    };
+
+    if (wk1 > wk0) {
+        const int ng = (int)((wk1 - wk0 + 15) / 16);
+        T av[4][RG][RL], bv[NT16][4];
+        loadA(wk0, av);
+        loadB(wk0, bv);
+        for (int g16 = 0; g16 < ng; ++g16) {
+            T an[4][RG][RL], bn[NT16][4];
+            if (g16 + 1 < ng) {
+                loadA(wk0 + 16 * (g16 + 1), an);
+                loadB(wk0 + 16 * (g16 + 1), bn);
+            }
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q)
+#pragma unroll
+                        for (int t = 0; t < NT16; ++t)
+                            acc[g][q][t] = M::op(bv[t][st], av[st][g][q], acc[g][q][t]);
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) av[st][g][q] = an[st][g][q];
+#pragma unroll
+            for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                for (int st = 0; st < 4; ++st) bv[t][st] = bn[t][st];
         }
     }
-    rearm_ticket(tickets + tile);
+
+    nn_finish<T, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part, tickets,
+                                 reinterpret_cast<double*>(smem), [&](int pg, double* red) {
+        const int t = pg / 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pp = 16 * t + M::mrow(kk, r) - pg;
+            if (pp >= 0 && pp < PG) {
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q)
+                        red[(w * PG + pp) * TR + 16 * RL * g + RL * rl + q] =
+                            (double)acc[g][q][t][r];
+            }
+        }
+    });
 }
 
 // --------------------------------------------------------------------------
-// rowtile: O(m x nout) = X(m x kin) * Y(kin x nout), kin <= KP <= 32.
-// Y(ji, jo) = Y[ji * ys_in + jo * ys_out], so B and B^T are both views.
+// rowtile: O(m x nout) = X(m x kin) * Y(kin x nout), kin <= 4*KS <= 32,
+// Y(ji, jo) = Y[ji * ys_in + jo * ys_out] (so B and B^T are both views).
+//
+// TSM2L (Design of TSM2L, Algorithm 6): a grid of fewer wavefronts than row
+// tiles walks the horizontal tiles of A; each lane loads its 16-byte row
+// runs of all kin columns once and B, held whole in registers, never leaves
+// the chip, so C is written once and never re-read.  The same kernel gives
+// dA = dC * B^T, where nout = k may be large: workgroups then also split the
+// output columns and a wavefront reuses its X registers for every 16*NT16
+// output columns of its range.
+//
+// On the matrix cores: O^T = Y^T * X^T with S[rl][kk] = Y(4 st + kk,
+// col0 + 16 t + rl) and T[kk][rl] = X[row(rl, q), 4 st + kk]; lane l holds
+// O[row(rl, q), col0 + 16 t + mrow(kk, r)] in acc[g][q][t][r] with
+// row(rl, q) = row0 + 16*RL*g + RL*rl + q.
 // --------------------------------------------------------------------------
-template <typename T, int KP, int NC, bool VEC>
+template <typename T, int KS, int NT16, int RG, bool VEC>
 __global__ __launch_bounds__(256) void rowtile_kernel(
     int64_t m, int kin, int64_t nout, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ys_in, int64_t ys_out, T* __restrict__ O,
-    int64_t ldo, int cols_per_block) {
+    int64_t ldo, int64_t cols_per_block) {
+    typedef Mfma<T> M;
+    typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
-    constexpr int TR = WAVE * RL;
+    constexpr int TR = 16 * RL * RG;
     constexpr int WPB = 4;
-    __shared__ __align__(16) T ys[(16384 / sizeof(T))];   // [cols_per_block][KP]
+    constexpr int CW = 16 * NT16;        // output columns per pass
 
     const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
-    const int64_t colbase = (int64_t)blockIdx.y * cols_per_block;
-    int ncb = cols_per_block;
-    if (colbase + ncb > nout) ncb = (int)(nout - colbase);
+    const int64_t cb0 = (int64_t)blockIdx.y * cols_per_block;
+    const int64_t cb1 = (cb0 + cols_per_block < nout) ? cb0 + cols_per_block : nout;
 
-    for (int e = threadIdx.x; e < cols_per_block * KP; e += 256) {
-        const int jo = e / KP, ji = e % KP;
-        const int64_t col = colbase + jo;
-        ys[e] = (ji < kin && jo < ncb) ? Y[ji * ys_in + col * ys_out] : T(0);
-    }
-    __syncthreads();
+    T yv[KS][NT16];
+    auto loadY = [&](int64_t c0) {
+#pragma unroll
+        for (int st = 0; st < KS; ++st)
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                const int ji = 4 * st + kk;
+                const int64_t jo = c0 + 16 * t + rl;
+                yv[st][t] = (ji < kin && jo < cb1) ? Y[ji * ys_in + jo * ys_out] : T(0);
+            }
+    };
+    const bool one_pass = (cb1 - cb0) <= CW;
+    if (one_pass) loadY(cb0);
 
     const int64_t ntiles = (m + TR - 1) / TR;
     for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles;
          tile += (int64_t)gridDim.x * WPB) {
         const int64_t row0 = tile * TR;
-        const int64_t lrow = row0 + (int64_t)lane * RL;
         const bool full = (row0 + TR <= m);
-        const int64_t rvalid = m - lrow;
-        T x[KP][RL];
+        T xv[KS][RG][RL];
 #pragma unroll
-        for (int ji = 0; ji < KP; ++ji) {
-            if (ji < kin)
-                load_run<T, RL, VEC>(X + lrow + ji * ldx, rvalid, full, x[ji]);
-            else
+        for (int st = 0; st < KS; ++st) {
+            const int ji = 4 * st + kk;
 #pragma unroll
-                for (int r = 0; r < RL; ++r) x[ji][r] = T(0);
-        }
-        for (int jo = 0; jo < ncb; jo += NC) {
-            T acc[NC][RL];
+            for (int g = 0; g < RG; ++g) {
+                const int64_t r = row0 + 16 * RL * g + RL * rl;
+                if (ji < kin)
+                    load_run<T, RL, VEC>(X + r + ji * ldx, m - r, full, xv[st][g]);
+                else
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) {
-                const T* __restrict__ yr = ys + (jo + cc) * KP;
-#pragma unroll
-                for (int r = 0; r < RL; ++r) acc[cc][r] = T(0);
-#pragma unroll
-                for (int ji = 0; ji < KP; ++ji) {
-                    const T b = yr[ji];
-#pragma unroll
-                    for (int r = 0; r < RL; ++r) acc[cc][r] = __builtin_fma(x[ji][r], b, acc[cc][r]);
-                }
+                    for (int q = 0; q < RL; ++q) xv[st][g][q] = T(0);
             }
+        }
+        for (int64_t c0 = cb0; c0 < cb1; c0 += CW) {
+            if (!one_pass) loadY(c0);
+            Acc acc[RG][RL][NT16];
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) {
-                if (jo + cc < ncb)
-                    store_run<T, RL, VEC>(O + lrow + (colbase + jo + cc) * ldo, rvalid, full, acc[cc]);
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int q = 0; q < RL; ++q)
+#pragma unroll
+                    for (int t = 0; t < NT16; ++t) acc[g][q][t] = Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < KS; ++st)
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q)
+#pragma unroll
+                        for (int t = 0; t < NT16; ++t)
+                            acc[g][q][t] = M::op(yv[st][t], xv[st][g][q], acc[g][q][t]);
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+                const int64_t r = row0 + 16 * RL * g + RL * rl;
+#pragma unroll
+                for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int64_t col = c0 + 16 * t + M::mrow(kk, rr);
+                        if (col < cb1) {
+                            T v[RL];
+#pragma unroll
+                            for (int q = 0; q < RL; ++q) v[q] = acc[g][q][t][rr];
+                            store_run<T, RL, VEC>(O + r + col * ldo, m - r, full, v);
+                        }
+                    }
             }
         }
     }
 }
 
 // --------------------------------------------------------------------------
-// tn: O(ncols x n) = X^T * Y, X (R x ncols), Y (R x n), both column-major.
+// tn: O(ncols x n) = X^T * Y with X (R x ncols) and Y (R x n) column-major:
+// a reduction along the contiguous dimension.  TSM2R with a row-major A
+// (X = A^T) and the gradient dB = A^T * dC.
+//
+// D = O tile: S[rl][kk] = X[r, c0 + rl], T[kk][rl] = Y[r, 16 t + rl] with the
+// reduction index r = rb + 4*RL*g + RL*kk + q for step q: lane l loads
+// 16 bytes of X column c0 + rl and of Y column 16 t + rl and feeds element q
+// to step q.  Lane l holds O[c0 + mrow(kk, r), 16 t + rl] in acc[t][r].
+// The WK wavefronts of a workgroup split the workgroup's slice of R, and
+// workgroups split R again; partials are added in double precision in a
+// fixed order (the last workgroup of a column tile to arrive adds them).
 // --------------------------------------------------------------------------
-template <typename T, int NP, int J, bool VEC>
+template <typename T, int NT16, int RG, bool VEC>
 __global__ __launch_bounds__(256) void tn_kernel(
     int64_t R, int64_t ncols, int n, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ O, int64_t ldo,
     int64_t rslice, double* __restrict__ part, unsigned* __restrict__ tickets) {
+    typedef Mfma<T> M;
+    typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
-    constexpr int TR = WAVE * RL;
-    constexpr int WPB = 4;
-    constexpr int CPB = WPB * J;   // output rows (columns of X) per workgroup
+    constexpr int WK = 4;
+    constexpr int RB = 4 * RL * RG;      // rows per wavefront step
+    constexpr int NV = 4 * NT16;         // accumulator values per lane
+    __shared__ double red[WK][WAVE][NV];
 
     const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
-    const int64_t cgroup = blockIdx.x;
-    const int64_t c0 = cgroup * CPB + (int64_t)w * J;
+    const int64_t ctile = blockIdx.x;
+    const int64_t c0 = ctile * 16;
     const int s = blockIdx.y, nsl = gridDim.y;
-    const int64_t rb0 = (int64_t)s * rslice;
-    const int64_t rb1 = (rb0 + rslice < R) ? rb0 + rslice : R;
+    const int64_t sb0 = (int64_t)s * rslice;
+    const int64_t sb1 = (sb0 + rslice < R) ? sb0 + rslice : R;
+    const int64_t lw = rslice / WK;      // multiple of RB
+    const int64_t wb0 = sb0 + w * lw;
+    const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
+    const int64_t xc = c0 + rl;          // this lane's X column
+    const bool xok = xc < ncols;
 
-    T acc[J][NP];
+    Acc acc[NT16];
 #pragma unroll
-    for (int c = 0; c < J; ++c)
-#pragma unroll
-        for (int p = 0; p < NP; ++p) acc[c][p] = T(0);
+    for (int t = 0; t < NT16; ++t) acc[t] = Acc{0, 0, 0, 0};
 
-    for (int64_t r = rb0 + (int64_t)lane * RL; r < rb1 + (int64_t)lane * RL; r += TR) {
-        // every lane runs the same trip count; lanes past rb1 load nothing
-        const int64_t rv = rb1 - r;
-        const bool full = rv >= RL;
-        T y[NP][RL];
+    auto load = [&](int64_t rb, T (&xv)[RG][RL], T (&yv)[RG][NT16][RL]) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (p < n)
-                load_run<T, RL, VEC>(Y + r + p * ldy, rv, full, y[p]);
+        for (int g = 0; g < RG; ++g) {
+            const int64_t r = rb + 4 * RL * g + RL * kk;
+            const int64_t valid = wb1 - r;
+            const bool full = valid >= RL;
+            if (xok)
+                load_run<T, RL, VEC>(X + r + xc * ldx, valid, full, xv[g]);
             else
 #pragma unroll
-                for (int q = 0; q < RL; ++q) y[p][q] = T(0);
+                for (int q = 0; q < RL; ++q) xv[g][q] = T(0);
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                const int p = 16 * t + rl;
+                if (p < n)
+                    load_run<T, RL, VEC>(Y + r + p * ldy, valid, full, yv[g][t]);
+                else
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) yv[g][t][q] = T(0);
+            }
         }
+    };
+
+    if (wb1 > wb0) {
+        const int64_t nst = (wb1 - wb0 + RB - 1) / RB;
+        T xv[RG][RL], yv[RG][NT16][RL];
+        load(wb0, xv, yv);
+        for (int64_t i = 0; i < nst; ++i) {
+            T xn[RG][RL], yn[RG][NT16][RL];
+            if (i + 1 < nst) load(wb0 + (i + 1) * RB, xn, yn);
 #pragma unroll
-        for (int c = 0; c < J; ++c) {
-            T x[RL];
-            if (c0 + c < ncols)
-                load_run<T, RL, VEC>(X + r + (c0 + c) * ldx, rv, full, x);
-            else
+            for (int g = 0; g < RG; ++g)
 #pragma unroll
-                for (int q = 0; q < RL; ++q) x[q] = T(0);
+                for (int q = 0; q < RL; ++q)
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
+                    for (int t = 0; t < NT16; ++t)
+                        acc[t] = M::op(xv[g][q], yv[g][t][q], acc[t]);
 #pragma unroll
-                for (int q = 0; q < RL; ++q) acc[c][p] = __builtin_fma(x[q], y[p][q], acc[c][p]);
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    xv[g][q] = xn[g][q];
+#pragma unroll
+                    for (int t = 0; t < NT16; ++t) yv[g][t][q] = yn[g][t][q];
+                }
         }
     }
 
-    // Butterfly sum over the 64 lanes in double; lane 0's value is used.
-    double tot[J][NP];
+    // Sum the WK wavefronts in wave order (double), then across workgroups.
 #pragma unroll
-    for (int c = 0; c < J; ++c)
+    for (int t = 0; t < NT16; ++t)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            double v = (double)acc[c][p];
+        for (int r = 0; r < 4; ++r) red[w][lane][4 * t + r] = (double)acc[t][r];
+    __syncthreads();
+    // element e of the tile: lane e / NV, value e % NV
+    constexpr int TILE = WAVE * NV;
+    constexpr int PBS = 16 * 16 * NT16;  // partial slots per column tile
+    for (int e = threadIdx.x; e < TILE; e += 256) {
+        const int ln = e / NV, vi = e % NV;
+        double v = red[0][ln][vi];
 #pragma unroll
-            for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-            tot[c][p] = v;
+        for (int ww = 1; ww < WK; ++ww) v += red[ww][ln][vi];
+        const int t = vi / 4, r = vi % 4;
+        const int64_t col = c0 + M::mrow(ln >> 4, r);
+        const int p = 16 * t + (ln & 15);
+        if (nsl == 1) {
+            if (col < ncols && p < n) O[col + p * ldo] = (T)v;
+        } else {
+            part[(ctile * nsl + s) * PBS + e] = v;
         }
-    if (nsl == 1) {
-        if (lane == 0) {
-#pragma unroll
-            for (int c = 0; c < J; ++c)
-#pragma unroll
-                for (int p = 0; p < NP; ++p)
-                    if (c0 + c < ncols && p < n) O[(c0 + c) + p * ldo] = (T)tot[c][p];
-        }
-        return;
     }
-    if (lane == 0) {
-#pragma unroll
-        for (int c = 0; c < J; ++c)
-#pragma unroll
-            for (int p = 0; p < NP; ++p)
-                part[((cgroup * nsl + s) * CPB + w * J + c) * NP + p] = tot[c][p];
-    }
-    if (!take_last_ticket(tickets + cgroup, nsl)) return;
-    for (int e = threadIdx.x; e < CPB * NP; e += 256) {
-        const int cc = e / NP, p = e % NP;
-        const int64_t col = cgroup * CPB + cc;
+    if (nsl == 1) return;
+    if (!take_last_ticket(tickets + ctile, nsl)) return;
+    for (int e = threadIdx.x; e < TILE; e += 256) {
+        const int ln = e / NV, vi = e % NV;
+        const int t = vi / 4, r = vi % 4;
+        const int64_t col = c0 + M::mrow(ln >> 4, r);
+        const int p = 16 * t + (ln & 15);
         if (col < ncols && p < n) {
             double v = 0.0;
-            for (int s2 = 0; s2 < nsl; ++s2) v += part[((cgroup * nsl + s2) * CPB + cc) * NP + p];
+            for (int s2 = 0; s2 < nsl; ++s2) v += part[(ctile * nsl + s2) * PBS + e];
             O[col + p * ldo] = (T)v;
         }
     }
-    rearm_ticket(tickets + cgroup);
+    rearm_ticket(tickets + ctile);
 }
 
 template <typename T>
@@ -441,37 +416,97 @@ __global__ void fill_zero_kernel(int64_t m, int64_t n, T* __restrict__ C, int64_
 // --------------------------------------------------------------------------
 static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-template <typename T>
-static int nn_dispatch(const LaunchNN& L, hipStream_t st) {
-    const int np = L.np;
-    const bool vec = aligned16(L.A) && ((L.lda * (int64_t)sizeof(T)) % 16 == 0);
-    dim3 grid((unsigned)L.tiles, (unsigned)L.S), block(WAVE * 4);
-#define TSM_NN(NPV, UV)                                                                           \
-    if (np == NPV) {                                                                              \
-        if (vec)                                                                                  \
-            hipLaunchKernelGGL((tsm2r_nn_kernel<T, NPV, 4, UV, true>), grid, block, 0, st, L.m,    \
-                               L.k, (int)L.n, (const T*)L.A, L.lda, (const T*)L.B, L.ldb,         \
-                               (T*)L.C, L.ldc, L.kslice, L.part, L.tickets);                      \
-        else                                                                                      \
-            hipLaunchKernelGGL((tsm2r_nn_kernel<T, NPV, 4, UV, false>), grid, block, 0, st, L.m,   \
-                               L.k, (int)L.n, (const T*)L.A, L.lda, (const T*)L.B, L.ldb,         \
-                               (T*)L.C, L.ldc, L.kslice, L.part, L.tickets);                      \
-        return 0;                                                                                 \
+// Resident workgroups per CU of a kernel instance (queried once).
+template <typename K>
+static int occupancy(K kernel, int threads) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
+}
+
+struct NNInstance {
+    const void* fn;
+    int tile_rows;
+    int occ;          // resident workgroups per CU
+};
+
+template <typename T, int NT16, int RG, bool VEC>
+static NNInstance nn_instance() {
+    static const int occ = occupancy(tsm2r_nn_kernel<T, NT16, RG, 4, VEC>, 256);
+    return NNInstance{(const void*)tsm2r_nn_kernel<T, NT16, RG, 4, VEC>,
+                      16 * (16 / (int)sizeof(T)) * RG, occ};
+}
+
+template <bool VEC>
+static bool nn_pick(int dtype, int np, NNInstance* out) {
+    if (dtype == DT_F64) {
+        *out = np <= 16 ? nn_instance<double, 1, 2, VEC>() : nn_instance<double, 2, 2, VEC>();
+        return true;
     }
-    TSM_NN(1, 8)
-    TSM_NN(2, 8)
-    TSM_NN(4, 8)
-    TSM_NN(8, 8)
-    TSM_NN(16, 8)
-    TSM_NN(32, 4)
-#undef TSM_NN
-    return 1;
+    if (dtype == DT_F32) {
+        *out = np <= 16 ? nn_instance<float, 1, 2, VEC>() : nn_instance<float, 2, 2, VEC>();
+        return true;
+    }
+    return false;
+}
+
+static inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P) {
+    // partial sums are stored at the kernel's padded width (16 or 32 columns)
+    const int np = n <= 16 ? 16 : 32;
+    NNInstance I{};
+    if (!(vec ? nn_pick<true>(dtype, np, &I) : nn_pick<false>(dtype, np, &I))) return 1;
+    const int es = dtype == DT_F64 ? 8 : 4;
+    const int WK = 4;
+    P->np = np;
+    P->fn = I.fn;
+    P->tiles = cdiv64(m, I.tile_rows);
+    P->tile_rows = I.tile_rows;
+    // One round of resident workgroups: split k so that tiles * S fills it.
+    const int64_t slots = (int64_t)cus * I.occ;
+    int64_t S = slots / P->tiles;
+    const int64_t s_len = k / (WK * 64);                          // >= 64 columns per wave
+    const int64_t s_cost = (k * es) / ((int64_t)np * 200);         // partials <= ~8 % of A
+    if (S > s_len) S = s_len;
+    if (S > s_cost) S = s_cost;
+    if (P->tiles > MAX_TICKETS) S = 1;
+    if (S < 1) S = 1;
+    const int64_t gran = (int64_t)WK * 16;
+    int64_t ks = cdiv64(k, S);
+    ks = cdiv64(ks, gran) * gran;
+    P->kslice = ks;
+    P->S = (int)cdiv64(k, ks);
+    if (P->S < 1) P->S = 1;
+    P->ws = P->S > 1 ? TICKET_BYTES + (size_t)P->tiles * P->S * np * I.tile_rows * 8 : 0;
+    return 0;
 }
 
 int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
-    if (dtype == DT_F64) return nn_dispatch<double>(L, st);
-    if (dtype == DT_F32) return nn_dispatch<float>(L, st);
-    return 1;
+    (void)dtype;
+    void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&L.n,    (void*)&L.A,
+                    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,
+                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&L.tickets};
+    int n32 = (int)L.n;
+    args[2] = (void*)&n32;
+    hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
+                                   0, st);
+    return e == hipSuccess ? 0 : 1;
+}
+
+template <typename T, int KS, int NT16, int RG>
+static int rowtile_launch(const LaunchRT& L, bool vec, hipStream_t st) {
+    dim3 grid((unsigned)L.blocks_x, (unsigned)L.blocks_y), block(256);
+    if (vec)
+        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, true>), grid, block, 0, st, L.m, L.kin,
+                           L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
+                           (T*)L.O, L.ldo, (int64_t)L.cols_per_block);
+    else
+        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, false>), grid, block, 0, st, L.m,
+                           L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in,
+                           L.ys_out, (T*)L.O, L.ldo, (int64_t)L.cols_per_block);
+    return 0;
 }
 
 template <typename T>
@@ -479,23 +514,12 @@ static int rowtile_dispatch(const LaunchRT& L, hipStream_t st) {
     const bool vec = aligned16(L.X) && aligned16(L.O) &&
                      ((L.ldx * (int64_t)sizeof(T)) % 16 == 0) &&
                      ((L.ldo * (int64_t)sizeof(T)) % 16 == 0);
-    dim3 grid((unsigned)L.blocks_x, (unsigned)L.blocks_y), block(256);
-#define TSM_RT(KPV, NCV)                                                                         \
-    if (L.kp == KPV) {                                                                           \
-        if (vec)                                                                                 \
-            hipLaunchKernelGGL((rowtile_kernel<T, KPV, NCV, true>), grid, block, 0, st, L.m,      \
-                               L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in,      \
-                               L.ys_out, (T*)L.O, L.ldo, L.cols_per_block);                      \
-        else                                                                                     \
-            hipLaunchKernelGGL((rowtile_kernel<T, KPV, NCV, false>), grid, block, 0, st, L.m,     \
-                               L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in,      \
-                               L.ys_out, (T*)L.O, L.ldo, L.cols_per_block);                      \
-        return 0;                                                                                \
+    const bool wide = L.nout > 16;   // two 16-column tiles per pass
+    switch (L.kp) {
+        case 8: return wide ? rowtile_launch<T, 2, 2, 2>(L, vec, st) : rowtile_launch<T, 2, 1, 2>(L, vec, st);
+        case 16: return wide ? rowtile_launch<T, 4, 2, 2>(L, vec, st) : rowtile_launch<T, 4, 1, 2>(L, vec, st);
+        case 32: return wide ? rowtile_launch<T, 8, 2, 1>(L, vec, st) : rowtile_launch<T, 8, 1, 2>(L, vec, st);
     }
-    TSM_RT(8, 8)
-    TSM_RT(16, 8)
-    TSM_RT(32, 4)
-#undef TSM_RT
     return 1;
 }
 
@@ -505,32 +529,26 @@ int launch_rowtile(const LaunchRT& L, int dtype, hipStream_t st) {
     return 1;
 }
 
+template <typename T, int NT16>
+static int tn_launch(const LaunchTN& L, bool vec, hipStream_t st) {
+    dim3 grid((unsigned)L.groups, (unsigned)L.S), block(256);
+    if (vec)
+        hipLaunchKernelGGL((tn_kernel<T, NT16, 2, true>), grid, block, 0, st, L.R, L.ncols,
+                           (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
+                           L.rslice, L.part, L.tickets);
+    else
+        hipLaunchKernelGGL((tn_kernel<T, NT16, 2, false>), grid, block, 0, st, L.R, L.ncols,
+                           (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
+                           L.rslice, L.part, L.tickets);
+    return 0;
+}
+
 template <typename T>
 static int tn_dispatch(const LaunchTN& L, hipStream_t st) {
     const bool vec = aligned16(L.X) && aligned16(L.Y) &&
                      ((L.ldx * (int64_t)sizeof(T)) % 16 == 0) &&
                      ((L.ldy * (int64_t)sizeof(T)) % 16 == 0);
-    dim3 grid((unsigned)L.groups, (unsigned)L.S), block(256);
-#define TSM_TN(NPV, JV)                                                                          \
-    if (L.np == NPV) {                                                                           \
-        if (vec)                                                                                 \
-            hipLaunchKernelGGL((tn_kernel<T, NPV, JV, true>), grid, block, 0, st, L.R, L.ncols,   \
-                               (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,    \
-                               L.ldo, L.rslice, L.part, L.tickets);                              \
-        else                                                                                     \
-            hipLaunchKernelGGL((tn_kernel<T, NPV, JV, false>), grid, block, 0, st, L.R, L.ncols,  \
-                               (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,    \
-                               L.ldo, L.rslice, L.part, L.tickets);                              \
-        return 0;                                                                                \
-    }
-    TSM_TN(1, TN_J(1))
-    TSM_TN(2, TN_J(2))
-    TSM_TN(4, TN_J(4))
-    TSM_TN(8, TN_J(8))
-    TSM_TN(16, TN_J(16))
-    TSM_TN(32, TN_J(32))
-#undef TSM_TN
-    return 1;
+    return L.n <= 16 ? tn_launch<T, 1>(L, vec, st) : tn_launch<T, 2>(L, vec, st);
 }
 
 int launch_tn(const LaunchTN& L, int dtype, hipStream_t st) {

@@ -1,0 +1,721 @@
+// Low-precision storage form of A for TSM2R on gfx950.
+//
+//  split_kernel   hi = RNE(a), lo = RNE(a - hi) for a float matrix A, written
+//                 as bfloat16 or binary16 planes (a - hi is exact in float).
+//
+//  tsm2r_lp       C = A*B with A given by its hi plane (single form) or its
+//                 hi and lo planes (split form, value hi + lo), B and C float.
+//                 The bulk arithmetic runs on the 16x16x32 bf16/f16 matrix
+//                 cores with float accumulation; the per-workgroup and
+//                 cross-workgroup sums are double, as in the float kernels.
+//
+// Dataflow (same outer-product form as the float TSM2R kernel): C^T = B^T*A^T
+// with the MFMA "S" operand a 16 x 32 block of B^T and the "T" operand a
+// 32 x 16 block of A^T.  The T operand wants, per lane, eight consecutive
+// k values of ONE row, but a column-major A is contiguous along rows; a lane
+// therefore loads 16 bytes (8 rows) from each of 8 columns j0 + 8*kk + i,
+// and transposes that 8 x 8 block of 16-bit values in registers (one byte
+// permute per output dword) so that MFMA instance q gets row 8*rl + q.
+// Every element of A is still loaded exactly once with 16-byte loads.
+//
+// B is float; it is split in the kernel into bf16/f16 terms B1 + B2 + B3
+// (b1 = RNE(b), b2 = RNE(b - b1), b3 = RNE(b - b1 - b2), each difference
+// exact in float), which reproduce a float B.  Products kept:
+//   single:  hi*(B1 + B2)
+//   split:   hi*(B1 + B2 + B3) + lo*(B1 + B2)
+// The dropped terms are below 2^-24 of |a||b| (bf16 storage) and the
+// arithmetic error is that of float accumulation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tsm2x_device.h"
+#include "tsm2x_internal.h"
+
+namespace tsm {
+
+enum { FMT_BF16 = 0, FMT_F16 = 1 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even of a float to the 16-bit format, as its bit pattern.
+template <int FMT>
+__device__ __forceinline__ uint32_t rne16(float x) {
+    if (FMT == FMT_BF16) {
+        uint32_t u = __float_as_uint(x);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // NaN stays NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return u >> 16;
+    } else {
+        _Float16 h = (_Float16)x;                                       // v_cvt_f16_f32, RNE
+        return (uint32_t)__builtin_bit_cast(uint16_t, h);
+    }
+}
+
+template <int FMT>
+__device__ __forceinline__ float val16(uint32_t h) {
+    if (FMT == FMT_BF16) return __uint_as_float(h << 16);
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+template <int FMT>
+__device__ __forceinline__ f32x4 mfma32(u32x4 s, u32x4 t, f32x4 d) {
+    if (FMT == FMT_BF16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, s),
+                                                       __builtin_bit_cast(bf16x8, t), d, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, s),
+                                                  __builtin_bit_cast(f16x8, t), d, 0, 0, 0);
+}
+
+// --------------------------------------------------------------------------
+// split
+// --------------------------------------------------------------------------
+template <int FMT, bool LO, bool VEC>
+__global__ __launch_bounds__(256) void split_kernel(int64_t m, int64_t k,
+                                                    const float* __restrict__ A, int64_t lda,
+                                                    uint16_t* __restrict__ hi,
+                                                    uint16_t* __restrict__ lo, int64_t ldh) {
+    const int64_t chunks = (m + 7) / 8;
+    const int64_t total = chunks * k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / chunks, i0 = (e % chunks) * 8;
+        const float* src = A + i0 + j * lda;
+        const int64_t valid = m - i0;
+        float a[8];
+        if (VEC && valid >= 8) {
+            const f32x4 v0 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+            const f32x4 v1 = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src) + 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = v0[q];
+                a[4 + q] = v1[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[q] = q < valid ? src[q] : 0.f;
+        }
+        uint32_t h[8], l[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            h[q] = rne16<FMT>(a[q]);
+            const float hv = val16<FMT>(h[q]);
+            // a - hi is exact; a non-finite hi (overflow, NaN) is carried on
+            l[q] = rne16<FMT>(__builtin_isfinite(hv) ? a[q] - hv : hv);
+        }
+        uint16_t* dh = hi + i0 + j * ldh;
+        uint16_t* dl = LO ? lo + i0 + j * ldh : nullptr;
+        if (VEC && valid >= 8) {
+            u32x4 vh, vl;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                vh[d] = h[2 * d] | (h[2 * d + 1] << 16);
+                vl[d] = l[2 * d] | (l[2 * d + 1] << 16);
+            }
+            __builtin_nontemporal_store(vh, reinterpret_cast<u32x4*>(dh));
+            if (LO) __builtin_nontemporal_store(vl, reinterpret_cast<u32x4*>(dl));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < valid) {
+                    dh[q] = (uint16_t)h[q];
+                    if (LO) dl[q] = (uint16_t)l[q];
+                }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// tsm2r_lp
+// --------------------------------------------------------------------------
+// 8 consecutive 16-bit values as 4 dwords (value 2d in the low half of d).
+template <bool VEC>
+__device__ __forceinline__ void load8h(const uint16_t* __restrict__ p, int64_t valid, bool full,
+                                       uint32_t (&d)[4]) {
+    if (VEC && full) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] = v[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t x0 = (2 * e < valid) ? p[2 * e] : 0u;
+            const uint32_t x1 = (2 * e + 1 < valid) ? p[2 * e + 1] : 0u;
+            d[e] = x0 | (x1 << 16);
+        }
+    }
+}
+
+template <int FMT, int NT16, bool SPLIT, int WK, bool VEC>
+__global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
+    int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
+    const uint16_t* __restrict__ Al, int64_t lda, const float* __restrict__ B, int64_t ldb,
+    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part,
+    unsigned* __restrict__ tickets) {
+    constexpr int TR = 128;              // 16 lanes x 8 rows
+    constexpr int NP = 16 * NT16;
+    constexpr int PG = 4;
+    constexpr int NPL = SPLIT ? 2 : 1;   // planes
+    constexpr int NBT = SPLIT ? 3 : 2;   // B terms
+    __shared__ __align__(16) unsigned char smem[WK * PG * TR * 8];
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & 15, kk = lane >> 4;
+    const int w = threadIdx.x / WAVE;
+    const int64_t tile = blockIdx.x;
+    const int s = blockIdx.y, nsl = gridDim.y;
+    const int64_t row0 = tile * TR;
+    const int64_t r = row0 + 8 * rl;     // this lane's 8 rows
+    const bool full = (row0 + TR <= m);
+    const int64_t kb0 = (int64_t)s * kslice;
+    const int64_t kb1 = (kb0 + kslice < k) ? kb0 + kslice : k;
+    const int64_t lw = kslice / WK;
+    const int64_t wk0 = kb0 + w * lw;
+    const int64_t wk1 = (wk0 + lw < kb1) ? wk0 + lw : kb1;
+
+    f32x4 acc[8][NT16];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // raw[pl][i][d]: plane pl, column j0 + 8 kk + i, rows r + 2d, r + 2d + 1
+    auto loadA = [&](int64_t j0, uint32_t (&raw)[NPL][8][4]) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t j = j0 + 8 * kk + i;
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) {
+                const uint16_t* P = pl == 0 ? Ah : Al;
+                if (j < wk1)
+                    load8h<VEC>(P + r + j * lda, m - r, full, raw[pl][i]);
+                else
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) raw[pl][i][d] = 0u;
+            }
+        }
+    };
+    auto loadB = [&](int64_t j0, float (&bv)[NT16][8]) {
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) {
+            const int p = 16 * t + rl;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t j = j0 + 8 * kk + i;
+                bv[t][i] = (p < n && j < wk1) ? B[j + p * ldb] : 0.f;
+            }
+        }
+    };
+
+    if (wk1 > wk0) {
+        const int ng = (int)((wk1 - wk0 + 31) / 32);
+        uint32_t raw[NPL][8][4];
+        float bv[NT16][8];
+        loadA(wk0, raw);
+        loadB(wk0, bv);
+        for (int g = 0; g < ng; ++g) {
+            uint32_t rawn[NPL][8][4];
+            float bn[NT16][8];
+            if (g + 1 < ng) {
+                loadA(wk0 + 32 * (g + 1), rawn);
+                loadB(wk0 + 32 * (g + 1), bn);
+            }
+            // B terms, packed as the S operand: dword e holds k = 2e, 2e + 1
+            u32x4 bt[NT16][NBT];
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                uint32_t h[NBT][8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    float res = bv[t][i];
+#pragma unroll
+                    for (int c = 0; c < NBT; ++c) {
+                        h[c][i] = rne16<FMT>(res);
+                        res = res - val16<FMT>(h[c][i]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NBT; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) bt[t][c][e] = h[c][2 * e] | (h[c][2 * e + 1] << 16);
+            }
+            // 8 x 8 transpose of each plane: instance q gets row r + q
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                u32x4 tq[NPL];
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t lo = raw[pl][2 * e][q / 2];
+                        const uint32_t hi = raw[pl][2 * e + 1][q / 2];
+                        tq[pl][e] = (q & 1) ? ((lo >> 16) | (hi & 0xffff0000u))
+                                            : ((lo & 0xffffu) | (hi << 16));
+                    }
+#pragma unroll
+                for (int t = 0; t < NT16; ++t) {
+#pragma unroll
+                    for (int c = 0; c < NBT; ++c) acc[q][t] = mfma32<FMT>(bt[t][c], tq[0], acc[q][t]);
+                    if (SPLIT) {
+                        acc[q][t] = mfma32<FMT>(bt[t][0], tq[NPL - 1], acc[q][t]);
+                        acc[q][t] = mfma32<FMT>(bt[t][1], tq[NPL - 1], acc[q][t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) raw[pl][i][d] = rawn[pl][i][d];
+#pragma unroll
+            for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bv[t][i] = bn[t][i];
+        }
+    }
+
+    // lane holds C[r + q, 16 t + 4 kk + rr] in acc[q][t][rr]
+    nn_finish<float, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part, tickets,
+                                     reinterpret_cast<double*>(smem), [&](int pg, double* red) {
+        const int t = pg / 16;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int pp = 16 * t + Mfma<float>::mrow(kk, rr) - pg;
+            if (pp >= 0 && pp < PG) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    red[(w * PG + pp) * TR + 8 * rl + q] = (double)acc[q][t][rr];
+            }
+        }
+    });
+}
+
+// Bit patterns of the NBT terms of eight float values, packed two per dword
+// (value 2e in the low half of dword e): the MFMA operand layout.
+template <int FMT, int NBT>
+__device__ __forceinline__ void split_terms8(const float (&v)[8], u32x4 (&out)[NBT]) {
+    uint32_t h[NBT][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float res = v[i];
+#pragma unroll
+        for (int c = 0; c < NBT; ++c) {
+            h[c][i] = rne16<FMT>(res);
+            res = res - val16<FMT>(h[c][i]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NBT; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[c][e] = h[c][2 * e] | (h[c][2 * e + 1] << 16);
+}
+
+// --------------------------------------------------------------------------
+// tsm2l_lp: C = A*B with A tall (m x k, k <= 32) in the low-precision form,
+// B (k x n, n <= 32) and C float.  TSM2L (Algorithm 6) on the matrix cores:
+// B's terms are built once per wavefront and stay in registers; a
+// persistent grid walks 128-row tiles, each lane loading its 8 rows of every
+// column (8 x 16 bytes per plane), transposing them as in tsm2r_lp, and
+// writing its 8 rows of each output column with 32-byte stores.
+// --------------------------------------------------------------------------
+template <int FMT, int NT16, bool SPLIT, bool VEC>
+__global__ __launch_bounds__(256) void tsm2l_lp_kernel(
+    int64_t m, int k, int n, const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
+    int64_t lda, const float* __restrict__ B, int64_t ldb, float* __restrict__ C, int64_t ldc) {
+    constexpr int TR = 128;
+    constexpr int WPB = 4;
+    constexpr int NPL = SPLIT ? 2 : 1;
+    constexpr int NBT = SPLIT ? 3 : 2;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & 15, kk = lane >> 4;
+    const int w = threadIdx.x / WAVE;
+
+    u32x4 bt[NT16][NBT];
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) {
+        float bv[8];
+        const int p = 16 * t + rl;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = 8 * kk + i;
+            bv[i] = (p < n && j < k) ? B[j + p * ldb] : 0.f;
+        }
+        split_terms8<FMT, NBT>(bv, bt[t]);
+    }
+
+    const int64_t ntiles = (m + TR - 1) / TR;
+    for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles;
+         tile += (int64_t)gridDim.x * WPB) {
+        const int64_t r = tile * TR + 8 * rl;
+        const bool full = (tile * TR + TR <= m);
+        uint32_t raw[NPL][8][4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = 8 * kk + i;
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) {
+                const uint16_t* P = pl == 0 ? Ah : Al;
+                if (j < k)
+                    load8h<VEC>(P + r + j * lda, m - r, full, raw[pl][i]);
+                else
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) raw[pl][i][d] = 0u;
+            }
+        }
+        f32x4 acc[8][NT16];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            u32x4 tq[NPL];
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t lo = raw[pl][2 * e][q / 2];
+                    const uint32_t hi = raw[pl][2 * e + 1][q / 2];
+                    tq[pl][e] = (q & 1) ? ((lo >> 16) | (hi & 0xffff0000u))
+                                        : ((lo & 0xffffu) | (hi << 16));
+                }
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < NBT; ++c) acc[q][t] = mfma32<FMT>(bt[t][c], tq[0], acc[q][t]);
+                if (SPLIT) {
+                    acc[q][t] = mfma32<FMT>(bt[t][0], tq[NPL - 1], acc[q][t]);
+                    acc[q][t] = mfma32<FMT>(bt[t][1], tq[NPL - 1], acc[q][t]);
+                }
+            }
+        }
+        // acc[q][t][rr] = C[r + q, 16 t + mrow(kk, rr)]: rows r .. r+7 of a column
+#pragma unroll
+        for (int t = 0; t < NT16; ++t)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int col = 16 * t + Mfma<float>::mrow(kk, rr);
+                if (col < n) {
+                    float v0[4], v1[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        v0[q] = acc[q][t][rr];
+                        v1[q] = acc[4 + q][t][rr];
+                    }
+                    store_run<float, 4, VEC>(C + r + col * ldc, m - r, full, v0);
+                    store_run<float, 4, VEC>(C + r + 4 + col * ldc, m - r - 4, full, v1);
+                }
+            }
+    }
+}
+
+// --------------------------------------------------------------------------
+// tn_lp: O(ncols x n) = X^T * Y with X (R x ncols) in the low-precision form
+// and Y (R x n) float: the gradient dB = A^T * dC of the low-precision form.
+// The reduction runs along X's columns, so a lane's 16-byte load of 8
+// consecutive rows of one X column is already the MFMA operand (no
+// transpose): S[rl][8 kk + i] = X[rb + 8 kk + i, c0 + rl] and
+// T[8 kk + i][rl] = Yterm[rb + 8 kk + i, 16 t + rl].  Products kept:
+// hi*(Y1 + Y2 + Y3) + lo*(Y1 + Y2) (split) or hi*(Y1 + Y2) (single).
+// Reduction across wavefronts and workgroups as in tn_kernel.
+// --------------------------------------------------------------------------
+template <int FMT, int NT16, bool SPLIT, bool VEC>
+__global__ __launch_bounds__(256) void tn_lp_kernel(
+    int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
+    const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
+    float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part,
+    unsigned* __restrict__ tickets) {
+    constexpr int WK = 4;
+    constexpr int RG = 2;
+    constexpr int RB = 32 * RG;          // rows per wavefront step
+    constexpr int NPL = SPLIT ? 2 : 1;
+    constexpr int NBT = SPLIT ? 3 : 2;
+    constexpr int NV = 4 * NT16;
+    __shared__ double red[WK][WAVE][NV];
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & 15, kk = lane >> 4;
+    const int w = threadIdx.x / WAVE;
+    const int64_t ctile = blockIdx.x;
+    const int64_t c0 = ctile * 16;
+    const int s = blockIdx.y, nsl = gridDim.y;
+    const int64_t sb0 = (int64_t)s * rslice;
+    const int64_t sb1 = (sb0 + rslice < R) ? sb0 + rslice : R;
+    const int64_t lw = rslice / WK;
+    const int64_t wb0 = sb0 + w * lw;
+    const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
+    const int64_t xc = c0 + rl;
+    const bool xok = xc < ncols;
+
+    f32x4 acc[NT16];
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    auto load = [&](int64_t rb, uint32_t (&xv)[RG][NPL][4], float (&yv)[RG][NT16][8]) {
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+            const int64_t r = rb + 32 * g + 8 * kk;
+            const int64_t valid = wb1 - r;
+            const bool full = valid >= 8;
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) {
+                const uint16_t* P = pl == 0 ? Xh : Xl;
+                if (xok)
+                    load8h<VEC>(P + r + xc * ldx, valid, full, xv[g][pl]);
+                else
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) xv[g][pl][d] = 0u;
+            }
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                const int p = 16 * t + rl;
+                if (p < n) {
+                    load_run<float, 4, VEC>(Y + r + p * ldy, valid, full,
+                                            *reinterpret_cast<float(*)[4]>(&yv[g][t][0]));
+                    load_run<float, 4, VEC>(Y + r + 4 + p * ldy, valid - 4, full,
+                                            *reinterpret_cast<float(*)[4]>(&yv[g][t][4]));
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) yv[g][t][i] = 0.f;
+                }
+            }
+        }
+    };
+
+    if (wb1 > wb0) {
+        const int64_t nst = (wb1 - wb0 + RB - 1) / RB;
+        uint32_t xv[RG][NPL][4];
+        float yv[RG][NT16][8];
+        load(wb0, xv, yv);
+        for (int64_t it = 0; it < nst; ++it) {
+            uint32_t xn[RG][NPL][4];
+            float yn[RG][NT16][8];
+            if (it + 1 < nst) load(wb0 + (it + 1) * RB, xn, yn);
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int t = 0; t < NT16; ++t) {
+                    u32x4 yt[NBT];
+                    split_terms8<FMT, NBT>(yv[g][t], yt);
+                    u32x4 x0{xv[g][0][0], xv[g][0][1], xv[g][0][2], xv[g][0][3]};
+#pragma unroll
+                    for (int c = 0; c < NBT; ++c) acc[t] = mfma32<FMT>(x0, yt[c], acc[t]);
+                    if (SPLIT) {
+                        u32x4 x1{xv[g][NPL - 1][0], xv[g][NPL - 1][1], xv[g][NPL - 1][2],
+                                 xv[g][NPL - 1][3]};
+                        acc[t] = mfma32<FMT>(x1, yt[0], acc[t]);
+                        acc[t] = mfma32<FMT>(x1, yt[1], acc[t]);
+                    }
+                }
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) xv[g][pl][d] = xn[g][pl][d];
+#pragma unroll
+                for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) yv[g][t][i] = yn[g][t][i];
+            }
+        }
+    }
+
+#pragma unroll
+    for (int t = 0; t < NT16; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[w][lane][4 * t + r] = (double)acc[t][r];
+    __syncthreads();
+    constexpr int TILE = WAVE * NV;
+    constexpr int PBS = 16 * 16 * NT16;
+    for (int e = threadIdx.x; e < TILE; e += 256) {
+        const int ln = e / NV, vi = e % NV;
+        double v = red[0][ln][vi];
+#pragma unroll
+        for (int ww = 1; ww < WK; ++ww) v += red[ww][ln][vi];
+        const int t = vi / 4, r = vi % 4;
+        const int64_t col = c0 + Mfma<float>::mrow(ln >> 4, r);
+        const int p = 16 * t + (ln & 15);
+        if (nsl == 1) {
+            if (col < ncols && p < n) O[col + p * ldo] = (float)v;
+        } else {
+            part[(ctile * nsl + s) * PBS + e] = v;
+        }
+    }
+    if (nsl == 1) return;
+    if (!take_last_ticket(tickets + ctile, nsl)) return;
+    for (int e = threadIdx.x; e < TILE; e += 256) {
+        const int ln = e / NV, vi = e % NV;
+        const int t = vi / 4, r = vi % 4;
+        const int64_t col = c0 + Mfma<float>::mrow(ln >> 4, r);
+        const int p = 16 * t + (ln & 15);
+        if (col < ncols && p < n) {
+            double v = 0.0;
+            for (int s2 = 0; s2 < nsl; ++s2) v += part[(ctile * nsl + s2) * PBS + e];
+            O[col + p * ldo] = (float)v;
+        }
+    }
+    rearm_ticket(tickets + ctile);
+}
+
+// --------------------------------------------------------------------------
+// plans and launches
+// --------------------------------------------------------------------------
+template <typename K>
+static int lp_occupancy(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
+}
+
+template <int FMT, int NT16, bool SPLIT, bool VEC>
+static const void* lp_fn(int* occ) {
+    static const int o = lp_occupancy(tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC>);
+    *occ = o;
+    return (const void*)tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC>;
+}
+
+template <bool VEC>
+static const void* lp_pick(int fmt, bool split, int nt16, int* occ) {
+    if (fmt == FMT_BF16) {
+        if (split) return nt16 == 1 ? lp_fn<FMT_BF16, 1, true, VEC>(occ) : lp_fn<FMT_BF16, 2, true, VEC>(occ);
+        return nt16 == 1 ? lp_fn<FMT_BF16, 1, false, VEC>(occ) : lp_fn<FMT_BF16, 2, false, VEC>(occ);
+    }
+    if (split) return nt16 == 1 ? lp_fn<FMT_F16, 1, true, VEC>(occ) : lp_fn<FMT_F16, 2, true, VEC>(occ);
+    return nt16 == 1 ? lp_fn<FMT_F16, 1, false, VEC>(occ) : lp_fn<FMT_F16, 2, false, VEC>(occ);
+}
+
+static inline int64_t cdiv_lp(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P) {
+    const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
+    const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
+    const int nt16 = n <= 16 ? 1 : 2;
+    int occ = 1;
+    P->fn = vec ? lp_pick<true>(fmt, split, nt16, &occ) : lp_pick<false>(fmt, split, nt16, &occ);
+    const int WK = 4, TR = 128;
+    const int es = split ? 4 : 2;
+    P->np = 16 * nt16;
+    P->tile_rows = TR;
+    P->tiles = cdiv_lp(m, TR);
+    const int64_t slots = (int64_t)cus * occ;
+    int64_t S = slots / P->tiles;
+    const int64_t s_len = k / (WK * 64);
+    const int64_t s_cost = (k * es) / ((int64_t)P->np * 200);
+    if (S > s_len) S = s_len;
+    if (S > s_cost) S = s_cost;
+    if (P->tiles > MAX_TICKETS) S = 1;
+    if (S < 1) S = 1;
+    const int64_t gran = (int64_t)WK * 32;
+    int64_t ks = cdiv_lp(k, S);
+    ks = cdiv_lp(ks, gran) * gran;
+    P->kslice = ks;
+    P->S = (int)cdiv_lp(k, ks);
+    if (P->S < 1) P->S = 1;
+    P->ws = P->S > 1 ? TICKET_BYTES + (size_t)P->tiles * P->S * P->np * TR * 8 : 0;
+    return 0;
+}
+
+int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st) {
+    const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
+    const uint16_t* ah = (const uint16_t*)L.A;
+    const uint16_t* al = split ? ah + L.lda * L.k : nullptr;
+    int n32 = (int)L.n;
+    void* args[] = {(void*)&L.m,   (void*)&L.k,   (void*)&n32,      (void*)&ah,
+                    (void*)&al,    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,
+                    (void*)&L.C,   (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part,
+                    (void*)&L.tickets};
+    hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
+                                   0, st);
+    return e == hipSuccess ? 0 : 1;
+}
+
+int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
+                    int64_t ldb, float* C, int64_t ldc, int dtype, int64_t blocks,
+                    hipStream_t st) {
+    const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
+    const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
+    const bool vec = ((uintptr_t)A & 15u) == 0 && (lda % 8) == 0 && ((uintptr_t)C & 15u) == 0 &&
+                     (ldc % 4) == 0;
+    const uint16_t* ah = (const uint16_t*)A;
+    const uint16_t* al = split ? ah + lda * k : nullptr;
+    dim3 g((unsigned)blocks), b(256);
+    const int ki = (int)k, ni = (int)n;
+#define TSM_L(F, NT, SP)                                                                          \
+    {                                                                                             \
+        if (vec)                                                                                  \
+            hipLaunchKernelGGL((tsm2l_lp_kernel<F, NT, SP, true>), g, b, 0, st, m, ki, ni, ah, al, \
+                               lda, B, ldb, C, ldc);                                              \
+        else                                                                                      \
+            hipLaunchKernelGGL((tsm2l_lp_kernel<F, NT, SP, false>), g, b, 0, st, m, ki, ni, ah,    \
+                               al, lda, B, ldb, C, ldc);                                          \
+        return 0;                                                                                 \
+    }
+    if (fmt == FMT_BF16) {
+        if (split) { if (n <= 16) TSM_L(FMT_BF16, 1, true) else TSM_L(FMT_BF16, 2, true) }
+        else { if (n <= 16) TSM_L(FMT_BF16, 1, false) else TSM_L(FMT_BF16, 2, false) }
+    } else {
+        if (split) { if (n <= 16) TSM_L(FMT_F16, 1, true) else TSM_L(FMT_F16, 2, true) }
+        else { if (n <= 16) TSM_L(FMT_F16, 1, false) else TSM_L(FMT_F16, 2, false) }
+    }
+#undef TSM_L
+    return 1;
+}
+
+int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st) {
+    const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
+    const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
+    const bool vec = ((uintptr_t)L.X & 15u) == 0 && (L.ldx % 8) == 0 &&
+                     ((uintptr_t)L.Y & 15u) == 0 && (L.ldy % 4) == 0;
+    const uint16_t* xh = (const uint16_t*)L.X;
+    const uint16_t* xl = split ? xh + L.ldx * L.ncols : nullptr;
+    dim3 g((unsigned)L.groups, (unsigned)L.S), b(256);
+    const int ni = (int)L.n;
+#define TSM_T(F, NT, SP)                                                                          \
+    {                                                                                             \
+        if (vec)                                                                                  \
+            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, true>), g, b, 0, st, L.R, L.ncols, ni, xh,  \
+                               xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo, L.rslice, \
+                               L.part, L.tickets);                                                \
+        else                                                                                      \
+            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, false>), g, b, 0, st, L.R, L.ncols, ni,     \
+                               xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,       \
+                               L.rslice, L.part, L.tickets);                                      \
+        return 0;                                                                                 \
+    }
+    if (fmt == FMT_BF16) {
+        if (split) { if (L.n <= 16) TSM_T(FMT_BF16, 1, true) else TSM_T(FMT_BF16, 2, true) }
+        else { if (L.n <= 16) TSM_T(FMT_BF16, 1, false) else TSM_T(FMT_BF16, 2, false) }
+    } else {
+        if (split) { if (L.n <= 16) TSM_T(FMT_F16, 1, true) else TSM_T(FMT_F16, 2, true) }
+        else { if (L.n <= 16) TSM_T(FMT_F16, 1, false) else TSM_T(FMT_F16, 2, false) }
+    }
+#undef TSM_T
+    return 1;
+}
+
+int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
+                 int64_t ldh, int fmt, hipStream_t st) {
+    const bool vec = ((uintptr_t)A & 15u) == 0 && (lda % 4) == 0 && ((uintptr_t)hi & 15u) == 0 &&
+                     (!lo || ((uintptr_t)lo & 15u) == 0) && (ldh % 8) == 0;
+    const int64_t total = cdiv_lp(m, 8) * k;
+    int64_t blocks = cdiv_lp(total, 256);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    dim3 g((unsigned)blocks), b(256);
+    uint16_t* h = (uint16_t*)hi;
+    uint16_t* l = (uint16_t*)lo;
+#define TSM_SPLIT(F, LO, V) \
+    hipLaunchKernelGGL((split_kernel<F, LO, V>), g, b, 0, st, m, k, A, lda, h, l, ldh)
+    if (fmt == FMT_BF16) {
+        if (lo) { if (vec) TSM_SPLIT(FMT_BF16, true, true); else TSM_SPLIT(FMT_BF16, true, false); }
+        else { if (vec) TSM_SPLIT(FMT_BF16, false, true); else TSM_SPLIT(FMT_BF16, false, false); }
+    } else {
+        if (lo) { if (vec) TSM_SPLIT(FMT_F16, true, true); else TSM_SPLIT(FMT_F16, true, false); }
+        else { if (vec) TSM_SPLIT(FMT_F16, false, true); else TSM_SPLIT(FMT_F16, false, false); }
+    }
+#undef TSM_SPLIT
+    return 0;
+}
+
+}  // namespace tsm

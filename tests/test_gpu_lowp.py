@@ -1,0 +1,121 @@
+"""Precision form: the split kernel against the oracle's split (bit-exact),
+and TSM2R on bf16/f16 hi(+lo) planes against the FP64 oracle on the stored
+values (arithmetic error) and on the float values (total error)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2002_03258_amd as tsm
+import seeded_inputs as si
+
+from helpers import dev_matrix, err, host_matrix, host_rows, sample_rows, to_np
+
+pytestmark = pytest.mark.gpu
+
+FMTS = [("bf16", oracle.BF16), ("f16", oracle.F16)]
+# normwise error bounds against the oracle on the stored values hi (+ lo):
+# float accumulation plus the dropped B terms
+TOL_STORED = 1e-5
+# against the float A: the storage error of the form
+TOL_VALUE = {("bf16", False): 4e-3, ("f16", False): 5e-4, ("bf16", True): 2e-5,
+             ("f16", True): 2e-5}
+
+
+def _planes_np(S):
+    hi = S.hi.contiguous().view(torch.int16).cpu().numpy().view(np.uint16)
+    lo = S.lo.contiguous().view(torch.int16).cpu().numpy().view(np.uint16) if S.has_lo else None
+    return hi, lo
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("m,k", [(1, 1), (37, 5), (1000, 333), (4099, 64)])
+def test_split_matches_oracle(dev, fmt, code, m, k):
+    A = dev_matrix(10 + m, si.STREAM_A, m, k, torch.float32, dev)
+    if m > 10:   # magnitudes from tiny to large, and specials
+        A[3, 0] = float("nan")
+        A[4, 0] = float("inf")
+        A[5, 0] = -0.0
+        A[6, 0] = 1e-30
+        A[7, 0] = 3.0e4 if fmt == "f16" else 3.0e38
+        A[8, 0] = 2.0 ** -20
+    S = tsm.split(A, fmt, lo=True)
+    hi, lo = _planes_np(S)
+    Ah = A.cpu().numpy()
+    rhi, rlo = oracle.split(np.asfortranarray(Ah), code)
+    assert np.array_equal(hi, rhi)
+    assert np.array_equal(lo, rlo)
+    S1 = tsm.split(A, fmt, lo=False)
+    assert S1.lo is None and torch.equal(S1.hi.contiguous(), S.hi.contiguous())
+
+
+def _stored_value(A32_np, code, with_lo):
+    hi, lo = oracle.split(np.asfortranarray(A32_np.astype(np.float32)), code)
+    v = oracle.decode_plane(hi, code)
+    if with_lo:
+        v = v + oracle.decode_plane(lo, code)
+    return v
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("with_lo", [False, True])
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (7, 5, 3), (300, 1000, 16), (1000, 3000, 32),
+                                   (4133, 2500, 8), (255, 4097, 17), (2048, 777, 12)])
+def test_tsm2r_lowp_small(dev, fmt, code, with_lo, m, k, n):
+    seed = 500 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, torch.float32, dev)
+    B = dev_matrix(seed, si.STREAM_B, k, n, torch.float32, dev)
+    C = tsm.tsm2r(tsm.split(A, fmt, lo=with_lo), B)
+    Ah = host_matrix(seed, si.STREAM_A, m, k, torch.float32)
+    Bh = host_matrix(seed, si.STREAM_B, k, n, torch.float32)
+    ref_stored = oracle.matmul(_stored_value(Ah, code, with_lo), Bh)
+    ref_value = oracle.matmul(Ah, Bh)
+    e_s, e_v = err(to_np(C), ref_stored), err(to_np(C), ref_value)
+    assert e_s <= TOL_STORED, (e_s, e_v)
+    assert e_v <= TOL_VALUE[(fmt, with_lo)], (e_s, e_v)
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+def test_tsm2r_lowp_integer_bit_exact(dev, fmt, code):
+    """Integer A with |a| <= 64 and B with |b| <= 8 are exact in both formats
+    (lo = 0, B = B1) and k*64*8 < 2^24 keeps float accumulation exact."""
+    m, k, n = 2000, 4096, 16
+    A = dev_matrix(7, si.STREAM_A, m, k, torch.float32, dev, dist="int", r=64)
+    B = dev_matrix(7, si.STREAM_B, k, n, torch.float32, dev, dist="int", r=8)
+    for with_lo in (False, True):
+        C = to_np(tsm.tsm2r(tsm.split(A, fmt, lo=with_lo), B))
+        ref = oracle.matmul(host_matrix(7, si.STREAM_A, m, k, torch.float32, dist="int", r=64),
+                            host_matrix(7, si.STREAM_B, k, n, torch.float32, dist="int", r=8))
+        assert np.array_equal(C, ref)
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+def test_tsm2r_lowp_deterministic(dev, fmt, code):
+    A = dev_matrix(8, si.STREAM_A, 3000, 20000, torch.float32, dev)
+    B = dev_matrix(8, si.STREAM_B, 20000, 32, torch.float32, dev)
+    S = tsm.split(A, fmt)
+    assert torch.equal(tsm.tsm2r(S, B).clone(), tsm.tsm2r(S, B))
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+def test_tsm2r_lowp_full_size_sampled(dev, fmt, code):
+    """A 32768 x 32768 stored single and split, B 32768 x n, n in {8, 16, 32}."""
+    seed = si.config_seed(3)
+    m = k = 32768
+    A = dev_matrix(seed, si.STREAM_A, m, k, torch.float32, dev)
+    rows = sample_rows(m, 24, seed=3)
+    Ar = host_rows(seed, si.STREAM_A, m, k, rows, torch.float32)
+    for with_lo in (False, True):
+        S = tsm.split(A, fmt, lo=with_lo)
+        stored = _stored_value(Ar, code, with_lo)
+        for n in (8, 16, 32):
+            B = dev_matrix(seed + n, si.STREAM_B, k, n, torch.float32, dev)
+            Bh = host_matrix(seed + n, si.STREAM_B, k, n, torch.float32)
+            Cs = to_np(tsm.tsm2r(S, B)[rows])
+            e_s = err(Cs, oracle.matmul(stored, Bh))
+            e_v = err(Cs, oracle.matmul(Ar, Bh))
+            print(fmt, "split" if with_lo else "single", n, "err stored %.2e value %.2e" % (e_s, e_v))
+            assert e_s <= TOL_STORED and e_v <= TOL_VALUE[(fmt, with_lo)]
+        del S
+    del A
+    torch.cuda.empty_cache()

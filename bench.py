@@ -74,6 +74,7 @@ def make_r_inputs(dev):
                 B = si.matrix(seed + n, si.STREAM_B, m, n, dtype=dtype, device=dev)
                 C = tsm.empty_colmajor(m, n, dtype, dev)
                 calls.append(dict(dtype=dtype, m=m, k=m, n=n, A=A, B=B, C=C, seed=seed,
+                                  workload="%s:%d:%d" % ("f64" if dtype == torch.float64 else "f32", m, n),
                                   bytes=(m * m + m * n + m * n) * es(dtype),
                                   kernel=nn_kernel_name(dtype, n)))
     return calls
@@ -127,23 +128,31 @@ def cpu_baseline(seconds_target=15.0):
                       "algorithmic bytes of the sample over the oracle's time" % (rows, m, k, n)}
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken from another kernel source."""
-    path = os.path.join(ROOT, "profiles", "tsm2r_nn_f64_m30720_n16_counters.txt")
-    if not os.path.exists(path):
-        return None
-    info = {}
-    for line in open(path):
-        if "=" in line and not line.startswith("#"):
-            key, val = line.split("=", 1)
-            info[key.strip()] = val.strip()
-    if info.get("kernel_source_sha256_16") != src_hash() or info.get("kernel") != kernel:
-        return None
-    try:
-        return float(info["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+def traffic_for(kernel: str, launches):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (profiles/*_counters.txt), averaged like the launches of the
+    timed step; None when a workload is missing or the summary was taken
+    from another kernel source."""
+    import glob
+    found = {}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_counters.txt")):
+        info = {}
+        for line in open(path):
+            if "=" in line and not line.startswith("#"):
+                key, val = line.split("=", 1)
+                info[key.strip()] = val.strip()
+        if info.get("kernel") != kernel or info.get("kernel_source_sha256_16") != src_hash():
+            continue
+        try:
+            found[info["workload"]] = float(info["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    tot = 0.0
+    for wl in launches:
+        if wl not in found:
+            return None
+        tot += found[wl]
+    return tot / len(launches) if launches else None
 
 
 def timed(fn, reps=5, warmup=1, flush=None):
@@ -195,6 +204,49 @@ def rows_tsm2l(dev):
     return out
 
 
+def rows_lowp(dev):
+    """Precision form of TSM2R on A 32768 x 32768: bf16 / f16 planes, single
+    and split, against plain FP32 on the same A (ratio of times vs ratio of
+    bytes), plus the one-time split of A."""
+    import oracle
+    out = []
+    seed = si.config_seed(3)
+    m = k = 32768
+    A = si.matrix(seed, si.STREAM_A, m, k, dtype=torch.float32, device=dev)
+    rows = [0, 12345, m - 1]
+    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, rows, dtype=torch.float32).double().numpy()
+    for n in (8, 16, 32):
+        B = si.matrix(seed + n, si.STREAM_B, k, n, dtype=torch.float32, device=dev)
+        C = tsm.empty_colmajor(m, n, torch.float32, dev)
+        t32 = timed(lambda: tsm.tsm2r(A, B, out=C))
+        b32 = (m * k + k * n + m * n) * 4
+        Bh = si.matrix(seed + n, si.STREAM_B, k, n, dtype=torch.float32).double().numpy()
+        for fmt, code in (("bf16", oracle.BF16), ("f16", oracle.F16)):
+            for lo in (False, True):
+                S = tsm.split(A, fmt, lo=lo)
+                t_split = timed(lambda: tsm.split(A, fmt, lo=lo), reps=2) if n == 8 else None
+                t = timed(lambda: tsm.tsm2r(S, B, out=C))
+                nb = S.nbytes() + (k * n + m * n) * 4
+                hi, lo_ = oracle.split(Ar.astype(np.float32), code)
+                stored = oracle.decode_plane(hi, code) + (oracle.decode_plane(lo_, code) if lo else 0)
+                Cs = C[rows].double().cpu().numpy()
+                row = {"row": "precision TSM2R A 32768^2 %s %s n=%d" % (fmt, "split" if lo else "single", n),
+                       "dtype": fmt + ("_split" if lo else ""), "GBps": nb / t / 1e9,
+                       "frac_of_8TBps": nb / t / 1e9 / PEAK_HBM_GBS,
+                       "fp32_GBps": b32 / t32 / 1e9, "speedup_vs_fp32": t32 / t,
+                       "bytes_ratio_fp32_over_form": b32 / nb,
+                       "err_vs_stored": oracle.normwise_error(Cs, oracle.matmul(stored, Bh)),
+                       "err_vs_fp32_values": oracle.normwise_error(Cs, oracle.matmul(Ar, Bh))}
+                if t_split is not None:
+                    row["split_GBps"] = (m * k * 4 + S.nbytes()) / t_split / 1e9
+                out.append(row)
+                del S
+        del B, C
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def rows_autograd(dev):
     """Forward + backward of C = A*B on the two autograd shapes."""
     import oracle
@@ -225,7 +277,7 @@ def rows_autograd(dev):
             e_f = oracle.normwise_error(C[rows].double().cpu().numpy(), oracle.matmul(Ar, Bh))
             e_a = oracle.normwise_error(dA[rows].double().cpu().numpy(), oracle.matmul(dCr, Bh.T))
             cols = [0, k // 2, k - 1]
-            if m * k <= (1 << 28):
+            if m * n <= (1 << 22):
                 Ac = si.matrix_cols(seed, si.STREAM_A, m, k, cols, dtype=dtype).double().numpy()
                 dCh = si.matrix(seed, si.STREAM_DC, m, n, dtype=dtype,
                                 dist="normal").double().numpy()
@@ -242,6 +294,31 @@ def rows_autograd(dev):
                         "err": {"C": e_f, "dA": e_a, "dB": e_b}, "tol": TOL[dtype]})
             del A, B, dC, C, dA, dB
             torch.cuda.empty_cache()
+    # bf16-split: forward on the planes (split once, reported apart), dA in
+    # float, dB on the planes
+    for shape, (m, k, n) in (("TSM2L", (8388608, 16, 16)), ("TSM2R", (16384, 16384, 8))):
+        A = si.matrix(seed, si.STREAM_A, m, k, dtype=torch.float32, device=dev)
+        B = si.matrix(seed, si.STREAM_B, k, n, dtype=torch.float32, device=dev)
+        dC = si.matrix(seed, si.STREAM_DC, m, n, dtype=torch.float32, device=dev, dist="normal")
+        S = tsm.split(A, "bf16", lo=True)
+        C = tsm.empty_colmajor(m, n, torch.float32, dev)
+        dA = tsm.empty_colmajor(m, k, torch.float32, dev)
+        dB = tsm.empty_colmajor(k, n, torch.float32, dev)
+        fwd = (lambda: tsm.tsm2l(S, B, out=C)) if shape == "TSM2L" else (lambda: tsm.tsm2r(S, B, out=C))
+        t_f = timed(fwd)
+        t_a = timed(lambda: tsm.grad_a(dC, B, out=dA))
+        t_b = timed(lambda: tsm.grad_b(S, dC, out=dB))
+        b_f = S.nbytes() + (k * n + m * n) * 4
+        b_a = (m * n + k * n + m * k) * 4
+        b_b = S.nbytes() + (m * n + k * n) * 4
+        out.append({"row": "autograd fwd+bwd %s shape m=%d k=%d n=%d" % (shape, m, k, n),
+                    "dtype": "bf16_split",
+                    "GBps": (b_f + b_a + b_b) / (t_f + t_a + t_b) / 1e9,
+                    "frac_of_8TBps": (b_f + b_a + b_b) / (t_f + t_a + t_b) / 1e9 / PEAK_HBM_GBS,
+                    "fwd_GBps": b_f / t_f / 1e9, "grad_a_GBps": b_a / t_a / 1e9,
+                    "grad_b_GBps": b_b / t_b / 1e9})
+        del A, B, dC, S, C, dA, dB
+        torch.cuda.empty_cache()
     return out
 
 
@@ -253,8 +330,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--profile-kernel", action="store_true",
-                    help="only launch the dominant kernel 5 times (for rocprofv3 counters)")
+    ap.add_argument("--profile-kernel", default=None, metavar="DTYPE:M:N",
+                    help="only launch TSM2R on one workload of the grid 5 times "
+                         "(for rocprofv3 counters), e.g. f64:30720:16")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -273,15 +351,18 @@ def main():
         print("copied 5 x %d bytes" % src.numel(), flush=True)
         return
     if args.profile_kernel:
-        m = R_SIZES[-1]
+        dts, ms, ns = args.profile_kernel.split(":")
+        dtype = torch.float64 if dts == "f64" else torch.float32
+        m, n = int(ms), int(ns)
         seed = si.config_seed(1)
-        A = si.matrix(seed, si.STREAM_A, m, m, device=dev)
-        B = si.matrix(seed + 16, si.STREAM_B, m, 16, device=dev)
-        C = tsm.empty_colmajor(m, 16, torch.float64, dev)
+        A = si.matrix(seed, si.STREAM_A, m, m, dtype=dtype, device=dev)
+        B = si.matrix(seed + n, si.STREAM_B, m, n, dtype=dtype, device=dev)
+        C = tsm.empty_colmajor(m, n, dtype, dev)
         for _ in range(5):
             tsm.tsm2r(A, B, out=C)
         torch.cuda.synchronize()
-        print("launched %s 5 times" % nn_kernel_name(torch.float64, 16), flush=True)
+        print("launched %s 5 times on m = k = %d, n = %d" % (nn_kernel_name(dtype, n), m, n),
+              flush=True)
         return
 
     t_setup = time.perf_counter()
@@ -307,20 +388,23 @@ def main():
     per_kernel = {}
     for s in range(args.steps):
         for i, c in enumerate(calls):
-            d = per_kernel.setdefault(c["kernel"], {"t": 0.0, "b": 0.0, "n": 0})
+            d = per_kernel.setdefault(c["kernel"], {"t": 0.0, "b": 0.0, "n": 0, "wl": []})
             d["t"] += evs[s][i][0].elapsed_time(evs[s][i][1]) / 1e3
             d["b"] += c["bytes"]
             d["n"] += 1
+            if s == 0:
+                d["wl"].append(c["workload"])
     dom = max(per_kernel, key=lambda k: per_kernel[k]["t"])
     d = per_kernel[dom]
     achieved = d["b"] / d["t"] / 1e9
     per_launch = d["b"] / d["n"]
-    traffic = traffic_for(dom)
+    traffic = traffic_for(dom, d["wl"])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                 "avg_launch_us": d["t"] / d["n"] * 1e6, "launches": d["n"],
                 "algorithmic_bytes_per_launch": per_launch,
-                "traffic": traffic}
+                "workloads": d["wl"], "traffic": traffic,
+                "traffic_over_algorithmic": (traffic / per_launch) if traffic else None}
     line = {
         "metric": "achieved HBM GB/s (% peak), TSM2R/TSM2L fp64 vs bf16-split fwd+bwd at tol",
         "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -337,7 +421,7 @@ def main():
     del calls
     torch.cuda.empty_cache()
     if not args.no_rows:
-        line["rows"] = rows_tsm2l(dev) + rows_autograd(dev)
+        line["rows"] = rows_tsm2l(dev) + rows_lowp(dev) + rows_autograd(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

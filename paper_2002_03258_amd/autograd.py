@@ -44,22 +44,26 @@ class TSMMatmul(torch.autograd.Function):
                 raise ValueError("mode %s needs %s A and B" % (mode, want))
             Aop = A
         C = tsm2l(Aop, B) if kd == "L" else tsm2r(Aop, B)
-        ctx.save_for_backward(B)
-        ctx.Aop = Aop            # the tensor A or its stored planes
-        ctx.lowp = mode in _LOWP
+        if mode in _LOWP:
+            ctx.save_for_backward(B)
+            ctx.planes = Aop     # A's stored planes (dB uses the stored values)
+        else:
+            ctx.save_for_backward(B, A)
+            ctx.planes = None
         return C
 
     @staticmethod
     def backward(ctx, dC: torch.Tensor):
         from . import grad_a, grad_b
-        (B,) = ctx.saved_tensors
+        saved = ctx.saved_tensors
+        B = saved[0]
+        Aop = ctx.planes if ctx.planes is not None else saved[1]
         dA = dB = None
         dC = dC.to(B.dtype)
         if ctx.needs_input_grad[0]:
             dA = grad_a(dC, B)
         if ctx.needs_input_grad[1]:
-            dB = grad_b(ctx.Aop, dC)
-        ctx.Aop = None
+            dB = grad_b(Aop, dC)
         return dA, dB, None, None
 
 

@@ -55,7 +55,7 @@ template <typename T, int NT16, int RG, int WK, bool VEC>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
     int64_t m, int64_t k, int n, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
-    int64_t kslice, double* __restrict__ part, unsigned* __restrict__ tickets) {
+    int64_t kslice, double* __restrict__ part, unsigned* __restrict__ tickets, int bvec) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -101,14 +101,25 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
             }
         }
     };
+    // a lane's four B values of a group are contiguous in B's column
     auto loadB = [&](int64_t j0, T (&bv)[NT16][4]) {
 #pragma unroll
         for (int t = 0; t < NT16; ++t) {
             const int p = 16 * t + rl;
+            const int64_t jb = j0 + 4 * kk;
+            const T* __restrict__ src = B + jb + (int64_t)p * ldb;
+            if (p < n && bvec && jb + 4 <= wk1) {
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const int64_t j = j0 + 4 * kk + st;
-                bv[t][st] = (p < n && j < wk1) ? B[j + p * ldb] : T(0);
+                for (int h = 0; h < 4 / RL + (RL > 4 ? 1 : 0); ++h) {
+                    T v[RL < 4 ? RL : 4];
+                    load_run<T, (RL < 4 ? RL : 4), true>(src + h * RL, RL, true, v);
+#pragma unroll
+                    for (int e = 0; e < (RL < 4 ? RL : 4); ++e) bv[t][h * RL + e] = v[e];
+                }
+            } else {
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+                    bv[t][st] = (p < n && jb + st < wk1) ? src[st] : T(0);
             }
         }
     };
@@ -484,12 +495,14 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
 }
 
 int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
-    (void)dtype;
-    void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&L.n,    (void*)&L.A,
-                    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,
-                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&L.tickets};
     int n32 = (int)L.n;
-    args[2] = (void*)&n32;
+    // 16-byte loads of B's column runs need an aligned B with ldb*size % 16 == 0
+    const int es = dtype == DT_F64 ? 8 : 4;
+    int bvec = aligned16(L.B) && ((L.ldb * es) % 16 == 0);
+    void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&n32,    (void*)&L.A,
+                    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,
+                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&L.tickets,
+                    (void*)&bvec};
     hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
                                    0, st);
     return e == hipSuccess ? 0 : 1;

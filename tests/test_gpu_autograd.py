@@ -19,12 +19,14 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("kind,shape", [("R", (9, 70, 3)), ("L", (300, 5, 4)), ("R", (33, 33, 17)),
                                         ("L", (257, 16, 16))])
 def test_gradcheck_f64(dev, kind, shape):
+    """C is linear in each input, so the central difference has no truncation
+    error; eps only has to keep |C| * 2^-53 / eps well below atol."""
     m, k, n = shape
     g = torch.Generator(device="cpu").manual_seed(m + k + n)
     A = torch.rand(m, k, dtype=torch.float64, generator=g).to(dev).requires_grad_()
     B = torch.rand(k, n, dtype=torch.float64, generator=g).to(dev).requires_grad_()
     assert torch.autograd.gradcheck(lambda a, b: tsm.matmul(a, b, "f64", kind), (A, B),
-                                    eps=1e-6, atol=1e-9, rtol=1e-7)
+                                    eps=1e-3, atol=1e-9, rtol=1e-7)
 
 
 def _stored(A32, mode):

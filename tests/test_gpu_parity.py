@@ -91,6 +91,17 @@ def test_tsm2r_k_zero_and_closed_forms(dev, dtype):
     assert torch.equal(C, A[:, [0, 5, 1234, k - 1]])
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,k,n", [(9, 70, 3), (33, 33, 17), (70, 9, 4), (1000, 777, 32)])
+def test_tsm2r_rowmajor_small(dev, dtype, m, k, n):
+    Arm = si.row_major(11, si.STREAM_A, m, k, dtype=dtype, device=dev)
+    B = dev_matrix(11, si.STREAM_B, k, n, dtype, dev)
+    C = tsm.tsm2r(Arm, B)
+    ref = oracle.matmul(si.row_major(11, si.STREAM_A, m, k).to(dtype).double().numpy(),
+                        host_matrix(11, si.STREAM_B, k, n, dtype))
+    assert err(to_np(C), ref) <= TOL[dtype]
+
+
 def test_tsm2r_rowmajor_config(dev):
     """A 1024 x 1024 row-major FP64 matrix times B 1024 x 4, checked in full."""
     seed = si.config_seed(0)
@@ -174,7 +185,7 @@ def test_tsm2l_full_size_sampled(dev, dtype, m):
 
 # --------------------------------------------------------------- gradients
 SMALL_G = [(1, 1, 1), (1000, 16, 16), (3000, 700, 8), (4097, 33, 5), (257, 2000, 32),
-           (70001, 16, 16)]
+           (70001, 16, 16), (9, 70, 3), (9, 70, 17), (33, 33, 17), (15, 64, 1)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)

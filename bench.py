@@ -57,7 +57,7 @@ def es(dtype) -> int:
 
 def nn_kernel_name(dtype, n) -> str:
     t = "double" if dtype == torch.float64 else "float"
-    return "tsm2r_nn_kernel<%s, %d, 2, 4, true>" % (t, 1 if n <= 16 else 2)
+    return "tsm2r_nn_kernel<%s, %d, 2, 4, true, true>" % (t, 1 if n <= 16 else 2)
 
 
 def src_hash() -> str:

@@ -33,14 +33,14 @@
  *
  * Workspace
  * ---------
- *  Kernels that split a reduction across workgroups need a workspace of
- *  tsm2x_workspace_size() bytes.  The *_ws entry points take it from the
- *  caller: it must be device memory, 256-byte aligned, and zero-filled
- *  before its first use (the library leaves it in that state after every
- *  call, so the same buffer can be reused).  The other entry points use a
- *  grow-only per-device buffer owned by the library (allocated with hipMalloc
- *  on first need, released by tsm2x_finalize).  Two calls that share one
- *  workspace must not run concurrently (e.g. on two streams).
+ *  Kernels that split a reduction across workgroups write double-precision
+ *  partial sums to a workspace of tsm2x_workspace_size() bytes and add them
+ *  in a second, ordered pass.  tsm2r_ex and tsm_grad_b take the workspace
+ *  from the caller when ws != NULL: device memory, 256-byte aligned, any
+ *  contents.  Otherwise the library uses a grow-only per-device buffer it
+ *  owns (allocated with hipMalloc on first need, released by
+ *  tsm2x_finalize).  Two calls that share one workspace must not run
+ *  concurrently (e.g. on two streams).
  */
 #ifndef TSM2X_H
 #define TSM2X_H

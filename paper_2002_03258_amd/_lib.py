@@ -10,7 +10,8 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtsm2x.so")
+# TSM2X_LIBRARY may point at another build of the same library
+LIB_PATH = os.environ.get("TSM2X_LIBRARY") or os.path.join(HERE, "libtsm2x.so")
 
 F64, F32, BF16, F16, BF16_SPLIT, F16_SPLIT = range(6)
 COL_MAJOR, ROW_MAJOR = 0, 1

@@ -147,19 +147,17 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     int64_t S = cdiv(target, P.groups);
     const int64_t s_len = R / (RB * 4 * 8);   // >= 8 steps per wavefront
     if (S > s_len) S = s_len;
-    if (P.groups > MAX_TICKETS) S = 1;
     if (S < 1) S = 1;
     int64_t rs = cdiv(R, S);
     rs = cdiv(rs, RB * 4) * (RB * 4);
     P.rslice = rs;
     P.S = (int)cdiv(R, rs);
     if (P.S < 1) P.S = 1;
-    P.ws = P.S > 1 ? TICKET_BYTES + (size_t)P.groups * P.S * 256 * NT16 * 8 : 0;
+    P.ws = P.S > 1 ? (size_t)P.groups * P.S * 256 * NT16 * 8 : 0;
     return P;
 }
 
-// Workspace: caller's (checked) or the library's grow-only per-device buffer,
-// whose counter region starts zeroed.
+// Workspace: caller's (checked) or the library's grow-only per-device buffer.
 int get_ws(size_t need, void* user, size_t user_bytes, void** out) {
     *out = nullptr;
     if (need == 0) return TSM_SUCCESS;
@@ -185,11 +183,6 @@ int get_ws(size_t need, void* user, size_t user_bytes, void** out) {
             g_last_hip = std::string("hipMalloc(workspace): ") + hipGetErrorString(e);
             return TSM_ERR_ALLOC;
         }
-        e = hipMemset(p, 0, bytes);
-        if (e != hipSuccess) {
-            (void)hipFree(p);
-            return hip_fail(e, "hipMemset(workspace)");
-        }
         d->ws = p;
         d->ws_bytes = bytes;
     }
@@ -197,10 +190,7 @@ int get_ws(size_t need, void* user, size_t user_bytes, void** out) {
     return TSM_SUCCESS;
 }
 
-void split_ws(void* ws, double** part, unsigned** tickets) {
-    *tickets = (unsigned*)ws;
-    *part = (double*)((char*)ws + TICKET_BYTES);
-}
+void split_ws(void* ws, double** part) { *part = (double*)ws; }
 
 // Validation of (m, k, n, A, lda, B, ldb, C, ldc, dtype) for C = A*B with
 // column-major (or, for `rowA`, row-major) A.  `base` is the position of m.
@@ -250,8 +240,9 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
         LaunchNN L{};
         L.fn = P.fn;
         L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C;
-        L.ldc = ldc; L.np = P.np; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
-        if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+        L.ldc = ldc; L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S;
+        L.kslice = P.kslice;
+        if (P.S > 1) split_ws(w, &L.part);
         if (launch_tsm2r_lp(L, dtype, st)) return check_launch("tsm2r_lp_kernel");
         return check_launch("tsm2r_lp_kernel");
     }
@@ -265,7 +256,7 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
         L.R = k; L.ncols = m; L.n = n;
         L.X = A; L.ldx = lda; L.Y = B; L.ldy = ldb; L.O = C; L.ldo = ldc;
         L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
-        if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+        if (P.S > 1) split_ws(w, &L.part);
         if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_kernel");
     }
@@ -276,8 +267,8 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
     LaunchNN L{};
     L.fn = P.fn;
     L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C; L.ldc = ldc;
-    L.np = P.np; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
-    if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+    L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
+    if (P.S > 1) split_ws(w, &L.part);
     if (launch_tsm2r_nn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("tsm2r_nn_kernel");
 }
@@ -375,7 +366,7 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     LaunchTN L{};
     L.R = m; L.ncols = k; L.n = n; L.X = A; L.ldx = lda; L.Y = dC; L.ldy = lddc; L.O = dB;
     L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
-    if (P.S > 1) split_ws(w, &L.part, &L.tickets);
+    if (P.S > 1) split_ws(w, &L.part);
     if (!plain_dtype(dtype)) {
         if (launch_tn_lp(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_lp_kernel");

@@ -1,6 +1,6 @@
 // Device-side building blocks shared by the gfx950 kernels: 16-byte runs,
-// the ticketed split-reduction protocol, the 16x16x4 matrix-core step and
-// the row-tile finish of the TSM2R kernels.
+// the 16x16x4 matrix-core step, the workgroup-level finish of the split
+// reductions and the ordered sum of split partials.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -47,31 +47,6 @@ __device__ __forceinline__ void store_run(T* __restrict__ p, int64_t valid,
     }
 }
 
-// Ticket protocol of the split reductions: every workgroup of a group
-// publishes its double-precision partial, then takes a ticket; the one that
-// draws the last ticket sums all partials in slice order and re-arms the
-// counter for the next launch.
-__device__ __forceinline__ bool take_last_ticket(unsigned* __restrict__ ticket,
-                                                 int nslices) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(ticket, 1u);
-        s_last = (prev == (unsigned)(nslices - 1)) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        return true;
-    }
-    return false;
-}
-
-__device__ __forceinline__ void rearm_ticket(unsigned* __restrict__ ticket) {
-    if (threadIdx.x == 0) atomicExch(ticket, 0u);
-}
-
 // --------------------------------------------------------------------------
 // Matrix-core building block shared by the kernels below.
 //
@@ -103,16 +78,16 @@ template <> struct Mfma<double> {
     }
 };
 
-// Sum of the WK wavefronts' double partials for one row tile and, when the k
-// range is split across workgroups, the ticketed final sum.  `red` is LDS
-// scratch of [WK][PG][TR] doubles; put(pg, red) stores this wavefront's
-// values of columns pg .. pg+PG-1.
+// Sum of the WK wavefronts' partials (double, wavefront order) for one row
+// tile.  With one k slice the result is the output; otherwise it is this
+// workgroup's partial, part[((tile * nsl + s) * NP + p) * TR + row], and a
+// second kernel (split_reduce_kernel) adds the slices in order.  `red` is LDS
+// scratch of [WK][PG][TR] doubles; put(pg, red) stores this wavefront's values
+// of columns pg .. pg+PG-1.
 template <typename T, int NP, int WK, int TR, int PG, typename Put>
 __device__ __forceinline__ void nn_finish(int64_t m, int n, T* __restrict__ C, int64_t ldc,
                                           int64_t tile, int s, int nsl,
-                                          double* __restrict__ part,
-                                          unsigned* __restrict__ tickets, double* red,
-                                          Put&& put) {
+                                          double* __restrict__ part, double* red, Put&& put) {
     constexpr int NT = WAVE * WK;
     const int64_t row0 = tile * TR;
 #pragma unroll
@@ -137,18 +112,62 @@ __device__ __forceinline__ void nn_finish(int64_t m, int n, T* __restrict__ C, i
             }
         }
     }
-    if (nsl == 1) return;
-    if (!take_last_ticket(tickets + tile, nsl)) return;
-    for (int e = threadIdx.x; e < n * TR; e += NT) {
-        const int p = e / TR, rr = e % TR;
-        const int64_t row = row0 + rr;
-        if (row < m) {
-            double v = 0.0;
-            for (int s2 = 0; s2 < nsl; ++s2) v += part[((tile * nsl + s2) * NP + p) * TR + rr];
-            C[row + p * ldc] = (T)v;
+}
+
+// The same for the column tiles of the tn kernels: acc[t][r] of lane l is
+// O[c0 + mrow(l/16, r), 16 t + l%16]; partials go to
+// part[((ctile * nsl + s) * NP + p) * 16 + c].
+template <typename T, int NT16, int WK, typename Acc, typename MRow>
+__device__ __forceinline__ void tn_finish(int64_t ncols, int n, T* __restrict__ O, int64_t ldo,
+                                          int64_t ctile, int s, int nsl,
+                                          double* __restrict__ part, double (*red)[WAVE][4 * NT16],
+                                          const Acc (&acc)[NT16], MRow mrow) {
+    constexpr int NV = 4 * NT16;
+    constexpr int NP = 16 * NT16;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int t = 0; t < NT16; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[w][lane][4 * t + r] = (double)acc[t][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < WAVE * NV; e += WAVE * WK) {
+        const int ln = e / NV, vi = e % NV;
+        double v = red[0][ln][vi];
+#pragma unroll
+        for (int ww = 1; ww < WK; ++ww) v += red[ww][ln][vi];
+        const int t = vi / 4, r = vi % 4;
+        const int c = mrow(ln >> 4, r);
+        const int64_t col = ctile * 16 + c;
+        const int p = 16 * t + (ln & 15);
+        if (nsl == 1) {
+            if (col < ncols && p < n) O[col + p * ldo] = (T)v;
+        } else {
+            part[((ctile * nsl + s) * NP + p) * 16 + c] = v;
         }
     }
-    rearm_ticket(tickets + tile);
+}
+
+// Ordered sum of split partials: O[g*W + r, p] = sum over s of
+// part[((g * S + s) * NP + p) * W + r], for rows g*W + r < rows and p < n.
+template <typename T>
+__global__ __launch_bounds__(256) void split_reduce_kernel(int64_t groups, int S, int NP, int W,
+                                                           int64_t rows, int n,
+                                                           const double* __restrict__ part,
+                                                           T* __restrict__ O, int64_t ldo) {
+    const int64_t E = (int64_t)NP * W;
+    const int64_t total = groups * E;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = idx / E, e = idx % E;
+        const int p = (int)(e / W), r = (int)(e % W);
+        const int64_t row = g * W + r;
+        if (p < n && row < rows) {
+            double v = 0.0;
+            for (int s = 0; s < S; ++s) v += part[(g * S + s) * E + e];
+            O[row + p * ldo] = (T)v;
+        }
+    }
 }
 
 }  // namespace tsm

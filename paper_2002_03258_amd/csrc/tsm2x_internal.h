@@ -9,14 +9,6 @@ enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3, DT_BF16_SPLIT = 4, DT_F1
 
 // Output rows per wavefront of the tn kernel for NP padded output columns:
 // J*NP accumulators per lane, at most 64.
-// Every workspace starts with a fixed region of MAX_TICKETS zero-initialised
-// counters (re-armed to zero by the kernels that use them), followed by the
-// partial sums.  The layout does not depend on the call, so one workspace can
-// serve calls of any shape.  Calls whose split would need more counters run
-// without a split.
-constexpr int64_t MAX_TICKETS = 4096;
-constexpr size_t TICKET_BYTES = MAX_TICKETS * 4;
-
 struct NNPlan {             // TSM2R launch plan (column-major A)
     const void* fn;         // kernel instance
     int np;                 // padded n
@@ -39,11 +31,11 @@ struct LaunchNN {           // tsm2r_nn: C = A*B, column-major A
     const void* B; int64_t ldb;
     void* C; int64_t ldc;
     int np;                 // padded n
+    int tile_rows;
     int64_t tiles;          // row tiles (gridDim.x)
     int S;                  // k slices (gridDim.y)
     int64_t kslice;         // columns per k slice
-    double* part;           // S > 1: partial sums
-    unsigned* tickets;      // S > 1: one counter per row tile
+    double* part;           // S > 1: partial sums (workspace)
 };
 
 struct LaunchRT {           // rowtile: O = X*Y, X m x kin (kin <= 32)
@@ -64,8 +56,7 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
     int64_t groups;         // 16-column tiles of the output (gridDim.x)
     int S;                  // reduction slices (gridDim.y)
     int64_t rslice;
-    double* part;
-    unsigned* tickets;
+    double* part;           // S > 1: partial sums (workspace)
 };
 
 // Low-precision storage forms of A (bf16 / f16, single or split planes).
@@ -83,5 +74,9 @@ int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st);
 int launch_rowtile(const LaunchRT& L, int dtype, hipStream_t st);
 int launch_tn(const LaunchTN& L, int dtype, hipStream_t st);
 int launch_fill_zero(int64_t m, int64_t n, void* C, int64_t ldc, int dtype, hipStream_t st);
+// Ordered sum over S slices of double partials laid out [g][s][NP][W] into
+// O[g*W + r + p*ldo] (rows g*W + r < rows, p < n).
+int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t rows, int n,
+                        const double* part, void* O, int64_t ldo, hipStream_t st);
 
 }  // namespace tsm

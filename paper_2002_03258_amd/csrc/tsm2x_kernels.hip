@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
+
 #include "tsm2x_internal.h"
 #include "tsm2x_device.h"
 
@@ -49,13 +51,24 @@ namespace tsm {
 //
 // The k range is split across the WK wavefronts of a workgroup and across
 // workgroups; the partial sums are added in double precision in a fixed
-// order, the last workgroup of a row tile to arrive doing the final sum.
+// order (in LDS within the workgroup, then by split_reduce_kernel).
 // --------------------------------------------------------------------------
-template <typename T, int NT16, int RG, int WK, bool VEC>
+// Explicit prefetch of the next 16-column group (Algorithm 4's nextA/nextB).
+#ifndef TSM2X_NN_PREFETCH
+#define TSM2X_NN_PREFETCH 1
+#endif
+#ifndef TSM2X_NN_RG64
+#define TSM2X_NN_RG64 2
+#endif
+#ifndef TSM2X_NN_RG32
+#define TSM2X_NN_RG32 2
+#endif
+
+template <typename T, int NT16, int RG, int WK, bool VEC, bool PF = TSM2X_NN_PREFETCH>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
     int64_t m, int64_t k, int n, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
-    int64_t kslice, double* __restrict__ part, unsigned* __restrict__ tickets, int bvec) {
+    int64_t kslice, double* __restrict__ part, int bvec) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -127,11 +140,16 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
     if (wk1 > wk0) {
         const int ng = (int)((wk1 - wk0 + 15) / 16);
         T av[4][RG][RL], bv[NT16][4];
-        loadA(wk0, av);
-        loadB(wk0, bv);
+        if (PF) {
+            loadA(wk0, av);
+            loadB(wk0, bv);
+        }
         for (int g16 = 0; g16 < ng; ++g16) {
             T an[4][RG][RL], bn[NT16][4];
-            if (g16 + 1 < ng) {
+            if (!PF) {
+                loadA(wk0 + 16 * g16, av);
+                loadB(wk0 + 16 * g16, bv);
+            } else if (g16 + 1 < ng) {
                 loadA(wk0 + 16 * (g16 + 1), an);
                 loadB(wk0 + 16 * (g16 + 1), bn);
             }
@@ -144,20 +162,22 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
 #pragma unroll
                         for (int t = 0; t < NT16; ++t)
                             acc[g][q][t] = M::op(bv[t][st], av[st][g][q], acc[g][q][t]);
+            if (PF) {
 #pragma unroll
-            for (int st = 0; st < 4; ++st)
+                for (int st = 0; st < 4; ++st)
 #pragma unroll
-                for (int g = 0; g < RG; ++g)
+                    for (int g = 0; g < RG; ++g)
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) av[st][g][q] = an[st][g][q];
+                        for (int q = 0; q < RL; ++q) av[st][g][q] = an[st][g][q];
 #pragma unroll
-            for (int t = 0; t < NT16; ++t)
+                for (int t = 0; t < NT16; ++t)
 #pragma unroll
-                for (int st = 0; st < 4; ++st) bv[t][st] = bn[t][st];
+                    for (int st = 0; st < 4; ++st) bv[t][st] = bn[t][st];
+            }
         }
     }
 
-    nn_finish<T, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part, tickets,
+    nn_finish<T, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part,
                                  reinterpret_cast<double*>(smem), [&](int pg, double* red) {
         const int t = pg / 16;
 #pragma unroll
@@ -298,7 +318,7 @@ template <typename T, int NT16, int RG, bool VEC>
 __global__ __launch_bounds__(256) void tn_kernel(
     int64_t R, int64_t ncols, int n, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ O, int64_t ldo,
-    int64_t rslice, double* __restrict__ part, unsigned* __restrict__ tickets) {
+    int64_t rslice, double* __restrict__ part) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -373,43 +393,8 @@ __global__ __launch_bounds__(256) void tn_kernel(
         }
     }
 
-    // Sum the WK wavefronts in wave order (double), then across workgroups.
-#pragma unroll
-    for (int t = 0; t < NT16; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[w][lane][4 * t + r] = (double)acc[t][r];
-    __syncthreads();
-    // element e of the tile: lane e / NV, value e % NV
-    constexpr int TILE = WAVE * NV;
-    constexpr int PBS = 16 * 16 * NT16;  // partial slots per column tile
-    for (int e = threadIdx.x; e < TILE; e += 256) {
-        const int ln = e / NV, vi = e % NV;
-        double v = red[0][ln][vi];
-#pragma unroll
-        for (int ww = 1; ww < WK; ++ww) v += red[ww][ln][vi];
-        const int t = vi / 4, r = vi % 4;
-        const int64_t col = c0 + M::mrow(ln >> 4, r);
-        const int p = 16 * t + (ln & 15);
-        if (nsl == 1) {
-            if (col < ncols && p < n) O[col + p * ldo] = (T)v;
-        } else {
-            part[(ctile * nsl + s) * PBS + e] = v;
-        }
-    }
-    if (nsl == 1) return;
-    if (!take_last_ticket(tickets + ctile, nsl)) return;
-    for (int e = threadIdx.x; e < TILE; e += 256) {
-        const int ln = e / NV, vi = e % NV;
-        const int t = vi / 4, r = vi % 4;
-        const int64_t col = c0 + M::mrow(ln >> 4, r);
-        const int p = 16 * t + (ln & 15);
-        if (col < ncols && p < n) {
-            double v = 0.0;
-            for (int s2 = 0; s2 < nsl; ++s2) v += part[(ctile * nsl + s2) * PBS + e];
-            O[col + p * ldo] = (T)v;
-        }
-    }
-    rearm_ticket(tickets + ctile);
+    tn_finish<T, NT16, WK>(ncols, n, O, ldo, ctile, s, nsl, part, red, acc,
+                           [](int kq, int r) { return Mfma<T>::mrow(kq, r); });
 }
 
 template <typename T>
@@ -452,11 +437,13 @@ static NNInstance nn_instance() {
 template <bool VEC>
 static bool nn_pick(int dtype, int np, NNInstance* out) {
     if (dtype == DT_F64) {
-        *out = np <= 16 ? nn_instance<double, 1, 2, VEC>() : nn_instance<double, 2, 2, VEC>();
+        *out = np <= 16 ? nn_instance<double, 1, TSM2X_NN_RG64, VEC>()
+                        : nn_instance<double, 2, TSM2X_NN_RG64, VEC>();
         return true;
     }
     if (dtype == DT_F32) {
-        *out = np <= 16 ? nn_instance<float, 1, 2, VEC>() : nn_instance<float, 2, 2, VEC>();
+        *out = np <= 16 ? nn_instance<float, 1, TSM2X_NN_RG32, VEC>()
+                        : nn_instance<float, 2, TSM2X_NN_RG32, VEC>();
         return true;
     }
     return false;
@@ -475,22 +462,26 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
     P->fn = I.fn;
     P->tiles = cdiv64(m, I.tile_rows);
     P->tile_rows = I.tile_rows;
-    // One round of resident workgroups: split k so that tiles * S fills it.
-    const int64_t slots = (int64_t)cus * I.occ;
+    // One round of resident workgroups, at most 3 per CU (12 wavefronts, which
+    // keep enough loads in flight; more slices only add partial traffic):
+    // split k so that tiles * S fills it without a tail round.
+    const int64_t per_cu = I.occ < 3 ? I.occ : 3;
+    const int64_t slots = (int64_t)cus * per_cu;
     int64_t S = slots / P->tiles;
     const int64_t s_len = k / (WK * 64);                          // >= 64 columns per wave
     const int64_t s_cost = (k * es) / ((int64_t)np * 200);         // partials <= ~8 % of A
     if (S > s_len) S = s_len;
     if (S > s_cost) S = s_cost;
-    if (P->tiles > MAX_TICKETS) S = 1;
     if (S < 1) S = 1;
+    const char* fs = std::getenv("TSM2X_NN_S");
+    if (fs && *fs) S = std::strtoll(fs, nullptr, 10) > 0 ? std::strtoll(fs, nullptr, 10) : S;
     const int64_t gran = (int64_t)WK * 16;
     int64_t ks = cdiv64(k, S);
     ks = cdiv64(ks, gran) * gran;
     P->kslice = ks;
     P->S = (int)cdiv64(k, ks);
     if (P->S < 1) P->S = 1;
-    P->ws = P->S > 1 ? TICKET_BYTES + (size_t)P->tiles * P->S * np * I.tile_rows * 8 : 0;
+    P->ws = P->S > 1 ? (size_t)P->tiles * P->S * np * I.tile_rows * 8 : 0;
     return 0;
 }
 
@@ -501,11 +492,14 @@ int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
     int bvec = aligned16(L.B) && ((L.ldb * es) % 16 == 0);
     void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&n32,    (void*)&L.A,
                     (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,
-                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&L.tickets,
-                    (void*)&bvec};
+                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&bvec};
     hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
                                    0, st);
-    return e == hipSuccess ? 0 : 1;
+    if (e != hipSuccess) return 1;
+    if (L.S > 1)
+        return launch_split_reduce(dtype, L.tiles, L.S, L.np, L.tile_rows, L.m, (int)L.n, L.part,
+                                   L.C, L.ldc, st);
+    return 0;
 }
 
 template <typename T, int KS, int NT16, int RG>
@@ -548,11 +542,11 @@ static int tn_launch(const LaunchTN& L, bool vec, hipStream_t st) {
     if (vec)
         hipLaunchKernelGGL((tn_kernel<T, NT16, 2, true>), grid, block, 0, st, L.R, L.ncols,
                            (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
-                           L.rslice, L.part, L.tickets);
+                           L.rslice, L.part);
     else
         hipLaunchKernelGGL((tn_kernel<T, NT16, 2, false>), grid, block, 0, st, L.R, L.ncols,
                            (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
-                           L.rslice, L.part, L.tickets);
+                           L.rslice, L.part);
     return 0;
 }
 
@@ -561,13 +555,31 @@ static int tn_dispatch(const LaunchTN& L, hipStream_t st) {
     const bool vec = aligned16(L.X) && aligned16(L.Y) &&
                      ((L.ldx * (int64_t)sizeof(T)) % 16 == 0) &&
                      ((L.ldy * (int64_t)sizeof(T)) % 16 == 0);
-    return L.n <= 16 ? tn_launch<T, 1>(L, vec, st) : tn_launch<T, 2>(L, vec, st);
+    const int rc = L.n <= 16 ? tn_launch<T, 1>(L, vec, st) : tn_launch<T, 2>(L, vec, st);
+    if (rc || L.S <= 1) return rc;
+    return launch_split_reduce(sizeof(T) == 8 ? DT_F64 : DT_F32, L.groups, L.S,
+                               L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n, L.part, L.O, L.ldo, st);
 }
 
 int launch_tn(const LaunchTN& L, int dtype, hipStream_t st) {
     if (dtype == DT_F64) return tn_dispatch<double>(L, st);
     if (dtype == DT_F32) return tn_dispatch<float>(L, st);
     return 1;
+}
+
+int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t rows, int n,
+                        const double* part, void* O, int64_t ldo, hipStream_t st) {
+    const int64_t total = groups * NP * W;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    if (dtype == DT_F64)
+        hipLaunchKernelGGL(split_reduce_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           groups, S, NP, W, rows, n, part, (double*)O, ldo);
+    else
+        hipLaunchKernelGGL(split_reduce_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           groups, S, NP, W, rows, n, part, (float*)O, ldo);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
 int launch_fill_zero(int64_t m, int64_t n, void* C, int64_t ldc, int dtype, hipStream_t st) {

@@ -151,8 +151,7 @@ template <int FMT, int NT16, bool SPLIT, int WK, bool VEC>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, const float* __restrict__ B, int64_t ldb,
-    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part,
-    unsigned* __restrict__ tickets) {
+    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part) {
     constexpr int TR = 128;              // 16 lanes x 8 rows
     constexpr int NP = 16 * NT16;
     constexpr int PG = 4;
@@ -277,7 +276,7 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     }
 
     // lane holds C[r + q, 16 t + 4 kk + rr] in acc[q][t][rr]
-    nn_finish<float, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part, tickets,
+    nn_finish<float, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part,
                                      reinterpret_cast<double*>(smem), [&](int pg, double* red) {
         const int t = pg / 16;
 #pragma unroll
@@ -422,8 +421,7 @@ template <int FMT, int NT16, bool SPLIT, bool VEC>
 __global__ __launch_bounds__(256) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
-    float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part,
-    unsigned* __restrict__ tickets) {
+    float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part) {
     constexpr int WK = 4;
     constexpr int RG = 2;
     constexpr int RB = 32 * RG;          // rows per wavefront step
@@ -520,41 +518,8 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
         }
     }
 
-#pragma unroll
-    for (int t = 0; t < NT16; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[w][lane][4 * t + r] = (double)acc[t][r];
-    __syncthreads();
-    constexpr int TILE = WAVE * NV;
-    constexpr int PBS = 16 * 16 * NT16;
-    for (int e = threadIdx.x; e < TILE; e += 256) {
-        const int ln = e / NV, vi = e % NV;
-        double v = red[0][ln][vi];
-#pragma unroll
-        for (int ww = 1; ww < WK; ++ww) v += red[ww][ln][vi];
-        const int t = vi / 4, r = vi % 4;
-        const int64_t col = c0 + Mfma<float>::mrow(ln >> 4, r);
-        const int p = 16 * t + (ln & 15);
-        if (nsl == 1) {
-            if (col < ncols && p < n) O[col + p * ldo] = (float)v;
-        } else {
-            part[(ctile * nsl + s) * PBS + e] = v;
-        }
-    }
-    if (nsl == 1) return;
-    if (!take_last_ticket(tickets + ctile, nsl)) return;
-    for (int e = threadIdx.x; e < TILE; e += 256) {
-        const int ln = e / NV, vi = e % NV;
-        const int t = vi / 4, r = vi % 4;
-        const int64_t col = c0 + Mfma<float>::mrow(ln >> 4, r);
-        const int p = 16 * t + (ln & 15);
-        if (col < ncols && p < n) {
-            double v = 0.0;
-            for (int s2 = 0; s2 < nsl; ++s2) v += part[(ctile * nsl + s2) * PBS + e];
-            O[col + p * ldo] = (float)v;
-        }
-    }
-    rearm_ticket(tickets + ctile);
+    tn_finish<float, NT16, WK>(ncols, n, O, ldo, ctile, s, nsl, part, red, acc,
+                               [](int kq, int r) { return Mfma<float>::mrow(kq, r); });
 }
 
 // --------------------------------------------------------------------------
@@ -598,13 +563,12 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     P->np = 16 * nt16;
     P->tile_rows = TR;
     P->tiles = cdiv_lp(m, TR);
-    const int64_t slots = (int64_t)cus * occ;
+    const int64_t slots = (int64_t)cus * (occ < 3 ? occ : 3);
     int64_t S = slots / P->tiles;
     const int64_t s_len = k / (WK * 64);
     const int64_t s_cost = (k * es) / ((int64_t)P->np * 200);
     if (S > s_len) S = s_len;
     if (S > s_cost) S = s_cost;
-    if (P->tiles > MAX_TICKETS) S = 1;
     if (S < 1) S = 1;
     const int64_t gran = (int64_t)WK * 32;
     int64_t ks = cdiv_lp(k, S);
@@ -612,7 +576,7 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     P->kslice = ks;
     P->S = (int)cdiv_lp(k, ks);
     if (P->S < 1) P->S = 1;
-    P->ws = P->S > 1 ? TICKET_BYTES + (size_t)P->tiles * P->S * P->np * TR * 8 : 0;
+    P->ws = P->S > 1 ? (size_t)P->tiles * P->S * P->np * TR * 8 : 0;
     return 0;
 }
 
@@ -623,11 +587,14 @@ int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st) {
     int n32 = (int)L.n;
     void* args[] = {(void*)&L.m,   (void*)&L.k,   (void*)&n32,      (void*)&ah,
                     (void*)&al,    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,
-                    (void*)&L.C,   (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part,
-                    (void*)&L.tickets};
+                    (void*)&L.C,   (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part};
     hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
                                    0, st);
-    return e == hipSuccess ? 0 : 1;
+    if (e != hipSuccess) return 1;
+    if (L.S > 1)
+        return launch_split_reduce(DT_F32, L.tiles, L.S, L.np, 128, L.m, (int)L.n, L.part, L.C,
+                                   L.ldc, st);
+    return 0;
 }
 
 int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
@@ -662,7 +629,7 @@ int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
     return 1;
 }
 
-int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st) {
+static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
     const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
     const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
     const bool vec = ((uintptr_t)L.X & 15u) == 0 && (L.ldx % 8) == 0 &&
@@ -676,11 +643,11 @@ int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st) {
         if (vec)                                                                                  \
             hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, true>), g, b, 0, st, L.R, L.ncols, ni, xh,  \
                                xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo, L.rslice, \
-                               L.part, L.tickets);                                                \
+                               L.part);                                                           \
         else                                                                                      \
             hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, false>), g, b, 0, st, L.R, L.ncols, ni,     \
                                xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,       \
-                               L.rslice, L.part, L.tickets);                                      \
+                               L.rslice, L.part);                                                 \
         return 0;                                                                                 \
     }
     if (fmt == FMT_BF16) {
@@ -692,6 +659,13 @@ int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st) {
     }
 #undef TSM_T
     return 1;
+}
+
+int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st) {
+    const int rc = launch_tn_lp_main(L, dtype, st);
+    if (rc || L.S <= 1) return rc;
+    return launch_split_reduce(DT_F32, L.groups, L.S, L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n,
+                               L.part, L.O, L.ldo, st);
 }
 
 int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,

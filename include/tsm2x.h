@@ -143,6 +143,20 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
                const void* dC, int64_t lddc, void* dB, int64_t lddb,
                int dtype, void* ws, size_t ws_bytes, void* stream);
 
+/* Fused backward of a TSM2L product C = A*B (k <= 32, n <= 32): one pass
+ * over the rows of A (m x k, lda) and dC (m x n, lddc) writes
+ * dA = dC * B^T (m x k, ldda) and dB = A^T * dC (k x n, lddb); B is k x n
+ * (ldb).  A, dC and dA each cross HBM once (the separate tsm_grad_a and
+ * tsm_grad_b read dC twice).  dB is reduced in double precision in a fixed
+ * order.  dtype: TSM_F64 or TSM_F32.  ws/ws_bytes as in tsm_grad_b (NULL:
+ * library buffer).  Arguments: 1 m, 2 k, 3 n, 4 A, 5 lda, 6 B, 7 ldb, 8 dC,
+ * 9 lddc, 10 dA, 11 ldda, 12 dB, 13 lddb, 14 dtype, 15 ws, 16 ws_bytes,
+ * 17 stream.  TSM_ERR_UNSUPPORTED if k > 32, n > 32 or dtype is 16-bit. */
+int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+                   const void* B, int64_t ldb, const void* dC, int64_t lddc,
+                   void* dA, int64_t ldda, void* dB, int64_t lddb, int dtype,
+                   void* ws, size_t ws_bytes, void* stream);
+
 /* Low-precision storage form of A: from a float m-by-k matrix A (lda),
  * write hi = RNE(a) and, if lo != NULL, lo = RNE(a - hi) (a - hi is exact in
  * float) as bfloat16 (fmt 0) or binary16 (fmt 1) planes of leading dimension

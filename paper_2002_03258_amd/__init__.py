@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (BF16, BF16_SPLIT, COL_MAJOR, F16, F16_SPLIT, F32, F64,
                    ROW_MAJOR, TSMError)
 
-__all__ = ["tsm2r", "tsm2l", "grad_a", "grad_b", "split", "SplitA", "colmajor",
+__all__ = ["tsm2r", "tsm2l", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA", "colmajor",
            "empty_colmajor", "workspace_size", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
            "BF16_SPLIT", "F16_SPLIT"]
 
@@ -204,6 +204,22 @@ def grad_b(A, dC: torch.Tensor, out: torch.Tensor | None = None,
     _lib.call("tsm_grad_b", m, k, n, A.data_ptr(), _ld(A), dC.data_ptr(), _ld(dC),
               dB.data_ptr(), _ld(dB), dt, ws, wsb, _stream())
     return dB
+
+
+def tsm2l_backward(A: torch.Tensor, B: torch.Tensor, dC: torch.Tensor):
+    """(dA, dB) = (dC*B^T, A^T*dC) for a TSM2L product (k, n <= 32) in one
+    fused pass over A and dC."""
+    _check_device(A, B, dC)
+    dt = _DT[A.dtype]
+    A, B, dC = colmajor(A), colmajor(B), colmajor(dC)
+    m, k = A.shape
+    n = B.shape[1]
+    dA = empty_colmajor(m, k, A.dtype, A.device)
+    dB = empty_colmajor(k, n, A.dtype, A.device)
+    _lib.call("tsm2l_backward", m, k, n, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
+              dC.data_ptr(), _ld(dC), dA.data_ptr(), _ld(dA), dB.data_ptr(), _ld(dB), dt,
+              None, 0, _stream())
+    return dA, dB
 
 
 def workspace_size(op: int, m: int, k: int, n: int, dtype: int) -> int:

@@ -50,6 +50,8 @@ def lib():
             L.tsm_grad_a.argtypes = mm
             L.tsm_grad_b.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
             L.tsm2x_split.argtypes = [i64, i64, vp, i64, vp, vp, i64, i32, vp]
+            L.tsm2l_backward.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                         i32, vp, sz, vp]
             L.tsm2x_workspace_size.argtypes = [i32, i64, i64, i64, i32]
             L.tsm2x_workspace_size.restype = sz
             L.tsm2x_error_string.argtypes = [i32]
@@ -60,7 +62,7 @@ def lib():
             L.tsm2x_finalize.argtypes = []
             L.tsm2x_finalize.restype = None
             for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm_grad_a", "tsm_grad_b",
-                      "tsm2x_split", "tsm2x_version"):
+                      "tsm2l_backward", "tsm2x_split", "tsm2x_version"):
                 getattr(L, f).restype = i32
             _lib = L
     return _lib
@@ -73,6 +75,7 @@ def call(fn: str, *args) -> None:
         raise TSMError(fn, rc, L)
 
 
-EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm_grad_a", "tsm_grad_b", "tsm2x_split",
+EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm_grad_a", "tsm_grad_b", "tsm2l_backward",
+           "tsm2x_split",
            "tsm2x_workspace_size", "tsm2x_error_string", "tsm2x_last_hip_error",
            "tsm2x_version", "tsm2x_finalize")

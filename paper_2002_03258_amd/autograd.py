@@ -3,7 +3,8 @@
 Forward: TSM2R (large A) or TSM2L (tall A with k <= 32).  Backward of the
 scalar loss with upstream gradient dC:  dA = dC*B^T (rowtile kernel, a TSM2L
 shape) and dB = A^T*dC (tn kernel, a reduction along m split across
-workgroups and finished in double).
+workgroups and finished in double).  For a TSM2L product needing both
+gradients, one fused pass (tsm2l_backward) reads A and dC once.
 
 Modes:
   "f64", "f32"            A, B, C and both gradients in that precision.
@@ -50,16 +51,21 @@ class TSMMatmul(torch.autograd.Function):
         else:
             ctx.save_for_backward(B, A)
             ctx.planes = None
+        ctx.fused = kd == "L" and mode not in _LOWP and B.shape[1] <= 32
         return C
 
     @staticmethod
     def backward(ctx, dC: torch.Tensor):
-        from . import grad_a, grad_b
+        from . import grad_a, grad_b, tsm2l_backward
         saved = ctx.saved_tensors
         B = saved[0]
         Aop = ctx.planes if ctx.planes is not None else saved[1]
         dA = dB = None
         dC = dC.to(B.dtype)
+        if ctx.fused and ctx.needs_input_grad[0] and ctx.needs_input_grad[1]:
+            # one pass over A and dC for both gradients of a TSM2L product
+            dA, dB = tsm2l_backward(Aop, B, dC)
+            return dA, dB, None, None
         if ctx.needs_input_grad[0]:
             dA = grad_a(dC, B)
         if ctx.needs_input_grad[1]:

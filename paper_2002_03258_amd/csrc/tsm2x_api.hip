@@ -131,6 +131,7 @@ struct TNPlan {
     int64_t groups;
     int S;
     int64_t rslice;
+    int rg;
     size_t ws;
 };
 
@@ -138,12 +139,16 @@ struct TNPlan {
 // WK = 4 wavefronts split the slice.
 TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     TNPlan P{};
-    // rows per wavefront step: 4 * RL * RG for the float kernels (RG = 2),
-    // 32 * RG for the 16-bit form
-    const int64_t RB = plain_dtype(dt) ? 4 * (16 / esize(dt)) * 2 : 64;
+    // rows per wavefront step: 4 * RL * RG for the float kernels, 32 * 2 for
+    // the 16-bit form
+    // G stages of 16*RL rows per wavefront loop iteration (float kernels);
+    // 64 rows per step for the 16-bit form
+    P.rg = (int)env_int("TSM2X_TN_G", 2);
+    if (P.rg != 1 && P.rg != 2 && P.rg != 4) P.rg = 2;
+    const int64_t RB = plain_dtype(dt) ? 16 * (16 / esize(dt)) * P.rg : 64;
     const int NT16 = n <= 16 ? 1 : 2;
     P.groups = cdiv(ncols, 16);
-    const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * 4);
+    const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * 2);
     int64_t S = cdiv(target, P.groups);
     const int64_t s_len = R / (RB * 4 * 8);   // >= 8 steps per wavefront
     if (S > s_len) S = s_len;
@@ -255,7 +260,7 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
         LaunchTN L{};
         L.R = k; L.ncols = m; L.n = n;
         L.X = A; L.ldx = lda; L.Y = B; L.ldy = ldb; L.O = C; L.ldo = ldc;
-        L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
+        L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg;
         if (P.S > 1) split_ws(w, &L.part);
         if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_kernel");
@@ -304,7 +309,7 @@ int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const voi
     LaunchRT L{};
     L.m = m; L.kin = (int)k; L.nout = n; L.X = A; L.ldx = lda; L.Y = B; L.ys_in = 1;
     L.ys_out = ldb; L.O = C; L.ldo = ldc; L.kp = P.kp; L.cols_per_block = (int)P.cpb;
-    L.blocks_x = P.bx; L.blocks_y = P.by;
+    L.blocks_x = P.bx; L.blocks_y = P.by; L.cus = cu_count();
     if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("rowtile_kernel");
 }
@@ -333,7 +338,7 @@ int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc, co
     LaunchRT L{};
     L.m = m; L.kin = (int)n; L.nout = k; L.X = dC; L.ldx = lddc; L.Y = B; L.ys_in = ldb;
     L.ys_out = 1; L.O = dA; L.ldo = ldda; L.kp = P.kp; L.cols_per_block = (int)P.cpb;
-    L.blocks_x = P.bx; L.blocks_y = P.by;
+    L.blocks_x = P.bx; L.blocks_y = P.by; L.cus = cu_count();
     if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("rowtile_kernel");
 }
@@ -365,7 +370,7 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     if (rc) return rc;
     LaunchTN L{};
     L.R = m; L.ncols = k; L.n = n; L.X = A; L.ldx = lda; L.Y = dC; L.ldy = lddc; L.O = dB;
-    L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice;
+    L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg;
     if (P.S > 1) split_ws(w, &L.part);
     if (!plain_dtype(dtype)) {
         if (launch_tn_lp(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
@@ -373,6 +378,46 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     }
     if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("tn_kernel");
+}
+
+int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, const void* dC, int64_t lddc, void* dA, int64_t ldda, void* dB,
+                   int64_t lddb, int dtype, void* ws, size_t ws_bytes, void* stream) {
+    if (m < 0) return -1;
+    if (k < 0) return -2;
+    if (n < 0) return -3;
+    if (!A && m > 0 && k > 0) return -4;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (!B && k > 0 && n > 0) return -6;
+    if (ldb < (k > 1 ? k : 1)) return -7;
+    if (!dC && m > 0 && n > 0) return -8;
+    if (lddc < (m > 1 ? m : 1)) return -9;
+    if (!dA && m > 0 && k > 0) return -10;
+    if (ldda < (m > 1 ? m : 1)) return -11;
+    if (!dB && k > 0 && n > 0) return -12;
+    if (lddb < (k > 1 ? k : 1)) return -13;
+    if (!valid_dtype(dtype)) return -14;
+    if (k > 32 || n > 32 || !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (k == 0) return TSM_SUCCESS;
+    hipStream_t st = (hipStream_t)stream;
+    if (m == 0 || n == 0) {
+        // dA (m x k) is zero when n == 0; dB (k x n) is zero when m == 0
+        if (m > 0) launch_fill_zero(m, k, dA, ldda, dtype, st);
+        if (n > 0) launch_fill_zero(k, n, dB, lddb, dtype, st);
+        return check_launch("fill_zero");
+    }
+    LaunchBwd L{};
+    L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.dC = dC;
+    L.lddc = lddc; L.dA = dA; L.ldda = ldda; L.dB = dB; L.lddb = lddb; L.cus = cu_count();
+    int64_t blocks = 0;
+    launch_tsm2l_bwd(L, dtype, &blocks, st, true);
+    const size_t need = (size_t)blocks * (k <= 16 ? 16 : 32) * (n <= 16 ? 16 : 32) * 8;
+    void* w = nullptr;
+    int rc = get_ws(need, ws, ws_bytes, &w);
+    if (rc) return rc;
+    L.part = (double*)w;
+    if (launch_tsm2l_bwd(L, dtype, &blocks, st, false)) return check_launch("tsm2l_bwd_kernel");
+    return check_launch("tsm2l_bwd_kernel");
 }
 
 int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,

@@ -150,22 +150,43 @@ __device__ __forceinline__ void tn_finish(int64_t ncols, int n, T* __restrict__ 
 
 // Ordered sum of split partials: O[g*W + r, p] = sum over s of
 // part[((g * S + s) * NP + p) * W + r], for rows g*W + r < rows and p < n.
-template <typename T>
+// One thread per output when S is small.  For many slices one wavefront
+// per output: lane l adds slices l, l+64, ... in order, then a butterfly in a
+// fixed pattern combines the lanes, so the result does not depend on timing.
+template <typename T, bool WIDE>
 __global__ __launch_bounds__(256) void split_reduce_kernel(int64_t groups, int S, int NP, int W,
                                                            int64_t rows, int n,
                                                            const double* __restrict__ part,
                                                            T* __restrict__ O, int64_t ldo) {
     const int64_t E = (int64_t)NP * W;
     const int64_t total = groups * E;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g = idx / E, e = idx % E;
-        const int p = (int)(e / W), r = (int)(e % W);
-        const int64_t row = g * W + r;
-        if (p < n && row < rows) {
-            double v = 0.0;
-            for (int s = 0; s < S; ++s) v += part[(g * S + s) * E + e];
-            O[row + p * ldo] = (T)v;
+    if (!WIDE) {
+        for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+             idx += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t g = idx / E, e = idx % E;
+            const int p = (int)(e / W), r = (int)(e % W);
+            const int64_t row = g * W + r;
+            if (p < n && row < rows) {
+                double v = 0.0;
+                for (int s = 0; s < S; ++s) v += part[(g * S + s) * E + e];
+                O[row + p * ldo] = (T)v;
+            }
+        }
+    } else {
+        const int lane = threadIdx.x & (WAVE - 1);
+        const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+        const int64_t nw = (int64_t)gridDim.x * blockDim.x / WAVE;
+        for (int64_t idx = wid; idx < total; idx += nw) {
+            const int64_t g = idx / E, e = idx % E;
+            const int p = (int)(e / W), r = (int)(e % W);
+            const int64_t row = g * W + r;
+            if (p < n && row < rows) {     // uniform across the wavefront
+                double v = 0.0;
+                for (int s = lane; s < S; s += WAVE) v += part[(g * S + s) * E + e];
+#pragma unroll
+                for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+                if (lane == 0) O[row + p * ldo] = (T)v;
+            }
         }
     }
 }

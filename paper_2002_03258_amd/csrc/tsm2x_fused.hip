@@ -1,0 +1,225 @@
+// Fused backward of a TSM2L product C = A*B (A m x k, B k x n, k, n <= 32):
+// one pass over the rows reads A and dC once and produces
+//   dA = dC * B^T   (written row tile by row tile, a TSM2L product with B^T)
+//   dB = A^T * dC   (accumulated in registers, reduced in double at the end)
+// instead of two passes (dC, dA) + (A, dC).
+//
+// Per wavefront and 16*RL*RG-row tile, on the 16x16x4 matrix cores:
+//  dA part (as rowtile): S[rl][kk] = B[16 t + rl, 4 st + kk] held in
+//    registers, T[kk][rl] = dC[row(rl, q), 4 st + kk]; lane l gets
+//    dA[row(rl, q), 16 t + mrow(kk, r)].
+//  dB part (as tn): the tile's rows r = rb + RL*kk + q in steps of 4*RL,
+//    S[rl][kk] = A[r, 16 ta + rl], T[kk][rl] = dC[r, 16 tb + rl]; lane l
+//    accumulates dB[16 ta + mrow(kk, r), 16 tb + rl].
+// dC is read in the two lane layouts; the second read of a tile hits the
+// caches, so HBM sees A, dC and dA once each.  A persistent grid walks the
+// row tiles; each workgroup leaves a double partial of dB, summed in
+// workgroup order by split_reduce_kernel.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tsm2x_device.h"
+#include "tsm2x_internal.h"
+
+namespace tsm {
+
+template <typename T, int NTK, int NTN, int RG, bool VEC>
+__global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
+    int64_t m, int k, int n, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+    int64_t ldb, const T* __restrict__ dC, int64_t lddc, T* __restrict__ dA, int64_t ldda,
+    double* __restrict__ part) {
+    typedef Mfma<T> M;
+    typedef typename M::acc Acc;
+    constexpr int RL = 16 / (int)sizeof(T);
+    constexpr int TR = 16 * RL * RG;
+    constexpr int WPB = 4;
+    constexpr int KSN = 4 * NTN;        // steps of 4 over n (dA part)
+    constexpr int NB = NTK * NTN;       // dB tiles
+    __shared__ double red[WPB][WAVE][4 * NB];
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & 15, kk = lane >> 4;
+    const int w = threadIdx.x / WAVE;
+
+    // B^T as the S operand of the dA part: yv[st][t] = B[16 t + rl, 4 st + kk]
+    T yv[KSN][NTK];
+#pragma unroll
+    for (int st = 0; st < KSN; ++st)
+#pragma unroll
+        for (int t = 0; t < NTK; ++t) {
+            const int j = 16 * t + rl, p = 4 * st + kk;
+            yv[st][t] = (j < k && p < n) ? B[j + (int64_t)p * ldb] : T(0);
+        }
+
+    Acc accb[NTK][NTN];
+#pragma unroll
+    for (int a = 0; a < NTK; ++a)
+#pragma unroll
+        for (int b = 0; b < NTN; ++b) accb[a][b] = Acc{0, 0, 0, 0};
+
+    const int64_t ntiles = (m + TR - 1) / TR;
+    for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles;
+         tile += (int64_t)gridDim.x * WPB) {
+        const int64_t row0 = tile * TR;
+        const bool full = (row0 + TR <= m);
+        // ---- dA = dC * B^T for this tile
+        T xv[KSN][RG][RL];
+#pragma unroll
+        for (int st = 0; st < KSN; ++st) {
+            const int p = 4 * st + kk;
+#pragma unroll
+            for (int g = 0; g < RG; ++g) {
+                const int64_t r = row0 + 16 * RL * g + RL * rl;
+                if (p < n)
+                    load_run<T, RL, VEC>(dC + r + p * lddc, m - r, full, xv[st][g]);
+                else
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) xv[st][g][q] = T(0);
+            }
+        }
+        Acc acca[RG][RL][NTK];
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int q = 0; q < RL; ++q)
+#pragma unroll
+                for (int t = 0; t < NTK; ++t) acca[g][q][t] = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < KSN; ++st)
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int q = 0; q < RL; ++q)
+#pragma unroll
+                    for (int t = 0; t < NTK; ++t)
+                        acca[g][q][t] = M::op(yv[st][t], xv[st][g][q], acca[g][q][t]);
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+            const int64_t r = row0 + 16 * RL * g + RL * rl;
+#pragma unroll
+            for (int t = 0; t < NTK; ++t)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int col = 16 * t + M::mrow(kk, rr);
+                    if (col < k) {
+                        T v[RL];
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) v[q] = acca[g][q][t][rr];
+                        store_run<T, RL, VEC>(dA + r + (int64_t)col * ldda, m - r, full, v);
+                    }
+                }
+        }
+        // ---- dB += A^T * dC over the same rows
+#pragma unroll
+        for (int sb = 0; sb < 4 * RG; ++sb) {
+            const int64_t r = row0 + 4 * RL * sb + RL * kk;
+            const int64_t valid = m - r;
+            const bool f = valid >= RL;
+            T xa[NTK][RL], yd[NTN][RL];
+#pragma unroll
+            for (int a = 0; a < NTK; ++a) {
+                const int c = 16 * a + rl;
+                if (c < k)
+                    load_run<T, RL, VEC>(A + r + (int64_t)c * lda, valid, f, xa[a]);
+                else
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) xa[a][q] = T(0);
+            }
+#pragma unroll
+            for (int b = 0; b < NTN; ++b) {
+                const int p = 16 * b + rl;
+                if (p < n)
+                    load_run<T, RL, VEC>(dC + r + (int64_t)p * lddc, valid, f, yd[b]);
+                else
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) yd[b][q] = T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < RL; ++q)
+#pragma unroll
+                for (int a = 0; a < NTK; ++a)
+#pragma unroll
+                    for (int b = 0; b < NTN; ++b)
+                        accb[a][b] = M::op(xa[a][q], yd[b][q], accb[a][b]);
+        }
+    }
+
+    // workgroup sum of dB in wave order; one partial per workgroup:
+    // part[blk][p][c] with c = 16 a + mrow(kk, r), p = 16 b + rl
+#pragma unroll
+    for (int a = 0; a < NTK; ++a)
+#pragma unroll
+        for (int b = 0; b < NTN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[w][lane][(a * NTN + b) * 4 + r] = (double)accb[a][b][r];
+    __syncthreads();
+    constexpr int NV = 4 * NB;
+    constexpr int W = 16 * NTK, NP = 16 * NTN;
+    for (int e = threadIdx.x; e < WAVE * NV; e += 256) {
+        const int ln = e / NV, vi = e % NV;
+        double v = red[0][ln][vi];
+#pragma unroll
+        for (int ww = 1; ww < WPB; ++ww) v += red[ww][ln][vi];
+        const int ab = vi / 4, r = vi % 4;
+        const int a = ab / NTN, b = ab % NTN;
+        const int c = 16 * a + M::mrow(ln >> 4, r);
+        const int p = 16 * b + (ln & 15);
+        part[((int64_t)blockIdx.x * NP + p) * W + c] = v;
+    }
+}
+
+template <typename K>
+static int fused_occupancy(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
+}
+
+template <typename T, int NTK, int NTN>
+static int bwd_launch(const LaunchBwd& L, int64_t* blocks_out, hipStream_t st, bool plan_only) {
+    constexpr int RG = 2;
+    constexpr int64_t TR = 16 * (16 / (int64_t)sizeof(T)) * RG;
+    static const int occ = fused_occupancy(tsm2l_bwd_kernel<T, NTK, NTN, RG, true>);
+    const int64_t ntiles = (L.m + TR - 1) / TR;
+    int64_t bx = (int64_t)L.cus * occ;
+    const int64_t need = (ntiles + 3) / 4;
+    if (bx > need) bx = need;
+    if (bx < 1) bx = 1;
+    *blocks_out = bx;
+    if (plan_only) return 0;
+    const bool vec = ((uintptr_t)L.A & 15u) == 0 && ((uintptr_t)L.dC & 15u) == 0 &&
+                     ((uintptr_t)L.dA & 15u) == 0 && (L.lda * (int64_t)sizeof(T)) % 16 == 0 &&
+                     (L.lddc * (int64_t)sizeof(T)) % 16 == 0 &&
+                     (L.ldda * (int64_t)sizeof(T)) % 16 == 0;
+    dim3 g((unsigned)bx), b(256);
+    if (vec)
+        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, true>), g, b, 0, st, L.m, (int)L.k,
+                           (int)L.n, (const T*)L.A, L.lda, (const T*)L.B, L.ldb, (const T*)L.dC,
+                           L.lddc, (T*)L.dA, L.ldda, L.part);
+    else
+        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, false>), g, b, 0, st, L.m,
+                           (int)L.k, (int)L.n, (const T*)L.A, L.lda, (const T*)L.B, L.ldb,
+                           (const T*)L.dC, L.lddc, (T*)L.dA, L.ldda, L.part);
+    if (hipGetLastError() != hipSuccess) return 1;
+    return launch_split_reduce(sizeof(T) == 8 ? DT_F64 : DT_F32, 1, (int)bx, 16 * NTN, 16 * NTK,
+                               L.k, (int)L.n, L.part, L.dB, L.lddb, st);
+}
+
+template <typename T>
+static int bwd_dispatch(const LaunchBwd& L, int64_t* blocks, hipStream_t st, bool plan_only) {
+    if (L.k <= 16)
+        return L.n <= 16 ? bwd_launch<T, 1, 1>(L, blocks, st, plan_only)
+                         : bwd_launch<T, 1, 2>(L, blocks, st, plan_only);
+    return L.n <= 16 ? bwd_launch<T, 2, 1>(L, blocks, st, plan_only)
+                     : bwd_launch<T, 2, 2>(L, blocks, st, plan_only);
+}
+
+int launch_tsm2l_bwd(const LaunchBwd& L, int dtype, int64_t* blocks, hipStream_t st,
+                     bool plan_only) {
+    if (dtype == DT_F64) return bwd_dispatch<double>(L, blocks, st, plan_only);
+    if (dtype == DT_F32) return bwd_dispatch<float>(L, blocks, st, plan_only);
+    return 1;
+}
+
+}  // namespace tsm

@@ -45,7 +45,9 @@ struct LaunchRT {           // rowtile: O = X*Y, X m x kin (kin <= 32)
     void* O; int64_t ldo;
     int kp;                 // padded kin: 8, 16 or 32
     int cols_per_block;
-    int64_t blocks_x, blocks_y;
+    int64_t blocks_x;       // upper bound on gridDim.x (0: none)
+    int64_t blocks_y;
+    int cus;                // compute units of the device
 };
 
 struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
@@ -56,6 +58,7 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
     int64_t groups;         // 16-column tiles of the output (gridDim.x)
     int S;                  // reduction slices (gridDim.y)
     int64_t rslice;
+    int rg;                 // stages per wavefront loop iteration (1, 2 or 4)
     double* part;           // S > 1: partial sums (workspace)
 };
 
@@ -67,6 +70,20 @@ int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, vo
 int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
                     int64_t ldb, float* C, int64_t ldc, int dtype, int64_t blocks,
                     hipStream_t st);
+
+struct LaunchBwd {          // fused TSM2L backward: dA = dC*B^T, dB = A^T*dC
+    int64_t m, k, n;
+    const void* A; int64_t lda;
+    const void* B; int64_t ldb;
+    const void* dC; int64_t lddc;
+    void* dA; int64_t ldda;
+    void* dB; int64_t lddb;
+    double* part;           // one k x n double partial per workgroup
+    int cus;
+};
+// plan_only: set *blocks (workgroups, one dB partial each) without launching
+int launch_tsm2l_bwd(const LaunchBwd& L, int dtype, int64_t* blocks, hipStream_t st,
+                     bool plan_only);
 
 int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st);
 struct LaunchTN;

@@ -64,8 +64,14 @@ namespace tsm {
 #define TSM2X_NN_RG32 2
 #endif
 
+// Waves per SIMD each instance is compiled for: three for the 16-column
+// instances (the double one needs the cap to stay within 168 registers).
+template <typename T, int NT16>
+constexpr int nn_waves() { return NT16 == 1 ? 3 : 2; }
+
 template <typename T, int NT16, int RG, int WK, bool VEC, bool PF = TSM2X_NN_PREFETCH>
-__global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
+__global__ __launch_bounds__(WAVE * WK)
+__attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kernel(
     int64_t m, int64_t k, int n, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
     int64_t kslice, double* __restrict__ part, int bvec) {
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_nn_kernel(
 // O[row(rl, q), col0 + 16 t + mrow(kk, r)] in acc[g][q][t][r] with
 // row(rl, q) = row0 + 16*RL*g + RL*rl + q.
 // --------------------------------------------------------------------------
-template <typename T, int KS, int NT16, int RG, bool VEC>
+template <typename T, int KS, int NT16, int RG, bool VEC, bool PF>
 __global__ __launch_bounds__(256) void rowtile_kernel(
     int64_t m, int kin, int64_t nout, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ys_in, int64_t ys_out, T* __restrict__ O,
@@ -244,12 +250,9 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
     const bool one_pass = (cb1 - cb0) <= CW;
     if (one_pass) loadY(cb0);
 
-    const int64_t ntiles = (m + TR - 1) / TR;
-    for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles;
-         tile += (int64_t)gridDim.x * WPB) {
+    auto loadX = [&](int64_t tile, T (&xv)[KS][RG][RL]) {
         const int64_t row0 = tile * TR;
         const bool full = (row0 + TR <= m);
-        T xv[KS][RG][RL];
 #pragma unroll
         for (int st = 0; st < KS; ++st) {
             const int ji = 4 * st + kk;
@@ -263,6 +266,20 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
                     for (int q = 0; q < RL; ++q) xv[st][g][q] = T(0);
             }
         }
+    };
+
+    const int64_t ntiles = (m + TR - 1) / TR;
+    const int64_t tstride = (int64_t)gridDim.x * WPB;
+    int64_t tile = (int64_t)blockIdx.x * WPB + w;
+    T xv[KS][RG][RL];
+    if (tile < ntiles) loadX(tile, xv);
+    for (; tile < ntiles; tile += tstride) {
+        const int64_t row0 = tile * TR;
+        const bool full = (row0 + TR <= m);
+        // the next tile's rows are requested before this tile is multiplied
+        T xn[KS][RG][RL];
+        const bool more = tile + tstride < ntiles;
+        if (PF && more) loadX(tile + tstride, xn);
         for (int64_t c0 = cb0; c0 < cb1; c0 += CW) {
             if (!one_pass) loadY(c0);
             Acc acc[RG][RL][NT16];
@@ -298,6 +315,18 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
                     }
             }
         }
+        if (more) {
+            if (PF) {
+#pragma unroll
+                for (int st = 0; st < KS; ++st)
+#pragma unroll
+                    for (int g = 0; g < RG; ++g)
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) xv[st][g][q] = xn[st][g][q];
+            } else {
+                loadX(tile + tstride, xv);
+            }
+        }
     }
 }
 
@@ -307,14 +336,22 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
 // (X = A^T) and the gradient dB = A^T * dC.
 //
 // D = O tile: S[rl][kk] = X[r, c0 + rl], T[kk][rl] = Y[r, 16 t + rl] with the
-// reduction index r = rb + 4*RL*g + RL*kk + q for step q: lane l loads
-// 16 bytes of X column c0 + rl and of Y column 16 t + rl and feeds element q
-// to step q.  Lane l holds O[c0 + mrow(kk, r), 16 t + rl] in acc[t][r].
+// reduction index r = rb + RL*kk + q for step q, so lane l needs RL
+// consecutive rows of ONE column for each operand.  Loading that directly
+// makes every load instruction touch 16 columns with 64-byte pieces, which
+// (measured) caps HBM reads near 60 %.  Instead each wavefront loads blocks
+// of SR = 16*RL rows with the 4-columns-x-256-bytes pattern of the other
+// kernels (lane (rl, kk) reads rows RL*rl .. of column 4 c + kk), stages
+// them in its own padded LDS tile [column][row], and reads them back in the
+// MFMA layout (16-byte LDS reads, four blocks of 4*RL rows per stage).  LDS operations of one
+// wavefront execute in order, so no barrier is needed between the stage and
+// the read-back.  Lane l holds O[c0 + mrow(kk, r), 16 t + rl] in acc[t][r].
 // The WK wavefronts of a workgroup split the workgroup's slice of R, and
 // workgroups split R again; partials are added in double precision in a
-// fixed order (the last workgroup of a column tile to arrive adds them).
+// fixed order (workgroup level here, across workgroups by
+// split_reduce_kernel).
 // --------------------------------------------------------------------------
-template <typename T, int NT16, int RG, bool VEC>
+template <typename T, int NT16, int G, bool VEC>
 __global__ __launch_bounds__(256) void tn_kernel(
     int64_t R, int64_t ncols, int n, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ O, int64_t ldo,
@@ -323,8 +360,11 @@ __global__ __launch_bounds__(256) void tn_kernel(
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
     constexpr int WK = 4;
-    constexpr int RB = 4 * RL * RG;      // rows per wavefront step
-    constexpr int NV = 4 * NT16;         // accumulator values per lane
+    constexpr int SR = 16 * RL;                // rows per stage
+    constexpr int SROW = SR + RL;              // padded LDS column (16 more bytes)
+    constexpr int NC = 16 + 16 * NT16;         // staged columns: X tile, then Y tiles
+    constexpr int NV = 4 * NT16;
+    __shared__ __align__(16) T lds[WK][NC][SROW];
     __shared__ double red[WK][WAVE][NV];
 
     const int lane = threadIdx.x & (WAVE - 1);
@@ -335,61 +375,82 @@ __global__ __launch_bounds__(256) void tn_kernel(
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t sb0 = (int64_t)s * rslice;
     const int64_t sb1 = (sb0 + rslice < R) ? sb0 + rslice : R;
-    const int64_t lw = rslice / WK;      // multiple of RB
+    const int64_t lw = rslice / WK;            // multiple of G * SR
     const int64_t wb0 = sb0 + w * lw;
     const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
-    const int64_t xc = c0 + rl;          // this lane's X column
-    const bool xok = xc < ncols;
+    T (*tile)[SROW] = lds[w];
 
     Acc acc[NT16];
 #pragma unroll
     for (int t = 0; t < NT16; ++t) acc[t] = Acc{0, 0, 0, 0};
 
-    auto load = [&](int64_t rb, T (&xv)[RG][RL], T (&yv)[RG][NT16][RL]) {
+    // staged column sc: sc < 16 -> X column c0 + sc, else Y column sc - 16
+    auto load = [&](int64_t rb, T (&v)[G][NC / 4][RL]) {
 #pragma unroll
-        for (int g = 0; g < RG; ++g) {
-            const int64_t r = rb + 4 * RL * g + RL * kk;
+        for (int gs = 0; gs < G; ++gs) {
+            const int64_t r = rb + gs * SR + RL * rl;
             const int64_t valid = wb1 - r;
             const bool full = valid >= RL;
-            if (xok)
-                load_run<T, RL, VEC>(X + r + xc * ldx, valid, full, xv[g]);
-            else
 #pragma unroll
-                for (int q = 0; q < RL; ++q) xv[g][q] = T(0);
-#pragma unroll
-            for (int t = 0; t < NT16; ++t) {
-                const int p = 16 * t + rl;
-                if (p < n)
-                    load_run<T, RL, VEC>(Y + r + p * ldy, valid, full, yv[g][t]);
+            for (int cg = 0; cg < NC / 4; ++cg) {
+                const int sc = 4 * cg + kk;
+                const T* src;
+                bool ok;
+                if (sc < 16) {
+                    src = X + r + (c0 + sc) * ldx;
+                    ok = c0 + sc < ncols;
+                } else {
+                    src = Y + r + (int64_t)(sc - 16) * ldy;
+                    ok = sc - 16 < n;
+                }
+                if (ok)
+                    load_run<T, RL, VEC>(src, valid, full, v[gs][cg]);
                 else
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) yv[g][t][q] = T(0);
+                    for (int q = 0; q < RL; ++q) v[gs][cg][q] = T(0);
             }
         }
     };
 
     if (wb1 > wb0) {
-        const int64_t nst = (wb1 - wb0 + RB - 1) / RB;
-        T xv[RG][RL], yv[RG][NT16][RL];
-        load(wb0, xv, yv);
-        for (int64_t i = 0; i < nst; ++i) {
-            T xn[RG][RL], yn[RG][NT16][RL];
-            if (i + 1 < nst) load(wb0 + (i + 1) * RB, xn, yn);
+        const int64_t nit = (wb1 - wb0 + G * SR - 1) / (G * SR);
+        T v[G][NC / 4][RL];
+        load(wb0, v);
+        for (int64_t it = 0; it < nit; ++it) {
+            T vn[G][NC / 4][RL];
+            if (it + 1 < nit) load(wb0 + (it + 1) * G * SR, vn);
 #pragma unroll
-            for (int g = 0; g < RG; ++g)
+            for (int gs = 0; gs < G; ++gs) {
+                // stage: column 4 cg + kk, rows RL*rl .. RL*rl + RL - 1
 #pragma unroll
-                for (int q = 0; q < RL; ++q)
+                for (int cg = 0; cg < NC / 4; ++cg) {
+                    typedef typename VecOf<T, RL>::type V;
+                    V x;
 #pragma unroll
-                    for (int t = 0; t < NT16; ++t)
-                        acc[t] = M::op(xv[g][q], yv[g][t][q], acc[t]);
-#pragma unroll
-            for (int g = 0; g < RG; ++g)
-#pragma unroll
-                for (int q = 0; q < RL; ++q) {
-                    xv[g][q] = xn[g][q];
-#pragma unroll
-                    for (int t = 0; t < NT16; ++t) yv[g][t][q] = yn[g][t][q];
+                    for (int q = 0; q < RL; ++q) x[q] = v[gs][cg][q];
+                    *reinterpret_cast<V*>(&tile[4 * cg + kk][RL * rl]) = x;
                 }
+                // read back in four blocks of 4*RL rows: X column rl and Y
+                // columns 16 t + rl, rows 4*RL*h + RL*kk + q
+                typedef typename VecOf<T, RL>::type V;
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const V xs = *reinterpret_cast<const V*>(&tile[rl][4 * RL * h + RL * kk]);
+#pragma unroll
+                    for (int t = 0; t < NT16; ++t) {
+                        const V ys =
+                            *reinterpret_cast<const V*>(&tile[16 + 16 * t + rl][4 * RL * h + RL * kk]);
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) acc[t] = M::op(xs[q], ys[q], acc[t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int gs = 0; gs < G; ++gs)
+#pragma unroll
+                for (int cg = 0; cg < NC / 4; ++cg)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) v[gs][cg][q] = vn[gs][cg][q];
         }
     }
 
@@ -410,8 +471,6 @@ __global__ void fill_zero_kernel(int64_t m, int64_t n, T* __restrict__ C, int64_
 // --------------------------------------------------------------------------
 // Launchers
 // --------------------------------------------------------------------------
-static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
-
 // Resident workgroups per CU of a kernel instance (queried once).
 template <typename K>
 static int occupancy(K kernel, int threads) {
@@ -420,6 +479,8 @@ static int occupancy(K kernel, int threads) {
         nb = 1;
     return nb;
 }
+
+static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 struct NNInstance {
     const void* fn;
@@ -502,18 +563,37 @@ int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
     return 0;
 }
 
-template <typename T, int KS, int NT16, int RG>
-static int rowtile_launch(const LaunchRT& L, bool vec, hipStream_t st) {
-    dim3 grid((unsigned)L.blocks_x, (unsigned)L.blocks_y), block(256);
+template <typename T, int KS, int NT16, int RG, bool PF>
+static int rowtile_launch_pf(const LaunchRT& L, bool vec, hipStream_t st) {
+    // persistent grid: as many workgroups as fit at once (queried occupancy),
+    // but no more than there are groups of 4 row tiles
+    static const int occ_v = occupancy(rowtile_kernel<T, KS, NT16, RG, true, PF>, 256);
+    static const int occ_s = occupancy(rowtile_kernel<T, KS, NT16, RG, false, PF>, 256);
+    constexpr int64_t TR = 16 * (16 / (int64_t)sizeof(T)) * RG;
+    const int64_t ntiles = (L.m + TR - 1) / TR;
+    int64_t bx = (int64_t)L.cus * (vec ? occ_v : occ_s) / (L.blocks_y > 0 ? L.blocks_y : 1);
+    const int64_t need = (ntiles + 3) / 4;
+    if (bx > need) bx = need;
+    if (L.blocks_x > 0 && bx > L.blocks_x) bx = L.blocks_x;
+    if (bx < 1) bx = 1;
+    dim3 grid((unsigned)bx, (unsigned)L.blocks_y), block(256);
     if (vec)
-        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, true>), grid, block, 0, st, L.m, L.kin,
-                           L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
+        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, true, PF>), grid, block, 0, st, L.m,
+                           L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
                            (T*)L.O, L.ldo, (int64_t)L.cols_per_block);
     else
-        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, false>), grid, block, 0, st, L.m,
+        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, false, PF>), grid, block, 0, st, L.m,
                            L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in,
                            L.ys_out, (T*)L.O, L.ldo, (int64_t)L.cols_per_block);
     return 0;
+}
+
+template <typename T, int KS, int NT16, int RG>
+static int rowtile_launch(const LaunchRT& L, bool vec, hipStream_t st) {
+    static const char* e = std::getenv("TSM2X_RT_PF");
+    const bool pf = e && *e == '1';   // measured: the extra waves beat the prefetch
+    return pf ? rowtile_launch_pf<T, KS, NT16, RG, true>(L, vec, st)
+              : rowtile_launch_pf<T, KS, NT16, RG, false>(L, vec, st);
 }
 
 template <typename T>
@@ -536,15 +616,15 @@ int launch_rowtile(const LaunchRT& L, int dtype, hipStream_t st) {
     return 1;
 }
 
-template <typename T, int NT16>
+template <typename T, int NT16, int G>
 static int tn_launch(const LaunchTN& L, bool vec, hipStream_t st) {
     dim3 grid((unsigned)L.groups, (unsigned)L.S), block(256);
     if (vec)
-        hipLaunchKernelGGL((tn_kernel<T, NT16, 2, true>), grid, block, 0, st, L.R, L.ncols,
+        hipLaunchKernelGGL((tn_kernel<T, NT16, G, true>), grid, block, 0, st, L.R, L.ncols,
                            (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
                            L.rslice, L.part);
     else
-        hipLaunchKernelGGL((tn_kernel<T, NT16, 2, false>), grid, block, 0, st, L.R, L.ncols,
+        hipLaunchKernelGGL((tn_kernel<T, NT16, G, false>), grid, block, 0, st, L.R, L.ncols,
                            (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
                            L.rslice, L.part);
     return 0;
@@ -555,7 +635,12 @@ static int tn_dispatch(const LaunchTN& L, hipStream_t st) {
     const bool vec = aligned16(L.X) && aligned16(L.Y) &&
                      ((L.ldx * (int64_t)sizeof(T)) % 16 == 0) &&
                      ((L.ldy * (int64_t)sizeof(T)) % 16 == 0);
-    const int rc = L.n <= 16 ? tn_launch<T, 1>(L, vec, st) : tn_launch<T, 2>(L, vec, st);
+    // G stages of 16*RL rows per loop iteration (loads for the next iteration
+    // are in flight while the current one is staged and multiplied)
+    int rc = 1;
+    if (L.rg == 4) rc = L.n <= 16 ? tn_launch<T, 1, 4>(L, vec, st) : tn_launch<T, 2, 4>(L, vec, st);
+    else if (L.rg == 2) rc = L.n <= 16 ? tn_launch<T, 1, 2>(L, vec, st) : tn_launch<T, 2, 2>(L, vec, st);
+    else rc = L.n <= 16 ? tn_launch<T, 1, 1>(L, vec, st) : tn_launch<T, 2, 1>(L, vec, st);
     if (rc || L.S <= 1) return rc;
     return launch_split_reduce(sizeof(T) == 8 ? DT_F64 : DT_F32, L.groups, L.S,
                                L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n, L.part, L.O, L.ldo, st);
@@ -570,15 +655,26 @@ int launch_tn(const LaunchTN& L, int dtype, hipStream_t st) {
 int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t rows, int n,
                         const double* part, void* O, int64_t ldo, hipStream_t st) {
     const int64_t total = groups * NP * W;
-    int64_t blocks = (total + 255) / 256;
+    const bool wide = S >= 16;
+    int64_t blocks = wide ? (total + 3) / 4 : (total + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    if (dtype == DT_F64)
-        hipLaunchKernelGGL(split_reduce_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
-                           groups, S, NP, W, rows, n, part, (double*)O, ldo);
-    else
-        hipLaunchKernelGGL(split_reduce_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
-                           groups, S, NP, W, rows, n, part, (float*)O, ldo);
+    const dim3 g((unsigned)blocks), b(256);
+    if (dtype == DT_F64) {
+        if (wide)
+            hipLaunchKernelGGL((split_reduce_kernel<double, true>), g, b, 0, st, groups, S, NP, W,
+                               rows, n, part, (double*)O, ldo);
+        else
+            hipLaunchKernelGGL((split_reduce_kernel<double, false>), g, b, 0, st, groups, S, NP,
+                               W, rows, n, part, (double*)O, ldo);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((split_reduce_kernel<float, true>), g, b, 0, st, groups, S, NP, W,
+                               rows, n, part, (float*)O, ldo);
+        else
+            hipLaunchKernelGGL((split_reduce_kernel<float, false>), g, b, 0, st, groups, S, NP, W,
+                               rows, n, part, (float*)O, ldo);
+    }
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

@@ -226,3 +226,23 @@ def test_shared_workspace_across_shapes(dev, dtype):
         dBref = oracle.matmul(Acols.T, host_matrix(40 + i, si.STREAM_DC, m, n, dtype,
                                                    dist="normal"))
         assert err(to_np(dB[cols]), dBref) <= TOL[dtype], ("grad_b", m, k, n)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (1000, 16, 16), (70001, 16, 16), (4097, 33 - 1, 5),
+                                   (2500, 7, 29), (66000, 32, 32), (300, 17, 3)])
+def test_tsm2l_backward_fused(dev, dtype, m, k, n):
+    seed = 600 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, dtype, dev)
+    B = dev_matrix(seed, si.STREAM_B, k, n, dtype, dev)
+    dC = dev_matrix(seed, si.STREAM_DC, m, n, dtype, dev, dist="normal")
+    dA, dB = tsm.tsm2l_backward(A, B, dC)
+    rA, rB = oracle.grad(host_matrix(seed, si.STREAM_A, m, k, dtype),
+                         host_matrix(seed, si.STREAM_B, k, n, dtype),
+                         host_matrix(seed, si.STREAM_DC, m, n, dtype, dist="normal"))
+    assert err(to_np(dA), rA) <= TOL[dtype]
+    assert err(to_np(dB), rB) <= TOL[dtype]
+    # same dA bits as the separate kernel (same products in the same order)
+    assert torch.equal(dA, tsm.grad_a(dC, B))
+    dA2, dB2 = tsm.tsm2l_backward(A, B, dC)
+    assert torch.equal(dA, dA2) and torch.equal(dB, dB2)

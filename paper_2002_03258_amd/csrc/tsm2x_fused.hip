@@ -11,10 +11,11 @@
 //  dB part (as tn): the tile's rows r = rb + RL*kk + q in steps of 4*RL,
 //    S[rl][kk] = A[r, 16 ta + rl], T[kk][rl] = dC[r, 16 tb + rl]; lane l
 //    accumulates dB[16 ta + mrow(kk, r), 16 tb + rl].
-// dC is read in the two lane layouts; the second read of a tile hits the
-// caches, so HBM sees A, dC and dA once each.  A persistent grid walks the
-// row tiles; each workgroup leaves a double partial of dB, summed in
-// workgroup order by split_reduce_kernel.
+// A and dC are loaded once, in the 4-columns-x-256-bytes pattern; the dB
+// part re-reads them from a wavefront-private LDS tile in its own layout.
+// HBM sees A, dC and dA once each.  A persistent grid walks the row tiles;
+// each workgroup leaves a double partial of dB, summed in workgroup order by
+// split_reduce_kernel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,16 +31,23 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
     double* __restrict__ part) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
+    typedef typename VecOf<T, 16 / sizeof(T)>::type V;
     constexpr int RL = 16 / (int)sizeof(T);
     constexpr int TR = 16 * RL * RG;
     constexpr int WPB = 4;
-    constexpr int KSN = 4 * NTN;        // steps of 4 over n (dA part)
+    constexpr int KSN = 4 * NTN;        // steps of 4 over n (dA part, dC columns)
+    constexpr int KSK = 4 * NTK;        // steps of 4 over k (A columns)
     constexpr int NB = NTK * NTN;       // dB tiles
+    constexpr int KP = 16 * NTK, NP = 16 * NTN;
+    constexpr int SR = 16 * RL;         // rows per staged block
+    constexpr int SROW = SR + RL;       // padded LDS column
+    __shared__ __align__(16) T lds[WPB][KP + NP][SROW];
     __shared__ double red[WPB][WAVE][4 * NB];
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
+    T (*tile)[SROW] = lds[w];
 
     // B^T as the S operand of the dA part: yv[st][t] = B[16 t + rl, 4 st + kk]
     T yv[KSN][NTK];
@@ -58,25 +66,36 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
         for (int b = 0; b < NTN; ++b) accb[a][b] = Acc{0, 0, 0, 0};
 
     const int64_t ntiles = (m + TR - 1) / TR;
-    for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles;
-         tile += (int64_t)gridDim.x * WPB) {
-        const int64_t row0 = tile * TR;
+    for (int64_t tile_i = (int64_t)blockIdx.x * WPB + w; tile_i < ntiles;
+         tile_i += (int64_t)gridDim.x * WPB) {
+        const int64_t row0 = tile_i * TR;
         const bool full = (row0 + TR <= m);
-        // ---- dA = dC * B^T for this tile
-        T xv[KSN][RG][RL];
+        // rows RL*rl + q of each 16*RL-row block g, columns 4 st + kk: the
+        // 4-columns-x-256-bytes load pattern, for dC and for A
+        T xv[KSN][RG][RL], xa[KSK][RG][RL];
 #pragma unroll
-        for (int st = 0; st < KSN; ++st) {
-            const int p = 4 * st + kk;
+        for (int g = 0; g < RG; ++g) {
+            const int64_t r = row0 + SR * g + RL * rl;
 #pragma unroll
-            for (int g = 0; g < RG; ++g) {
-                const int64_t r = row0 + 16 * RL * g + RL * rl;
+            for (int st = 0; st < KSN; ++st) {
+                const int p = 4 * st + kk;
                 if (p < n)
                     load_run<T, RL, VEC>(dC + r + p * lddc, m - r, full, xv[st][g]);
                 else
 #pragma unroll
                     for (int q = 0; q < RL; ++q) xv[st][g][q] = T(0);
             }
+#pragma unroll
+            for (int st = 0; st < KSK; ++st) {
+                const int c = 4 * st + kk;
+                if (c < k)
+                    load_run<T, RL, VEC>(A + r + (int64_t)c * lda, m - r, full, xa[st][g]);
+                else
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) xa[st][g][q] = T(0);
+            }
         }
+        // ---- dA = dC * B^T for this tile
         Acc acca[RG][RL][NTK];
 #pragma unroll
         for (int g = 0; g < RG; ++g)
@@ -95,7 +114,7 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
                         acca[g][q][t] = M::op(yv[st][t], xv[st][g][q], acca[g][q][t]);
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
-            const int64_t r = row0 + 16 * RL * g + RL * rl;
+            const int64_t r = row0 + SR * g + RL * rl;
 #pragma unroll
             for (int t = 0; t < NTK; ++t)
 #pragma unroll
@@ -109,38 +128,42 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
                     }
                 }
         }
-        // ---- dB += A^T * dC over the same rows
+        // ---- dB += A^T * dC over the same rows: stage each 16*RL-row block
+        // in this wavefront's LDS tile [column][row] (A columns, then dC
+        // columns) and read it back with the reduction index on kk
 #pragma unroll
-        for (int sb = 0; sb < 4 * RG; ++sb) {
-            const int64_t r = row0 + 4 * RL * sb + RL * kk;
-            const int64_t valid = m - r;
-            const bool f = valid >= RL;
-            T xa[NTK][RL], yd[NTN][RL];
+        for (int g = 0; g < RG; ++g) {
 #pragma unroll
-            for (int a = 0; a < NTK; ++a) {
-                const int c = 16 * a + rl;
-                if (c < k)
-                    load_run<T, RL, VEC>(A + r + (int64_t)c * lda, valid, f, xa[a]);
-                else
+            for (int st = 0; st < KSK; ++st) {
+                V x;
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) xa[a][q] = T(0);
+                for (int q = 0; q < RL; ++q) x[q] = xa[st][g][q];
+                *reinterpret_cast<V*>(&tile[4 * st + kk][RL * rl]) = x;
             }
 #pragma unroll
-            for (int b = 0; b < NTN; ++b) {
-                const int p = 16 * b + rl;
-                if (p < n)
-                    load_run<T, RL, VEC>(dC + r + (int64_t)p * lddc, valid, f, yd[b]);
-                else
+            for (int st = 0; st < KSN; ++st) {
+                V x;
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) yd[b][q] = T(0);
+                for (int q = 0; q < RL; ++q) x[q] = xv[st][g][q];
+                *reinterpret_cast<V*>(&tile[KP + 4 * st + kk][RL * rl]) = x;
             }
 #pragma unroll
-            for (int q = 0; q < RL; ++q)
+            for (int h = 0; h < 4; ++h) {
+                V xs[NTK], ys[NTN];
 #pragma unroll
                 for (int a = 0; a < NTK; ++a)
+                    xs[a] = *reinterpret_cast<const V*>(&tile[16 * a + rl][4 * RL * h + RL * kk]);
 #pragma unroll
-                    for (int b = 0; b < NTN; ++b)
-                        accb[a][b] = M::op(xa[a][q], yd[b][q], accb[a][b]);
+                for (int b = 0; b < NTN; ++b)
+                    ys[b] = *reinterpret_cast<const V*>(&tile[KP + 16 * b + rl][4 * RL * h + RL * kk]);
+#pragma unroll
+                for (int q = 0; q < RL; ++q)
+#pragma unroll
+                    for (int a = 0; a < NTK; ++a)
+#pragma unroll
+                        for (int b = 0; b < NTN; ++b)
+                            accb[a][b] = M::op(xs[a][q], ys[b][q], accb[a][b]);
+            }
         }
     }
 
@@ -154,7 +177,6 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
             for (int r = 0; r < 4; ++r) red[w][lane][(a * NTN + b) * 4 + r] = (double)accb[a][b][r];
     __syncthreads();
     constexpr int NV = 4 * NB;
-    constexpr int W = 16 * NTK, NP = 16 * NTN;
     for (int e = threadIdx.x; e < WAVE * NV; e += 256) {
         const int ln = e / NV, vi = e % NV;
         double v = red[0][ln][vi];
@@ -164,7 +186,7 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
         const int a = ab / NTN, b = ab % NTN;
         const int c = 16 * a + M::mrow(ln >> 4, r);
         const int p = 16 * b + (ln & 15);
-        part[((int64_t)blockIdx.x * NP + p) * W + c] = v;
+        part[((int64_t)blockIdx.x * NP + p) * KP + c] = v;
     }
 }
 

@@ -55,9 +55,8 @@ def es(dtype) -> int:
     return 8 if dtype == torch.float64 else 4
 
 
-def nn_kernel_name(dtype, n) -> str:
-    t = "double" if dtype == torch.float64 else "float"
-    return "tsm2r_nn_kernel<%s, %d, 2, 4, true, true>" % (t, 1 if n <= 16 else 2)
+def nn_kernel_name(dtype, m, n) -> str:
+    return tsm.kernel_name(tsm.OP_TSM2R, m, m, n, tsm.F64 if dtype == torch.float64 else tsm.F32)
 
 
 def src_hash() -> str:
@@ -76,7 +75,7 @@ def make_r_inputs(dev):
                 calls.append(dict(dtype=dtype, m=m, k=m, n=n, A=A, B=B, C=C, seed=seed,
                                   workload="%s:%d:%d" % ("f64" if dtype == torch.float64 else "f32", m, n),
                                   bytes=(m * m + m * n + m * n) * es(dtype),
-                                  kernel=nn_kernel_name(dtype, n)))
+                                  kernel=nn_kernel_name(dtype, m, n)))
     return calls
 
 
@@ -374,7 +373,7 @@ def main():
         for _ in range(5):
             tsm.tsm2r(A, B, out=C)
         torch.cuda.synchronize()
-        print("launched %s 5 times on m = k = %d, n = %d" % (nn_kernel_name(dtype, n), m, n),
+        print("launched %s 5 times on m = k = %d, n = %d" % (nn_kernel_name(dtype, m, n), m, n),
               flush=True)
         return
 

@@ -170,6 +170,13 @@ int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi,
 size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n,
                             int dtype);
 
+/* Name of the main kernel a call (op, m, k, n, dtype) launches, as
+ * profilers print it (for matching timings with profiler summaries), with
+ * A 16-byte aligned and lda a multiple of 16 bytes.  Static storage; NULL
+ * for ops other than TSM_OP_TSM2R, the 16-bit forms, or empty or
+ * unsupported shapes. */
+const char* tsm2x_kernel_name(int op, int64_t m, int64_t k, int64_t n, int dtype);
+
 /* Static description of an error code (never NULL). */
 const char* tsm2x_error_string(int code);
 

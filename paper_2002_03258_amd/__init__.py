@@ -11,12 +11,13 @@ from __future__ import annotations
 import torch
 
 from . import _lib
-from ._lib import (BF16, BF16_SPLIT, COL_MAJOR, F16, F16_SPLIT, F32, F64,
-                   ROW_MAJOR, TSMError)
+from ._lib import (BF16, BF16_SPLIT, COL_MAJOR, F16, F16_SPLIT, F32, F64, OP_GRAD_A,
+                   OP_GRAD_B, OP_TSM2L, OP_TSM2R, OP_TSM2R_ROWMAJOR, ROW_MAJOR, TSMError)
 
 __all__ = ["tsm2r", "tsm2l", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA", "colmajor",
-           "empty_colmajor", "workspace_size", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
-           "BF16_SPLIT", "F16_SPLIT"]
+           "empty_colmajor", "workspace_size", "kernel_name", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
+           "BF16_SPLIT", "F16_SPLIT", "OP_TSM2R", "OP_TSM2L", "OP_GRAD_A", "OP_GRAD_B",
+           "OP_TSM2R_ROWMAJOR"]
 
 _DT = {torch.float64: F64, torch.float32: F32}
 
@@ -224,6 +225,12 @@ def tsm2l_backward(A: torch.Tensor, B: torch.Tensor, dC: torch.Tensor):
 
 def workspace_size(op: int, m: int, k: int, n: int, dtype: int) -> int:
     return int(_lib.lib().tsm2x_workspace_size(op, m, k, n, dtype))
+
+
+def kernel_name(op: int, m: int, k: int, n: int, dtype: int):
+    """Name of the main kernel the call launches (TSM2R, plain types), or None."""
+    r = _lib.lib().tsm2x_kernel_name(op, m, k, n, dtype)
+    return r.decode() if r else None
 
 
 from .autograd import TSMMatmul, matmul  # noqa: E402,F401

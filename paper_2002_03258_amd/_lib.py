@@ -54,6 +54,8 @@ def lib():
                                          i32, vp, sz, vp]
             L.tsm2x_workspace_size.argtypes = [i32, i64, i64, i64, i32]
             L.tsm2x_workspace_size.restype = sz
+            L.tsm2x_kernel_name.argtypes = [i32, i64, i64, i64, i32]
+            L.tsm2x_kernel_name.restype = ctypes.c_char_p
             L.tsm2x_error_string.argtypes = [i32]
             L.tsm2x_error_string.restype = ctypes.c_char_p
             L.tsm2x_last_hip_error.argtypes = []
@@ -77,5 +79,5 @@ def call(fn: str, *args) -> None:
 
 EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm_grad_a", "tsm_grad_b", "tsm2l_backward",
            "tsm2x_split",
-           "tsm2x_workspace_size", "tsm2x_error_string", "tsm2x_last_hip_error",
+           "tsm2x_workspace_size", "tsm2x_kernel_name", "tsm2x_error_string", "tsm2x_last_hip_error",
            "tsm2x_version", "tsm2x_finalize")

@@ -195,8 +195,6 @@ int get_ws(size_t need, void* user, size_t user_bytes, void** out) {
     return TSM_SUCCESS;
 }
 
-void split_ws(void* ws, double** part) { *part = (double*)ws; }
-
 // Validation of (m, k, n, A, lda, B, ldb, C, ldc, dtype) for C = A*B with
 // column-major (or, for `rowA`, row-major) A.  `base` is the position of m.
 int check_mm(int base, int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
@@ -247,8 +245,8 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
         L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C;
         L.ldc = ldc; L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S;
         L.kslice = P.kslice;
-        if (P.S > 1) split_ws(w, &L.part);
-        if (launch_tsm2r_lp(L, dtype, st)) return check_launch("tsm2r_lp_kernel");
+        if (P.S > 1) L.part = (double*)w;
+        launch_tsm2r_lp(L, dtype, st);
         return check_launch("tsm2r_lp_kernel");
     }
     if (rowA) {
@@ -261,7 +259,7 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
         L.R = k; L.ncols = m; L.n = n;
         L.X = A; L.ldx = lda; L.Y = B; L.ldy = ldb; L.O = C; L.ldo = ldc;
         L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg;
-        if (P.S > 1) split_ws(w, &L.part);
+        if (P.S > 1) L.part = (double*)w;
         if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_kernel");
     }
@@ -273,7 +271,7 @@ int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t 
     L.fn = P.fn;
     L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C; L.ldc = ldc;
     L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
-    if (P.S > 1) split_ws(w, &L.part);
+    if (P.S > 1) L.part = (double*)w;
     if (launch_tsm2r_nn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("tsm2r_nn_kernel");
 }
@@ -371,7 +369,7 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     LaunchTN L{};
     L.R = m; L.ncols = k; L.n = n; L.X = A; L.ldx = lda; L.Y = dC; L.ldy = lddc; L.O = dB;
     L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg;
-    if (P.S > 1) split_ws(w, &L.part);
+    if (P.S > 1) L.part = (double*)w;
     if (!plain_dtype(dtype)) {
         if (launch_tn_lp(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_lp_kernel");
@@ -416,7 +414,7 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, 
     int rc = get_ws(need, ws, ws_bytes, &w);
     if (rc) return rc;
     L.part = (double*)w;
-    if (launch_tsm2l_bwd(L, dtype, &blocks, st, false)) return check_launch("tsm2l_bwd_kernel");
+    launch_tsm2l_bwd(L, dtype, &blocks, st, false);
     return check_launch("tsm2l_bwd_kernel");
 }
 
@@ -454,6 +452,13 @@ size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n, int dtype) 
         case TSM_OP_GRAD_B: return plan_tn(m, k, n, dtype, cus).ws;
         default: return 0;
     }
+}
+
+const char* tsm2x_kernel_name(int op, int64_t m, int64_t k, int64_t n, int dtype) {
+    if (op != TSM_OP_TSM2R || m <= 0 || k <= 0 || n <= 0 || n > 32 || !plain_dtype(dtype))
+        return nullptr;
+    NNPlan P{};
+    return plan_tsm2r(m, k, n, dtype, cu_count(), true, &P) ? nullptr : P.name;
 }
 
 const char* tsm2x_error_string(int code) {

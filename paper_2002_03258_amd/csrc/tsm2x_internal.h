@@ -11,6 +11,7 @@ enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3, DT_BF16_SPLIT = 4, DT_F1
 // J*NP accumulators per lane, at most 64.
 struct NNPlan {             // TSM2R launch plan (column-major A)
     const void* fn;         // kernel instance
+    const char* name;       // its name as profilers print it
     int np;                 // padded n
     int tile_rows;
     int64_t tiles;          // row tiles (gridDim.x)

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdio>
 #include <cstdlib>
 
 #include "tsm2x_internal.h"
@@ -42,18 +43,18 @@ namespace tsm {
 //
 // Outer-product form of the Design of TSM2R (Algorithm 2) on the matrix
 // cores: C^T = B^T * A^T.  S is a 16 x 4 block of B^T (lane l: B[j, 16t+rl]),
-// T a 4 x 16 block of A^T.  A 16-column group at j0 is consumed in steps
-// st = 0..3 with columns j = j0 + 4*kk + st; a lane's four B values of a
-// group, B[j0+4kk .. j0+4kk+3, 16t+rl], are contiguous in B's column.  The
-// next group's A and B are loaded while the current one is multiplied (the
-// prefetching of Algorithm 4).  Lane l ends up with
+// T a 4 x 16 block of A^T.  A chunk of 4*ST columns at j0 is consumed in
+// steps st = 0..ST-1 with columns j = j0 + ST*kk + st; a lane's ST B values
+// of a chunk, B[j0+ST*kk .. j0+ST*kk+ST-1, 16t+rl], are contiguous in B's
+// column.  The next chunk's A and B are loaded while the current one is
+// multiplied (the prefetching of Algorithm 4).  Lane l ends up with
 // C[row0 + 16*RL*g + RL*rl + q, 16t + mrow(kk, r)] in acc[g][q][t][r].
 //
 // The k range is split across the WK wavefronts of a workgroup and across
 // workgroups; the partial sums are added in double precision in a fixed
 // order (in LDS within the workgroup, then by split_reduce_kernel).
 // --------------------------------------------------------------------------
-// Explicit prefetch of the next 16-column group (Algorithm 4's nextA/nextB).
+// Explicit prefetch of the next chunk (Algorithm 4's nextA/nextB).
 #ifndef TSM2X_NN_PREFETCH
 #define TSM2X_NN_PREFETCH 1
 #endif
@@ -63,13 +64,20 @@ namespace tsm {
 #ifndef TSM2X_NN_RG32
 #define TSM2X_NN_RG32 2
 #endif
+// MFMA steps per chunk (a chunk is 4*ST columns)
+#ifndef TSM2X_NN_ST64
+#define TSM2X_NN_ST64 4
+#endif
+#ifndef TSM2X_NN_ST32
+#define TSM2X_NN_ST32 4
+#endif
 
 // Waves per SIMD each instance is compiled for: three for the 16-column
 // instances (the double one needs the cap to stay within 168 registers).
 template <typename T, int NT16>
 constexpr int nn_waves() { return NT16 == 1 ? 3 : 2; }
 
-template <typename T, int NT16, int RG, int WK, bool VEC, bool PF = TSM2X_NN_PREFETCH>
+template <typename T, int NT16, int RG, int ST, int WK, bool VEC, bool PF = TSM2X_NN_PREFETCH>
 __global__ __launch_bounds__(WAVE * WK)
 __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kernel(
     int64_t m, int64_t k, int n, const T* __restrict__ A, int64_t lda,
@@ -79,8 +87,11 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
     constexpr int TR = 16 * RL * RG;     // rows per tile
+    constexpr int CW = 4 * ST;           // columns per chunk
     constexpr int NP = 16 * NT16;
     constexpr int PG = 4;
+    // B run of a lane: ST values in vector loads of at most 16 bytes
+    constexpr int BW = ST * (int)sizeof(T) > 16 ? RL : ST;
     static_assert(WK * PG * TR * 8 <= 32768, "LDS budget");
     __shared__ __align__(16) unsigned char smem[WK * PG * TR * 8];
 
@@ -105,10 +116,10 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
 #pragma unroll
             for (int t = 0; t < NT16; ++t) acc[g][q][t] = Acc{0, 0, 0, 0};
 
-    auto loadA = [&](int64_t j0, T (&av)[4][RG][RL]) {
+    auto loadA = [&](int64_t j0, T (&av)[ST][RG][RL]) {
 #pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            const int64_t j = j0 + 4 * kk + st;
+        for (int st = 0; st < ST; ++st) {
+            const int64_t j = j0 + ST * kk + st;
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
                 const int64_t r = row0 + 16 * RL * g + RL * rl;
@@ -120,47 +131,48 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
             }
         }
     };
-    // a lane's four B values of a group are contiguous in B's column
-    auto loadB = [&](int64_t j0, T (&bv)[NT16][4]) {
+    // a lane's ST values of B in a chunk are contiguous in B's column; B is
+    // re-read by every row tile, so these are ordinary (cached) loads
+    auto loadB = [&](int64_t j0, T (&bv)[NT16][ST]) {
 #pragma unroll
         for (int t = 0; t < NT16; ++t) {
             const int p = 16 * t + rl;
-            const int64_t jb = j0 + 4 * kk;
+            const int64_t jb = j0 + ST * kk;
             const T* __restrict__ src = B + jb + (int64_t)p * ldb;
-            if (p < n && bvec && jb + 4 <= wk1) {
+            if (p < n && bvec && jb + ST <= wk1) {
+                typedef typename VecOf<T, BW>::type V;
 #pragma unroll
-                for (int h = 0; h < 4 / RL + (RL > 4 ? 1 : 0); ++h) {
-                    T v[RL < 4 ? RL : 4];
-                    load_run<T, (RL < 4 ? RL : 4), true>(src + h * RL, RL, true, v);
+                for (int h = 0; h < ST / BW; ++h) {
+                    const V v = *reinterpret_cast<const V*>(src + h * BW);
 #pragma unroll
-                    for (int e = 0; e < (RL < 4 ? RL : 4); ++e) bv[t][h * RL + e] = v[e];
+                    for (int e = 0; e < BW; ++e) bv[t][h * BW + e] = v[e];
                 }
             } else {
 #pragma unroll
-                for (int st = 0; st < 4; ++st)
+                for (int st = 0; st < ST; ++st)
                     bv[t][st] = (p < n && jb + st < wk1) ? src[st] : T(0);
             }
         }
     };
 
     if (wk1 > wk0) {
-        const int ng = (int)((wk1 - wk0 + 15) / 16);
-        T av[4][RG][RL], bv[NT16][4];
+        const int ng = (int)((wk1 - wk0 + CW - 1) / CW);
+        T av[ST][RG][RL], bv[NT16][ST];
         if (PF) {
             loadA(wk0, av);
             loadB(wk0, bv);
         }
-        for (int g16 = 0; g16 < ng; ++g16) {
-            T an[4][RG][RL], bn[NT16][4];
+        for (int gc = 0; gc < ng; ++gc) {
+            T an[ST][RG][RL], bn[NT16][ST];
             if (!PF) {
-                loadA(wk0 + 16 * g16, av);
-                loadB(wk0 + 16 * g16, bv);
-            } else if (g16 + 1 < ng) {
-                loadA(wk0 + 16 * (g16 + 1), an);
-                loadB(wk0 + 16 * (g16 + 1), bn);
+                loadA(wk0 + CW * gc, av);
+                loadB(wk0 + CW * gc, bv);
+            } else if (gc + 1 < ng) {
+                loadA(wk0 + CW * (gc + 1), an);
+                loadB(wk0 + CW * (gc + 1), bn);
             }
 #pragma unroll
-            for (int st = 0; st < 4; ++st)
+            for (int st = 0; st < ST; ++st)
 #pragma unroll
                 for (int g = 0; g < RG; ++g)
 #pragma unroll
@@ -170,7 +182,7 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
                             acc[g][q][t] = M::op(bv[t][st], av[st][g][q], acc[g][q][t]);
             if (PF) {
 #pragma unroll
-                for (int st = 0; st < 4; ++st)
+                for (int st = 0; st < ST; ++st)
 #pragma unroll
                     for (int g = 0; g < RG; ++g)
 #pragma unroll
@@ -178,7 +190,7 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
 #pragma unroll
                 for (int t = 0; t < NT16; ++t)
 #pragma unroll
-                    for (int st = 0; st < 4; ++st) bv[t][st] = bn[t][st];
+                    for (int st = 0; st < ST; ++st) bv[t][st] = bn[t][st];
             }
         }
     }
@@ -485,26 +497,34 @@ static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; 
 struct NNInstance {
     const void* fn;
     int tile_rows;
+    int chunk;        // columns per chunk of a wavefront
     int occ;          // resident workgroups per CU
+    const char* name; // as profilers print the kernel
 };
 
-template <typename T, int NT16, int RG, bool VEC>
+template <typename T, int NT16, int RG, int ST, bool VEC>
 static NNInstance nn_instance() {
-    static const int occ = occupancy(tsm2r_nn_kernel<T, NT16, RG, 4, VEC>, 256);
-    return NNInstance{(const void*)tsm2r_nn_kernel<T, NT16, RG, 4, VEC>,
-                      16 * (16 / (int)sizeof(T)) * RG, occ};
+    static const int occ = occupancy(tsm2r_nn_kernel<T, NT16, RG, ST, 4, VEC>, 256);
+    static char name[80];
+    static const bool named =
+        std::snprintf(name, sizeof name, "tsm2r_nn_kernel<%s, %d, %d, %d, 4, %s, %s>",
+                      sizeof(T) == 8 ? "double" : "float", NT16, RG, ST, VEC ? "true" : "false",
+                      TSM2X_NN_PREFETCH ? "true" : "false") > 0;
+    (void)named;
+    return NNInstance{(const void*)tsm2r_nn_kernel<T, NT16, RG, ST, 4, VEC>,
+                      16 * (16 / (int)sizeof(T)) * RG, 4 * ST, occ, name};
 }
 
 template <bool VEC>
 static bool nn_pick(int dtype, int np, NNInstance* out) {
     if (dtype == DT_F64) {
-        *out = np <= 16 ? nn_instance<double, 1, TSM2X_NN_RG64, VEC>()
-                        : nn_instance<double, 2, TSM2X_NN_RG64, VEC>();
+        *out = np <= 16 ? nn_instance<double, 1, TSM2X_NN_RG64, TSM2X_NN_ST64, VEC>()
+                        : nn_instance<double, 2, TSM2X_NN_RG64, TSM2X_NN_ST64, VEC>();
         return true;
     }
     if (dtype == DT_F32) {
-        *out = np <= 16 ? nn_instance<float, 1, TSM2X_NN_RG32, VEC>()
-                        : nn_instance<float, 2, TSM2X_NN_RG32, VEC>();
+        *out = np <= 16 ? nn_instance<float, 1, TSM2X_NN_RG32, TSM2X_NN_ST32, VEC>()
+                        : nn_instance<float, 2, TSM2X_NN_RG32, TSM2X_NN_ST32, VEC>();
         return true;
     }
     return false;
@@ -521,12 +541,16 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
     const int WK = 4;
     P->np = np;
     P->fn = I.fn;
+    P->name = I.name;
     P->tiles = cdiv64(m, I.tile_rows);
     P->tile_rows = I.tile_rows;
     // One round of resident workgroups, at most 3 per CU (12 wavefronts, which
     // keep enough loads in flight; more slices only add partial traffic):
     // split k so that tiles * S fills it without a tail round.
-    const int64_t per_cu = I.occ < 3 ? I.occ : 3;
+    int64_t cap = 3;
+    const char* fc = std::getenv("TSM2X_NN_PER_CU");
+    if (fc && *fc && std::strtoll(fc, nullptr, 10) > 0) cap = std::strtoll(fc, nullptr, 10);
+    const int64_t per_cu = I.occ < cap ? I.occ : cap;
     const int64_t slots = (int64_t)cus * per_cu;
     int64_t S = slots / P->tiles;
     const int64_t s_len = k / (WK * 64);                          // >= 64 columns per wave
@@ -536,7 +560,7 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
     if (S < 1) S = 1;
     const char* fs = std::getenv("TSM2X_NN_S");
     if (fs && *fs) S = std::strtoll(fs, nullptr, 10) > 0 ? std::strtoll(fs, nullptr, 10) : S;
-    const int64_t gran = (int64_t)WK * 16;
+    const int64_t gran = (int64_t)WK * I.chunk;
     int64_t ks = cdiv64(k, S);
     ks = cdiv64(ks, gran) * gran;
     P->kslice = ks;

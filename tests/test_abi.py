@@ -94,3 +94,49 @@ def test_binding_refuses_cpu_tensors():
     import torch
     with pytest.raises(ValueError):
         tsm.tsm2r(torch.zeros(4, 4, dtype=torch.float64), torch.zeros(4, 2, dtype=torch.float64))
+
+
+def test_fused_backward_argument_checks():
+    L = _lib.lib()
+    # m k n A lda B ldb dC lddc dA ldda dB lddb dtype ws wsb stream
+    ok = [8, 4, 4, P, 8, P, 4, P, 8, P, 8, P, 4, 0, NULL, 0, NULL]
+    for pos, bad in [(0, -1), (4, 7), (6, 3), (8, 7), (10, 7), (12, 3), (13, 9)]:
+        args = list(ok)
+        args[pos] = bad
+        assert L.tsm2l_backward(*args) == -(pos + 1), pos
+    args = list(ok)
+    args[1] = 33
+    args[6] = 33
+    args[12] = 33
+    assert L.tsm2l_backward(*args) == 1          # k > 32 unsupported
+    args = list(ok)
+    args[1] = 0
+    assert L.tsm2l_backward(*args) == 0          # empty dA and dB: no-op
+
+
+def test_split_argument_checks():
+    L = _lib.lib()
+    assert L.tsm2x_split(-1, 4, P, 4, P, P, 4, 0, NULL) == -1
+    assert L.tsm2x_split(4, 4, P, 3, P, P, 4, 0, NULL) == -4
+    assert L.tsm2x_split(4, 4, P, 4, P, P, 3, 0, NULL) == -7
+    assert L.tsm2x_split(4, 4, P, 4, P, P, 4, 2, NULL) == -8
+    assert L.tsm2x_split(0, 4, NULL, 1, NULL, NULL, 1, 0, NULL) == 0
+
+
+def test_workspace_size_is_zero_without_split():
+    L = _lib.lib()
+    # no reduction split for tiny problems; an op outside the table needs none
+    assert L.tsm2x_workspace_size(1, 1000, 16, 16, 0) == 0
+    assert L.tsm2x_workspace_size(99, 1000, 1000, 16, 0) == 0
+
+
+def test_kernel_name_query():
+    import paper_2002_03258_amd as tsm
+    for dt, tname in ((tsm.F64, "double"), (tsm.F32, "float")):
+        for n in (1, 16, 17, 32):
+            name = tsm.kernel_name(tsm.OP_TSM2R, 4096, 4096, n, dt)
+            assert name.startswith("tsm2r_nn_kernel<%s, %d, " % (tname, 1 if n <= 16 else 2)), name
+    assert tsm.kernel_name(tsm.OP_TSM2R, 4096, 4096, 33, tsm.F64) is None
+    assert tsm.kernel_name(tsm.OP_TSM2R, 0, 4096, 8, tsm.F64) is None
+    assert tsm.kernel_name(tsm.OP_TSM2L, 4096, 8, 8, tsm.F64) is None
+    assert tsm.kernel_name(tsm.OP_TSM2R, 4096, 4096, 8, tsm.BF16) is None

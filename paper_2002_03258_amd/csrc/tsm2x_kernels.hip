@@ -58,22 +58,8 @@ namespace tsm {
 #ifndef TSM2X_NN_PREFETCH
 #define TSM2X_NN_PREFETCH 1
 #endif
-#ifndef TSM2X_NN_RG64
-#define TSM2X_NN_RG64 2
-#endif
-#ifndef TSM2X_NN_RG32
-#define TSM2X_NN_RG32 2
-#endif
-// MFMA steps per chunk (a chunk is 4*ST columns)
-#ifndef TSM2X_NN_ST64
-#define TSM2X_NN_ST64 4
-#endif
-#ifndef TSM2X_NN_ST32
-#define TSM2X_NN_ST32 4
-#endif
-
-// Waves per SIMD each instance is compiled for: three for the 16-column
-// instances (the double one needs the cap to stay within 168 registers).
+// Waves per SIMD each instance is compiled for: three for n <= 16 (the
+// register budget is then 168), two for n <= 32.
 template <typename T, int NT16>
 constexpr int nn_waves() { return NT16 == 1 ? 3 : 2; }
 
@@ -515,16 +501,22 @@ static NNInstance nn_instance() {
                       16 * (16 / (int)sizeof(T)) * RG, 4 * ST, occ, name};
 }
 
+// Two tile heights per type: 16*RL*2 rows with 16-column chunks, and twice
+// the rows with 8-column chunks.  Both keep 8 KB of A in flight per wavefront.
 template <bool VEC>
-static bool nn_pick(int dtype, int np, NNInstance* out) {
+static bool nn_pick(int dtype, int np, bool tall, NNInstance* out) {
     if (dtype == DT_F64) {
-        *out = np <= 16 ? nn_instance<double, 1, TSM2X_NN_RG64, TSM2X_NN_ST64, VEC>()
-                        : nn_instance<double, 2, TSM2X_NN_RG64, TSM2X_NN_ST64, VEC>();
+        if (tall)
+            *out = np <= 16 ? nn_instance<double, 1, 4, 2, VEC>() : nn_instance<double, 2, 4, 2, VEC>();
+        else
+            *out = np <= 16 ? nn_instance<double, 1, 2, 4, VEC>() : nn_instance<double, 2, 2, 4, VEC>();
         return true;
     }
     if (dtype == DT_F32) {
-        *out = np <= 16 ? nn_instance<float, 1, TSM2X_NN_RG32, TSM2X_NN_ST32, VEC>()
-                        : nn_instance<float, 2, TSM2X_NN_RG32, TSM2X_NN_ST32, VEC>();
+        if (tall)
+            *out = np <= 16 ? nn_instance<float, 1, 4, 2, VEC>() : nn_instance<float, 2, 4, 2, VEC>();
+        else
+            *out = np <= 16 ? nn_instance<float, 1, 2, 4, VEC>() : nn_instance<float, 2, 2, 4, VEC>();
         return true;
     }
     return false;
@@ -532,42 +524,66 @@ static bool nn_pick(int dtype, int np, NNInstance* out) {
 
 static inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Grid of the TSM2R kernel.  Measured on gfx950, the streaming rate peaks when
+// about 15/8 workgroups (7.5 wavefronts, 8 KB of A in flight each) are
+// resident per CU: fewer leave HBM latency uncovered, more add concurrent
+// streams without adding bandwidth, and a grid that leaves some CUs with one
+// workgroup more than others runs at the pace of those CUs.  For each tile
+// height the k split S is the one that brings tiles * S closest to that
+// target; the tile height whose grid lands closer wins, ties going to fewer
+// slices (longer streams per wavefront).
 int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P) {
     // partial sums are stored at the kernel's padded width (16 or 32 columns)
     const int np = n <= 16 ? 16 : 32;
-    NNInstance I{};
-    if (!(vec ? nn_pick<true>(dtype, np, &I) : nn_pick<false>(dtype, np, &I))) return 1;
     const int es = dtype == DT_F64 ? 8 : 4;
     const int WK = 4;
-    P->np = np;
-    P->fn = I.fn;
-    P->name = I.name;
-    P->tiles = cdiv64(m, I.tile_rows);
-    P->tile_rows = I.tile_rows;
-    // One round of resident workgroups, at most 3 per CU (12 wavefronts, which
-    // keep enough loads in flight; more slices only add partial traffic):
-    // split k so that tiles * S fills it without a tail round.
-    int64_t cap = 3;
-    const char* fc = std::getenv("TSM2X_NN_PER_CU");
-    if (fc && *fc && std::strtoll(fc, nullptr, 10) > 0) cap = std::strtoll(fc, nullptr, 10);
-    const int64_t per_cu = I.occ < cap ? I.occ : cap;
-    const int64_t slots = (int64_t)cus * per_cu;
-    int64_t S = slots / P->tiles;
-    const int64_t s_len = k / (WK * 64);                          // >= 64 columns per wave
-    const int64_t s_cost = (k * es) / ((int64_t)np * 200);         // partials <= ~8 % of A
-    if (S > s_len) S = s_len;
-    if (S > s_cost) S = s_cost;
-    if (S < 1) S = 1;
+    int64_t target = (int64_t)cus * 15 / 8;
+    const char* ft = std::getenv("TSM2X_NN_TARGET");
+    if (ft && *ft && std::strtoll(ft, nullptr, 10) > 0) target = std::strtoll(ft, nullptr, 10);
     const char* fs = std::getenv("TSM2X_NN_S");
-    if (fs && *fs) S = std::strtoll(fs, nullptr, 10) > 0 ? std::strtoll(fs, nullptr, 10) : S;
-    const int64_t gran = (int64_t)WK * I.chunk;
-    int64_t ks = cdiv64(k, S);
-    ks = cdiv64(ks, gran) * gran;
-    P->kslice = ks;
-    P->S = (int)cdiv64(k, ks);
-    if (P->S < 1) P->S = 1;
-    P->ws = P->S > 1 ? (size_t)P->tiles * P->S * np * I.tile_rows * 8 : 0;
-    return 0;
+    const int64_t s_force = (fs && *fs) ? std::strtoll(fs, nullptr, 10) : 0;
+    const char* fh = std::getenv("TSM2X_NN_TALL");     // 0 or 1 forces a tile height
+    const int64_t tall_force = (fh && *fh) ? std::strtoll(fh, nullptr, 10) : -1;
+
+    bool found = false;
+    double best_dev = 0;
+    for (int tall = 0; tall < 2; ++tall) {
+        if (tall_force >= 0 && tall != (int)tall_force) continue;
+        NNInstance I{};
+        if (!(vec ? nn_pick<true>(dtype, np, tall, &I) : nn_pick<false>(dtype, np, tall, &I)))
+            return 1;
+        const int64_t tiles = cdiv64(m, I.tile_rows);
+        const int64_t slots = (int64_t)cus * I.occ;
+        const int64_t tgt = target < slots ? target : slots;
+        int64_t S = (tgt + tiles / 2) / tiles;                        // nearest integer
+        const int64_t s_len = k / (WK * 64);                          // >= 64 columns per wave
+        const int64_t s_cost = (k * es) / ((int64_t)np * 200);         // partials <= ~4 % of A
+        if (S > s_len) S = s_len;
+        if (S > s_cost) S = s_cost;
+        if (S < 1) S = 1;
+        if (s_force > 0) S = s_force;
+        const int64_t gran = (int64_t)WK * I.chunk;
+        int64_t ks = cdiv64(k, S);
+        ks = cdiv64(ks, gran) * gran;
+        S = cdiv64(k, ks);
+        if (S < 1) S = 1;
+        const int64_t W = tiles * S;
+        const double dev = (double)(W > tgt ? W - tgt : tgt - W) / (double)tgt;
+        // a later (taller) instance must be clearly better to replace the first
+        if (!found || dev < best_dev - 0.02) {
+            found = true;
+            best_dev = dev;
+            P->np = np;
+            P->fn = I.fn;
+            P->name = I.name;
+            P->tiles = tiles;
+            P->tile_rows = I.tile_rows;
+            P->kslice = ks;
+            P->S = (int)S;
+            P->ws = S > 1 ? (size_t)tiles * S * np * I.tile_rows * 8 : 0;
+        }
+    }
+    return found ? 0 : 1;
 }
 
 int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {

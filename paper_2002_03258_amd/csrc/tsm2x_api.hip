@@ -139,13 +139,11 @@ struct TNPlan {
 // WK = 4 wavefronts split the slice.
 TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     TNPlan P{};
-    // rows per wavefront step: 4 * RL * RG for the float kernels, 32 * 2 for
-    // the 16-bit form
-    // G stages of 16*RL rows per wavefront loop iteration (float kernels);
-    // 64 rows per step for the 16-bit form
+    // rows per wavefront loop iteration: G stages of 16*RL rows for the
+    // float kernels, 128 for the 16-bit form
     P.rg = (int)env_int("TSM2X_TN_G", 2);
     if (P.rg != 1 && P.rg != 2 && P.rg != 4) P.rg = 2;
-    const int64_t RB = plain_dtype(dt) ? 16 * (16 / esize(dt)) * P.rg : 64;
+    const int64_t RB = plain_dtype(dt) ? 16 * (16 / esize(dt)) * P.rg : 128;
     const int NT16 = n <= 16 ? 1 : 2;
     P.groups = cdiv(ncols, 16);
     const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * 2);
@@ -295,12 +293,8 @@ int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const voi
         return check_launch("fill_zero");
     }
     if (!plain_dtype(dtype)) {
-        // 128-row tiles walked by a persistent grid of about 8 workgroups per CU
-        int64_t blocks = cdiv(cdiv(m, 128), 4);
-        const int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cu_count() * 8);
-        if (blocks > cap) blocks = cap;
-        if (blocks < 1) blocks = 1;
-        launch_tsm2l_lp(m, k, n, A, lda, (const float*)B, ldb, (float*)C, ldc, dtype, blocks, st);
+        launch_tsm2l_lp(m, k, n, A, lda, (const float*)B, ldb, (float*)C, ldc, dtype, cu_count(),
+                        st);
         return check_launch("tsm2l_lp_kernel");
     }
     RTPlan P = plan_rowtile(m, k, n, dtype, cu_count());

@@ -69,8 +69,7 @@ int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st);
 int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
                  int64_t ldh, int fmt, hipStream_t st);
 int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
-                    int64_t ldb, float* C, int64_t ldc, int dtype, int64_t blocks,
-                    hipStream_t st);
+                    int64_t ldb, float* C, int64_t ldc, int dtype, int cus, hipStream_t st);
 
 struct LaunchBwd {          // fused TSM2L backward: dA = dC*B^T, dB = A^T*dC
     int64_t m, k, n;

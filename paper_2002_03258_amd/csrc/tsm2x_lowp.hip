@@ -311,88 +311,110 @@ __device__ __forceinline__ void split_terms8(const float (&v)[8], u32x4 (&out)[N
         for (int e = 0; e < 4; ++e) out[c][e] = h[c][2 * e] | (h[c][2 * e + 1] << 16);
 }
 
+// Float value of the 16-bit element h (0: low half, 1: high half) of a dword.
+template <int FMT>
+__device__ __forceinline__ float half_val(uint32_t d, int h) {
+    if (FMT == FMT_BF16) return __uint_as_float(h ? (d & 0xffff0000u) : (d << 16));
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(h ? (d >> 16) : (d & 0xffffu)));
+}
+
+// Value of row q (0..7) of a lane's 16-byte run of each plane: hi, or hi + lo.
+// hi + lo is exact in float: lo rounds a - hi at or above a's last bit, so
+// the sum stays on a's 24-bit grid.
+template <int FMT, int NPL>
+__device__ __forceinline__ float plane_val(const uint32_t (&raw)[NPL][4], int q) {
+    float a = half_val<FMT>(raw[0][q >> 1], q & 1);
+    if (NPL == 2) a += half_val<FMT>(raw[NPL - 1][q >> 1], q & 1);
+    return a;
+}
+
 // --------------------------------------------------------------------------
 // tsm2l_lp: C = A*B with A tall (m x k, k <= 32) in the low-precision form,
-// B (k x n, n <= 32) and C float.  TSM2L (Algorithm 6) on the matrix cores:
-// B's terms are built once per wavefront and stay in registers; a
-// persistent grid walks 128-row tiles, each lane loading its 8 rows of every
-// column (8 x 16 bytes per plane), transposing them as in tsm2r_lp, and
-// writing its 8 rows of each output column with 32-byte stores.
+// B (k x n, n <= 32) and C float.  TSM2L (Algorithm 6) carries few flops per
+// byte (2*n per element of A), so the planes are widened to float in
+// registers and the float 16x16x4 matrix cores do the products, with B kept
+// in float.  A lane's 16-byte load is 8 rows of one column: element q is the
+// T operand of MFMA instance q as it stands, S is a 16 x 4 block of B^T held
+// in registers for the whole kernel.  A persistent grid walks 128-row tiles;
+// the next tile's planes (16 VGPRs per plane) are in flight while the
+// current one is multiplied and stored.
 // --------------------------------------------------------------------------
-template <int FMT, int NT16, bool SPLIT, bool VEC>
-__global__ __launch_bounds__(256) void tsm2l_lp_kernel(
+// waves per SIMD the instances are compiled for (the most that fit without spills)
+template <int KS, int NT16>
+constexpr int lp_l_waves() { return (NT16 == 1 && KS <= 4) ? 3 : (KS * NT16 <= 8 ? 2 : 1); }
+
+template <int FMT, int KS, int NT16, bool SPLIT, bool VEC>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_kernel(
     int64_t m, int k, int n, const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
     int64_t lda, const float* __restrict__ B, int64_t ldb, float* __restrict__ C, int64_t ldc) {
-    constexpr int TR = 128;
+    typedef Mfma<float> M;
+    constexpr int RL = 8;                // rows per 16-byte run of 16-bit values
+    constexpr int TR = 16 * RL;
     constexpr int WPB = 4;
     constexpr int NPL = SPLIT ? 2 : 1;
-    constexpr int NBT = SPLIT ? 3 : 2;
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
 
-    u32x4 bt[NT16][NBT];
+    // S operand: B[4 st + kk, 16 t + rl]
+    float bv[KS][NT16];
 #pragma unroll
-    for (int t = 0; t < NT16; ++t) {
-        float bv[8];
-        const int p = 16 * t + rl;
+    for (int st = 0; st < KS; ++st)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int j = 8 * kk + i;
-            bv[i] = (p < n && j < k) ? B[j + p * ldb] : 0.f;
+        for (int t = 0; t < NT16; ++t) {
+            const int j = 4 * st + kk, p = 16 * t + rl;
+            bv[st][t] = (j < k && p < n) ? B[j + (int64_t)p * ldb] : 0.f;
         }
-        split_terms8<FMT, NBT>(bv, bt[t]);
-    }
 
-    const int64_t ntiles = (m + TR - 1) / TR;
-    for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles;
-         tile += (int64_t)gridDim.x * WPB) {
-        const int64_t r = tile * TR + 8 * rl;
-        const bool full = (tile * TR + TR <= m);
-        uint32_t raw[NPL][8][4];
+    auto load = [&](int64_t tile, uint32_t (&raw)[KS][NPL][4]) {
+        const int64_t r = tile * TR + RL * rl;
+        const bool full = tile * TR + TR <= m;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int j = 8 * kk + i;
+        for (int st = 0; st < KS; ++st) {
+            const int j = 4 * st + kk;
 #pragma unroll
             for (int pl = 0; pl < NPL; ++pl) {
                 const uint16_t* P = pl == 0 ? Ah : Al;
                 if (j < k)
-                    load8h<VEC>(P + r + j * lda, m - r, full, raw[pl][i]);
+                    load8h<VEC>(P + r + (int64_t)j * lda, m - r, full, raw[st][pl]);
                 else
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) raw[pl][i][d] = 0u;
+                    for (int d = 0; d < 4; ++d) raw[st][pl][d] = 0u;
             }
         }
-        f32x4 acc[8][NT16];
+    };
+
+    const int64_t ntiles = (m + TR - 1) / TR;
+    const int64_t tstride = (int64_t)gridDim.x * WPB;
+    int64_t tile = (int64_t)blockIdx.x * WPB + w;
+    uint32_t raw[KS][NPL][4];
+    if (tile < ntiles) load(tile, raw);
+    for (; tile < ntiles; tile += tstride) {
+        const int64_t r = tile * TR + RL * rl;
+        const bool full = tile * TR + TR <= m;
+        const bool more = tile + tstride < ntiles;
+        uint32_t rn[KS][NPL][4];
+        if (more) load(tile + tstride, rn);
+        f32x4 acc[RL][NT16];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            u32x4 tq[NPL];
+        for (int q = 0; q < RL; ++q)
 #pragma unroll
-            for (int pl = 0; pl < NPL; ++pl)
+            for (int t = 0; t < NT16; ++t) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t lo = raw[pl][2 * e][q / 2];
-                    const uint32_t hi = raw[pl][2 * e + 1][q / 2];
-                    tq[pl][e] = (q & 1) ? ((lo >> 16) | (hi & 0xffff0000u))
-                                        : ((lo & 0xffffu) | (hi << 16));
-                }
+        for (int st = 0; st < KS; ++st)
 #pragma unroll
-            for (int t = 0; t < NT16; ++t) {
-                acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < RL; ++q) {
+                const float a = plane_val<FMT, NPL>(raw[st], q);
 #pragma unroll
-                for (int c = 0; c < NBT; ++c) acc[q][t] = mfma32<FMT>(bt[t][c], tq[0], acc[q][t]);
-                if (SPLIT) {
-                    acc[q][t] = mfma32<FMT>(bt[t][0], tq[NPL - 1], acc[q][t]);
-                    acc[q][t] = mfma32<FMT>(bt[t][1], tq[NPL - 1], acc[q][t]);
-                }
+                for (int t = 0; t < NT16; ++t) acc[q][t] = M::op(bv[st][t], a, acc[q][t]);
             }
-        }
-        // acc[q][t][rr] = C[r + q, 16 t + mrow(kk, rr)]: rows r .. r+7 of a column
+        // acc[q][t][rr] = C[r + q, 16 t + mrow(kk, rr)]: 8 rows of a column
 #pragma unroll
         for (int t = 0; t < NT16; ++t)
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                const int col = 16 * t + Mfma<float>::mrow(kk, rr);
+                const int col = 16 * t + M::mrow(kk, rr);
                 if (col < n) {
                     float v0[4], v1[4];
 #pragma unroll
@@ -400,35 +422,46 @@ __global__ __launch_bounds__(256) void tsm2l_lp_kernel(
                         v0[q] = acc[q][t][rr];
                         v1[q] = acc[4 + q][t][rr];
                     }
-                    store_run<float, 4, VEC>(C + r + col * ldc, m - r, full, v0);
-                    store_run<float, 4, VEC>(C + r + 4 + col * ldc, m - r - 4, full, v1);
+                    store_run<float, 4, VEC>(C + r + (int64_t)col * ldc, m - r, full, v0);
+                    store_run<float, 4, VEC>(C + r + 4 + (int64_t)col * ldc, m - r - 4, full, v1);
                 }
             }
+        if (more) {
+#pragma unroll
+            for (int st = 0; st < KS; ++st)
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) raw[st][pl][d] = rn[st][pl][d];
+        }
     }
 }
 
 // --------------------------------------------------------------------------
 // tn_lp: O(ncols x n) = X^T * Y with X (R x ncols) in the low-precision form
 // and Y (R x n) float: the gradient dB = A^T * dC of the low-precision form.
-// The reduction runs along X's columns, so a lane's 16-byte load of 8
-// consecutive rows of one X column is already the MFMA operand (no
-// transpose): S[rl][8 kk + i] = X[rb + 8 kk + i, c0 + rl] and
-// T[8 kk + i][rl] = Yterm[rb + 8 kk + i, 16 t + rl].  Products kept:
-// hi*(Y1 + Y2 + Y3) + lo*(Y1 + Y2) (split) or hi*(Y1 + Y2) (single).
-// Reduction across wavefronts and workgroups as in tn_kernel.
+// As tn_kernel: per wavefront step of 128 rows, a lane loads 8 rows of one X
+// column per plane and 4 rows of one Y column twice (16 bytes each, four
+// columns per load instruction), widens X to float and stages both in a
+// wavefront-private LDS tile; it reads back X column rl and Y columns
+// 16 t + rl, 4 consecutive rows at a time, as the S and T operands of the
+// float 16x16x4 matrix cores.  Reduction across wavefronts and workgroups
+// as in tn_kernel.
 // --------------------------------------------------------------------------
 template <int FMT, int NT16, bool SPLIT, bool VEC>
 __global__ __launch_bounds__(256) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
     float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part) {
+    typedef Mfma<float> M;
     constexpr int WK = 4;
-    constexpr int RG = 2;
-    constexpr int RB = 32 * RG;          // rows per wavefront step
+    constexpr int SR = 128;                    // rows per step
+    constexpr int SROW = SR + 4;               // padded LDS column (16 more bytes)
+    constexpr int NC = 16 + 16 * NT16;         // staged columns: X tile, then Y tiles
+    constexpr int YG = 4 * NT16;               // Y column groups of 4
     constexpr int NPL = SPLIT ? 2 : 1;
-    constexpr int NBT = SPLIT ? 3 : 2;
-    constexpr int NV = 4 * NT16;
-    __shared__ double red[WK][WAVE][NV];
+    __shared__ __align__(16) float lds[WK][NC][SROW];
+    __shared__ double red[WK][WAVE][4 * NT16];
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
@@ -438,83 +471,106 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t sb0 = (int64_t)s * rslice;
     const int64_t sb1 = (sb0 + rslice < R) ? sb0 + rslice : R;
-    const int64_t lw = rslice / WK;
+    const int64_t lw = rslice / WK;            // multiple of SR
     const int64_t wb0 = sb0 + w * lw;
     const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
-    const int64_t xc = c0 + rl;
-    const bool xok = xc < ncols;
+    float (*tile)[SROW] = lds[w];
 
     f32x4 acc[NT16];
 #pragma unroll
     for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    auto load = [&](int64_t rb, uint32_t (&xv)[RG][NPL][4], float (&yv)[RG][NT16][8]) {
-#pragma unroll
-        for (int g = 0; g < RG; ++g) {
-            const int64_t r = rb + 32 * g + 8 * kk;
+    auto load = [&](int64_t rb, uint32_t (&xv)[4][NPL][4], float (&yv)[2][YG][4]) {
+        {
+            const int64_t r = rb + 8 * rl;
             const int64_t valid = wb1 - r;
             const bool full = valid >= 8;
 #pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) {
-                const uint16_t* P = pl == 0 ? Xh : Xl;
-                if (xok)
-                    load8h<VEC>(P + r + xc * ldx, valid, full, xv[g][pl]);
+            for (int cg = 0; cg < 4; ++cg) {
+                const int64_t c = c0 + 4 * cg + kk;
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl) {
+                    const uint16_t* P = pl == 0 ? Xh : Xl;
+                    if (c < ncols)
+                        load8h<VEC>(P + r + c * ldx, valid, full, xv[cg][pl]);
+                    else
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) xv[cg][pl][d] = 0u;
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t r = rb + 64 * h + 4 * rl;
+            const int64_t valid = wb1 - r;
+            const bool full = valid >= 4;
+#pragma unroll
+            for (int cg = 0; cg < YG; ++cg) {
+                const int p = 4 * cg + kk;
+                if (p < n)
+                    load_run<float, 4, VEC>(Y + r + (int64_t)p * ldy, valid, full, yv[h][cg]);
                 else
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) xv[g][pl][d] = 0u;
-            }
-#pragma unroll
-            for (int t = 0; t < NT16; ++t) {
-                const int p = 16 * t + rl;
-                if (p < n) {
-                    load_run<float, 4, VEC>(Y + r + p * ldy, valid, full,
-                                            *reinterpret_cast<float(*)[4]>(&yv[g][t][0]));
-                    load_run<float, 4, VEC>(Y + r + 4 + p * ldy, valid - 4, full,
-                                            *reinterpret_cast<float(*)[4]>(&yv[g][t][4]));
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) yv[g][t][i] = 0.f;
-                }
+                    for (int q = 0; q < 4; ++q) yv[h][cg][q] = 0.f;
             }
         }
     };
 
     if (wb1 > wb0) {
-        const int64_t nst = (wb1 - wb0 + RB - 1) / RB;
-        uint32_t xv[RG][NPL][4];
-        float yv[RG][NT16][8];
+        const int64_t nit = (wb1 - wb0 + SR - 1) / SR;
+        uint32_t xv[4][NPL][4];
+        float yv[2][YG][4];
         load(wb0, xv, yv);
-        for (int64_t it = 0; it < nst; ++it) {
-            uint32_t xn[RG][NPL][4];
-            float yn[RG][NT16][8];
-            if (it + 1 < nst) load(wb0 + (it + 1) * RB, xn, yn);
+        for (int64_t it = 0; it < nit; ++it) {
+            uint32_t xn[4][NPL][4];
+            float yn[2][YG][4];
+            if (it + 1 < nit) load(wb0 + (it + 1) * SR, xn, yn);
+            // stage: X column 4 cg + kk rows 8 rl .. 8 rl + 7 (widened),
+            //        Y column 4 cg + kk rows 64 h + 4 rl .. 64 h + 4 rl + 3
 #pragma unroll
-            for (int g = 0; g < RG; ++g)
+            for (int cg = 0; cg < 4; ++cg) {
+                f32x4 x0, x1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    x0[q] = plane_val<FMT, NPL>(xv[cg], q);
+                    x1[q] = plane_val<FMT, NPL>(xv[cg], 4 + q);
+                }
+                *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl]) = x0;
+                *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl + 4]) = x1;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int cg = 0; cg < YG; ++cg) {
+                    f32x4 y;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) y[q] = yv[h][cg][q];
+                    *reinterpret_cast<f32x4*>(&tile[16 + 4 * cg + kk][64 * h + 4 * rl]) = y;
+                }
+            // read back 16-row blocks: rows 16 hb + 4 kk + q
+#pragma unroll
+            for (int hb = 0; hb < SR / 16; ++hb) {
+                const f32x4 xs = *reinterpret_cast<const f32x4*>(&tile[rl][16 * hb + 4 * kk]);
 #pragma unroll
                 for (int t = 0; t < NT16; ++t) {
-                    u32x4 yt[NBT];
-                    split_terms8<FMT, NBT>(yv[g][t], yt);
-                    u32x4 x0{xv[g][0][0], xv[g][0][1], xv[g][0][2], xv[g][0][3]};
+                    const f32x4 ys =
+                        *reinterpret_cast<const f32x4*>(&tile[16 + 16 * t + rl][16 * hb + 4 * kk]);
 #pragma unroll
-                    for (int c = 0; c < NBT; ++c) acc[t] = mfma32<FMT>(x0, yt[c], acc[t]);
-                    if (SPLIT) {
-                        u32x4 x1{xv[g][NPL - 1][0], xv[g][NPL - 1][1], xv[g][NPL - 1][2],
-                                 xv[g][NPL - 1][3]};
-                        acc[t] = mfma32<FMT>(x1, yt[0], acc[t]);
-                        acc[t] = mfma32<FMT>(x1, yt[1], acc[t]);
-                    }
+                    for (int q = 0; q < 4; ++q) acc[t] = M::op(xs[q], ys[q], acc[t]);
                 }
+            }
 #pragma unroll
-            for (int g = 0; g < RG; ++g) {
+            for (int cg = 0; cg < 4; ++cg)
 #pragma unroll
                 for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) xv[g][pl][d] = xn[g][pl][d];
+                    for (int d = 0; d < 4; ++d) xv[cg][pl][d] = xn[cg][pl][d];
 #pragma unroll
-                for (int t = 0; t < NT16; ++t)
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) yv[g][t][i] = yn[g][t][i];
-            }
+                for (int cg = 0; cg < YG; ++cg)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) yv[h][cg][q] = yn[h][cg][q];
         }
     }
 
@@ -597,36 +653,58 @@ int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st) {
     return 0;
 }
 
+template <int FMT, int KS, int NT16, bool SPLIT>
+static void tsm2l_lp_go(int64_t m, int k, int n, const uint16_t* ah, const uint16_t* al,
+                        int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
+                        bool vec, int cus, hipStream_t st) {
+    // persistent grid: as many workgroups as fit at once, no more than there
+    // are groups of 4 row tiles
+    static const int occ_v = lp_occupancy(tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, true>);
+    static const int occ_s = lp_occupancy(tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, false>);
+    int64_t blocks = (int64_t)cus * (vec ? occ_v : occ_s);
+    const int64_t need = cdiv_lp(cdiv_lp(m, 128), 4);
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    dim3 g((unsigned)blocks), b(256);
+    if (vec)
+        hipLaunchKernelGGL((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, true>), g, b, 0, st, m, k, n, ah,
+                           al, lda, B, ldb, C, ldc);
+    else
+        hipLaunchKernelGGL((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, false>), g, b, 0, st, m, k, n,
+                           ah, al, lda, B, ldb, C, ldc);
+}
+
+template <int FMT, bool SPLIT>
+static void tsm2l_lp_ks(int64_t m, int k, int n, const uint16_t* ah, const uint16_t* al,
+                        int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc, bool vec,
+                        int cus, hipStream_t st) {
+#define TSM_L(KS, NT)                                                                       \
+    tsm2l_lp_go<FMT, KS, NT, SPLIT>(m, k, n, ah, al, lda, B, ldb, C, ldc, vec, cus, st); \
+    return
+    if (k <= 8) { if (n <= 16) { TSM_L(2, 1); } TSM_L(2, 2); }
+    if (k <= 16) { if (n <= 16) { TSM_L(4, 1); } TSM_L(4, 2); }
+    if (n <= 16) { TSM_L(8, 1); }
+    TSM_L(8, 2);
+#undef TSM_L
+}
+
 int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
-                    int64_t ldb, float* C, int64_t ldc, int dtype, int64_t blocks,
-                    hipStream_t st) {
+                    int64_t ldb, float* C, int64_t ldc, int dtype, int cus, hipStream_t st) {
     const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
     const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
     const bool vec = ((uintptr_t)A & 15u) == 0 && (lda % 8) == 0 && ((uintptr_t)C & 15u) == 0 &&
                      (ldc % 4) == 0;
     const uint16_t* ah = (const uint16_t*)A;
     const uint16_t* al = split ? ah + lda * k : nullptr;
-    dim3 g((unsigned)blocks), b(256);
     const int ki = (int)k, ni = (int)n;
-#define TSM_L(F, NT, SP)                                                                          \
-    {                                                                                             \
-        if (vec)                                                                                  \
-            hipLaunchKernelGGL((tsm2l_lp_kernel<F, NT, SP, true>), g, b, 0, st, m, ki, ni, ah, al, \
-                               lda, B, ldb, C, ldc);                                              \
-        else                                                                                      \
-            hipLaunchKernelGGL((tsm2l_lp_kernel<F, NT, SP, false>), g, b, 0, st, m, ki, ni, ah,    \
-                               al, lda, B, ldb, C, ldc);                                          \
-        return 0;                                                                                 \
-    }
     if (fmt == FMT_BF16) {
-        if (split) { if (n <= 16) TSM_L(FMT_BF16, 1, true) else TSM_L(FMT_BF16, 2, true) }
-        else { if (n <= 16) TSM_L(FMT_BF16, 1, false) else TSM_L(FMT_BF16, 2, false) }
+        if (split) tsm2l_lp_ks<FMT_BF16, true>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
+        else tsm2l_lp_ks<FMT_BF16, false>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
     } else {
-        if (split) { if (n <= 16) TSM_L(FMT_F16, 1, true) else TSM_L(FMT_F16, 2, true) }
-        else { if (n <= 16) TSM_L(FMT_F16, 1, false) else TSM_L(FMT_F16, 2, false) }
+        if (split) tsm2l_lp_ks<FMT_F16, true>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
+        else tsm2l_lp_ks<FMT_F16, false>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
     }
-#undef TSM_L
-    return 1;
+    return 0;
 }
 
 static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {

@@ -120,3 +120,68 @@ def test_tsm2r_lowp_full_size_sampled(dev, fmt, code):
         del S
     del A
     torch.cuda.empty_cache()
+
+
+# TSM2L and dB = A^T * dC on the planes: the planes are widened to float (hi + lo
+# is exact in float) and multiplied on the float matrix cores, so the error
+# against the stored values is that of float accumulation over k (TSM2L) or
+# m (dB) terms.
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("with_lo", [False, True])
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (7, 5, 3), (1000, 8, 8), (4133, 16, 16),
+                                   (2049, 32, 32), (300, 17, 5), (5000, 3, 29), (129, 9, 17)])
+def test_tsm2l_lowp_small(dev, fmt, code, with_lo, m, k, n):
+    seed = 700 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, torch.float32, dev)
+    B = dev_matrix(seed, si.STREAM_B, k, n, torch.float32, dev)
+    C = tsm.tsm2l(tsm.split(A, fmt, lo=with_lo), B)
+    Ah = host_matrix(seed, si.STREAM_A, m, k, torch.float32)
+    Bh = host_matrix(seed, si.STREAM_B, k, n, torch.float32)
+    e_s = err(to_np(C), oracle.matmul(_stored_value(Ah, code, with_lo), Bh))
+    e_v = err(to_np(C), oracle.matmul(Ah, Bh))
+    assert e_s <= TOL_STORED, (e_s, e_v)
+    assert e_v <= TOL_VALUE[(fmt, with_lo)], (e_s, e_v)
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("with_lo", [False, True])
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (7, 5, 3), (1000, 16, 16), (5000, 33, 8),
+                                   (3000, 17, 20), (130, 40, 32), (70001, 16, 16)])
+def test_grad_b_lowp_small(dev, fmt, code, with_lo, m, k, n):
+    seed = 900 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, torch.float32, dev)
+    dC = dev_matrix(seed, si.STREAM_DC, m, n, torch.float32, dev, dist="normal")
+    dB = tsm.grad_b(tsm.split(A, fmt, lo=with_lo), dC)
+    Ah = host_matrix(seed, si.STREAM_A, m, k, torch.float32)
+    dCh = host_matrix(seed, si.STREAM_DC, m, n, torch.float32, dist="normal")
+    e_s = err(to_np(dB), oracle.matmul(_stored_value(Ah, code, with_lo).T, dCh))
+    e_v = err(to_np(dB), oracle.matmul(Ah.T, dCh))
+    assert e_s <= TOL_STORED, (e_s, e_v)
+    assert e_v <= TOL_VALUE[(fmt, with_lo)], (e_s, e_v)
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+def test_tsm2l_grad_b_lowp_integer_bit_exact(dev, fmt, code):
+    """Integer A (|a| <= 64, exact in both formats, lo = 0) and B, dC with
+    |b| <= 8: every product and partial sum is an integer below 2^24."""
+    m, k, n = 9000, 16, 16
+    A = dev_matrix(11, si.STREAM_A, m, k, torch.float32, dev, dist="int", r=64)
+    B = dev_matrix(11, si.STREAM_B, k, n, torch.float32, dev, dist="int", r=8)
+    dC = dev_matrix(11, si.STREAM_DC, m, n, torch.float32, dev, dist="int", r=8)
+    Ah = host_matrix(11, si.STREAM_A, m, k, torch.float32, dist="int", r=64)
+    Bh = host_matrix(11, si.STREAM_B, k, n, torch.float32, dist="int", r=8)
+    dCh = host_matrix(11, si.STREAM_DC, m, n, torch.float32, dist="int", r=8)
+    for with_lo in (False, True):
+        S = tsm.split(A, fmt, lo=with_lo)
+        assert np.array_equal(to_np(tsm.tsm2l(S, B)), oracle.matmul(Ah, Bh))
+        assert np.array_equal(to_np(tsm.grad_b(S, dC)), oracle.matmul(Ah.T, dCh))
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+def test_tsm2l_grad_b_lowp_deterministic(dev, fmt, code):
+    A = dev_matrix(12, si.STREAM_A, 300000, 16, torch.float32, dev)
+    B = dev_matrix(12, si.STREAM_B, 16, 16, torch.float32, dev)
+    dC = dev_matrix(12, si.STREAM_DC, 300000, 16, torch.float32, dev, dist="normal")
+    S = tsm.split(A, fmt)
+    assert torch.equal(tsm.tsm2l(S, B).clone(), tsm.tsm2l(S, B))
+    assert torch.equal(tsm.grad_b(S, dC).clone(), tsm.grad_b(S, dC))

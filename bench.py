@@ -48,7 +48,10 @@ R_DTYPES = (torch.float64, torch.float32)
 L_MS = (1 << 20, 1 << 22, 1 << 24)
 L_KS = (8, 16, 32)
 TOL = {torch.float64: 1e-13, torch.float32: 1e-5}
-KERNEL_SRC = os.path.join(ROOT, "paper_2002_03258_amd", "csrc", "tsm2x_kernels.hip")
+# the TSM2R kernel's sources: counter summaries taken from another version of
+# them are not used
+KERNEL_SRC = [os.path.join(ROOT, "paper_2002_03258_amd", "csrc", f)
+              for f in ("tsm2x_tsm2r.hip", "tsm2x_device.h")]
 
 
 def es(dtype) -> int:
@@ -60,7 +63,10 @@ def nn_kernel_name(dtype, m, n) -> str:
 
 
 def src_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def make_r_inputs(dev):

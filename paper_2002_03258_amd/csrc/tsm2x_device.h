@@ -31,7 +31,10 @@ __device__ __forceinline__ void load_run(const T* __restrict__ p, int64_t valid,
     }
 }
 
-template <typename T, int RL, bool VEC>
+// The store counterpart; NT = false for ordinary stores (a wavefront whose
+// 16-byte stores leave gaps that a second instruction fills: non-temporal
+// stores of such half-filled lines reach HBM as separate partial writes).
+template <typename T, int RL, bool VEC, bool NT = true>
 __device__ __forceinline__ void store_run(T* __restrict__ p, int64_t valid,
                                           bool full, const T (&v)[RL]) {
     if (VEC && full) {
@@ -39,7 +42,10 @@ __device__ __forceinline__ void store_run(T* __restrict__ p, int64_t valid,
         V x;
 #pragma unroll
         for (int r = 0; r < RL; ++r) x[r] = v[r];
-        __builtin_nontemporal_store(x, reinterpret_cast<V*>(p));
+        if (NT)
+            __builtin_nontemporal_store(x, reinterpret_cast<V*>(p));
+        else
+            *reinterpret_cast<V*>(p) = x;
     } else {
 #pragma unroll
         for (int r = 0; r < RL; ++r)

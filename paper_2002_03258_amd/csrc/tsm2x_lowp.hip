@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
+
 #include "tsm2x_device.h"
 #include "tsm2x_internal.h"
 
@@ -422,8 +424,10 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
                         v0[q] = acc[q][t][rr];
                         v1[q] = acc[4 + q][t][rr];
                     }
-                    store_run<float, 4, VEC>(C + r + (int64_t)col * ldc, m - r, full, v0);
-                    store_run<float, 4, VEC>(C + r + 4 + (int64_t)col * ldc, m - r - 4, full, v1);
+                    // the two stores fill alternate 16-byte halves of the lines
+                    store_run<float, 4, VEC, false>(C + r + (int64_t)col * ldc, m - r, full, v0);
+                    store_run<float, 4, VEC, false>(C + r + 4 + (int64_t)col * ldc, m - r - 4, full,
+                                                    v1);
                 }
             }
         if (more) {
@@ -657,13 +661,17 @@ template <int FMT, int KS, int NT16, bool SPLIT>
 static void tsm2l_lp_go(int64_t m, int k, int n, const uint16_t* ah, const uint16_t* al,
                         int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                         bool vec, int cus, hipStream_t st) {
-    // persistent grid: as many workgroups as fit at once, no more than there
-    // are groups of 4 row tiles
+    // k <= 16: one 128-row tile per wavefront (measured faster); k = 32: a
+    // persistent grid of as many workgroups as fit at once, each wavefront
+    // prefetching its next tile.  Never more than there are groups of 4 tiles.
     static const int occ_v = lp_occupancy(tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, true>);
     static const int occ_s = lp_occupancy(tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, false>);
-    int64_t blocks = (int64_t)cus * (vec ? occ_v : occ_s);
+    int64_t blocks = KS <= 4 ? INT64_MAX : (int64_t)cus * (vec ? occ_v : occ_s);
+    const char* fb = std::getenv("TSM2X_RT_BLOCKS");
+    if (fb && *fb && std::strtoll(fb, nullptr, 10) > 0) blocks = std::strtoll(fb, nullptr, 10);
     const int64_t need = cdiv_lp(cdiv_lp(m, 128), 4);
     if (blocks > need) blocks = need;
+    if (blocks > 0x7fffffff) blocks = 0x7fffffff;
     if (blocks < 1) blocks = 1;
     dim3 g((unsigned)blocks), b(256);
     if (vec)

@@ -153,7 +153,7 @@ template <int FMT, int NT16, bool SPLIT, int WK, bool VEC>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, const float* __restrict__ B, int64_t ldb,
-    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part) {
+    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part, int bvec) {
     constexpr int TR = 128;              // 16 lanes x 8 rows
     constexpr int NP = 16 * NT16;
     constexpr int PG = 4;
@@ -197,14 +197,25 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
             }
         }
     };
+    // a lane's 8 values of B in a chunk, B[j0 + 8 kk .. j0 + 8 kk + 7, p], are
+    // contiguous: two 16-byte (cached) loads when B is aligned
     auto loadB = [&](int64_t j0, float (&bv)[NT16][8]) {
 #pragma unroll
         for (int t = 0; t < NT16; ++t) {
             const int p = 16 * t + rl;
+            const int64_t jb = j0 + 8 * kk;
+            const float* __restrict__ src = B + jb + (int64_t)p * ldb;
+            if (p < n && bvec && jb + 8 <= wk1) {
+                const f32x4 v0 = *reinterpret_cast<const f32x4*>(src);
+                const f32x4 v1 = *reinterpret_cast<const f32x4*>(src + 4);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int64_t j = j0 + 8 * kk + i;
-                bv[t][i] = (p < n && j < wk1) ? B[j + p * ldb] : 0.f;
+                for (int i = 0; i < 4; ++i) {
+                    bv[t][i] = v0[i];
+                    bv[t][4 + i] = v1[i];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bv[t][i] = (p < n && jb + i < wk1) ? src[i] : 0.f;
             }
         }
     };
@@ -623,13 +634,18 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     P->np = 16 * nt16;
     P->tile_rows = TR;
     P->tiles = cdiv_lp(m, TR);
-    const int64_t slots = (int64_t)cus * (occ < 3 ? occ : 3);
-    int64_t S = slots / P->tiles;
+    // as for the float kernel: aim at about 15/8 resident workgroups per CU
+    const int64_t slots = (int64_t)cus * occ;
+    int64_t tgt = (int64_t)cus * 15 / 8;
+    if (tgt > slots) tgt = slots;
+    int64_t S = (tgt + P->tiles / 2) / P->tiles;
     const int64_t s_len = k / (WK * 64);
     const int64_t s_cost = (k * es) / ((int64_t)P->np * 200);
     if (S > s_len) S = s_len;
     if (S > s_cost) S = s_cost;
     if (S < 1) S = 1;
+    const char* fs = std::getenv("TSM2X_LP_S");
+    if (fs && *fs && std::strtoll(fs, nullptr, 10) > 0) S = std::strtoll(fs, nullptr, 10);
     const int64_t gran = (int64_t)WK * 32;
     int64_t ks = cdiv_lp(k, S);
     ks = cdiv_lp(ks, gran) * gran;
@@ -645,9 +661,12 @@ int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st) {
     const uint16_t* ah = (const uint16_t*)L.A;
     const uint16_t* al = split ? ah + L.lda * L.k : nullptr;
     int n32 = (int)L.n;
+    // 16-byte loads of B's column runs need an aligned B with ldb % 4 == 0
+    int bvec = ((uintptr_t)L.B & 15u) == 0 && (L.ldb % 4) == 0;
     void* args[] = {(void*)&L.m,   (void*)&L.k,   (void*)&n32,      (void*)&ah,
                     (void*)&al,    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,
-                    (void*)&L.C,   (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part};
+                    (void*)&L.C,   (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part,
+                    (void*)&bvec};
     hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
                                    0, st);
     if (e != hipSuccess) return 1;

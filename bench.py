@@ -223,14 +223,14 @@ def rows_lowp(dev):
     for n in (8, 16, 32):
         B = si.matrix(seed + n, si.STREAM_B, k, n, dtype=torch.float32, device=dev)
         C = tsm.empty_colmajor(m, n, torch.float32, dev)
-        t32 = timed(lambda: tsm.tsm2r(A, B, out=C))
+        t32 = timed(lambda: tsm.tsm2r(A, B, out=C), reps=10)
         b32 = (m * k + k * n + m * n) * 4
         Bh = si.matrix(seed + n, si.STREAM_B, k, n, dtype=torch.float32).double().numpy()
         for fmt, code in (("bf16", oracle.BF16), ("f16", oracle.F16)):
             for lo in (False, True):
                 S = tsm.split(A, fmt, lo=lo)
                 t_split = timed(lambda: tsm.split(A, fmt, lo=lo), reps=2) if n == 8 else None
-                t = timed(lambda: tsm.tsm2r(S, B, out=C))
+                t = timed(lambda: tsm.tsm2r(S, B, out=C), reps=10)
                 nb = S.nbytes() + (k * n + m * n) * 4
                 hi, lo_ = oracle.split(Ar.astype(np.float32), code)
                 stored = oracle.decode_plane(hi, code) + (oracle.decode_plane(lo_, code) if lo else 0)

@@ -104,7 +104,10 @@ RTPlan plan_rowtile(int64_t m, int64_t kin, int64_t nout, int dt, int cus) {
     const int64_t TR = 16 * RL * RG;
     const int64_t ntiles = cdiv(m, TR);
     const int64_t wblocks = cdiv(ntiles, 4);
-    const int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cus * 8);
+    // workgroups resident at once (the rowtile instances fit 2-4 per CU): the
+    // output columns are split so that one round covers them, each wavefront
+    // keeping one row tile for its whole column range
+    const int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cus * 4);
     if (nout <= 32) {
         P.cpb = nout;
         P.by = 1;

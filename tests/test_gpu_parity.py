@@ -204,6 +204,32 @@ def test_grads_small(dev, dtype, m, k, n):
     assert err(to_np(dB), rB) <= TOL[dtype]
 
 
+# dA of TSM2R shapes (many output columns): column ranges split across
+# workgroups, ragged rows and column ranges, padded (unaligned) leading
+# dimensions
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,k,n,pad", [(1000, 300, 16, 0), (777, 129, 1, 0), (4099, 1000, 9, 3),
+                                       (65, 65, 8, 1), (2048, 4096, 16, 0), (3, 700, 2, 0)])
+def test_grad_a_rank_update(dev, dtype, m, k, n, pad):
+    seed = 600 + m + k + n
+    B = dev_matrix(seed, si.STREAM_B, k, n, dtype, dev, ld=k + pad)
+    dC = dev_matrix(seed, si.STREAM_DC, m, n, dtype, dev, ld=m + pad, dist="normal")
+    dA = tsm.grad_a(dC, B)
+    rA = oracle.matmul(host_matrix(seed, si.STREAM_DC, m, n, dtype, dist="normal"),
+                       host_matrix(seed, si.STREAM_B, k, n, dtype).T)
+    assert err(to_np(dA), rA) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_grad_a_rank_update_integer_exact(dev, dtype):
+    m, k, n = 5000, 3000, 16
+    B = dev_matrix(61, si.STREAM_B, k, n, dtype, dev, dist="int", r=8)
+    dC = dev_matrix(61, si.STREAM_DC, m, n, dtype, dev, dist="int", r=8)
+    ref = oracle.matmul(host_matrix(61, si.STREAM_DC, m, n, dtype, dist="int", r=8),
+                        host_matrix(61, si.STREAM_B, k, n, dtype, dist="int", r=8).T)
+    assert np.array_equal(to_np(tsm.grad_a(dC, B)), ref)
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_shared_workspace_across_shapes(dev, dtype):
     """Calls of different shapes share the library workspace: a call with few

@@ -17,14 +17,17 @@
  * ---------------------------------------
  *  - Matrices are column-major ("by convention", Design of TSM2R, Efficient
  *    Off-Chip Memory Access): element (i,j) of X with leading dimension ldX
- *    is X[i + j*ldX].  tsm2r_ex also accepts a row-major A.
+ *    is X[i + j*ldX].  The _ex forms also take A and/or B given as their
+ *    transposes (equivalently, row-major A or B).
  *  - All matrix pointers are DEVICE pointers owned by the caller; the library
  *    never frees or retains them.  `stream` is a hipStream_t (NULL = the
  *    null stream).  Every call is asynchronous on `stream`; a return value of
  *    0 means the work was enqueued.
- *  - The output is overwritten, never read (C := A*B, not C += A*B).
+ *  - The output is overwritten, never read (C := A*B), except in the _ex and
+ *    gemm forms with beta != 0 (C := beta*C + A*B, the accumulating form of
+ *    the paper's algorithms, which load C before adding to it).
  *  - m == 0 or n == 0 (or, for the gradients, an empty output) is a no-op.
- *    k == 0 writes zeros.
+ *    k == 0 writes zeros (beta*C in the _ex forms).
  *  - Results are deterministic: a repeated call on the same inputs gives the
  *    same bits (fixed reduction orders, no floating-point atomics).
  *  - Arguments are checked on the host before any HIP call.  An invalid
@@ -71,8 +74,6 @@ typedef enum {
     TSM_F16_SPLIT = 5
 } tsm_dtype;
 
-typedef enum { TSM_COL_MAJOR = 0, TSM_ROW_MAJOR = 1 } tsm_order;
-
 /* Operations, for tsm2x_workspace_size. */
 typedef enum {
     TSM_OP_TSM2R = 0,
@@ -91,34 +92,66 @@ enum {
 };
 
 /* TSM2R: C = A*B, A m-by-k (lda >= max(1,m)), B k-by-n (ldb >= max(1,k)),
- * C m-by-n (ldc >= max(1,m)), n <= 32.  A is streamed from memory once
- * (outer-product form of Algorithm 2 with the on-chip B tile of
- * Algorithms 3-4); the k range is split across wavefronts and workgroups and
- * the partial sums are added in double precision in a fixed order.
- * dtype: any tsm_dtype.  Errors: -1..-11 for arguments 1..11,
- * TSM_ERR_UNSUPPORTED if n > 32. */
+ * C m-by-n (ldc >= max(1,m)).  A is streamed from memory once (outer-product
+ * form of Algorithm 2 with the on-chip B tile of Algorithms 3-4); the k range
+ * is split across wavefronts and workgroups and the partial sums are added in
+ * double precision in a fixed order.  n > 32 runs in panels of 32 columns of
+ * B and C (A read once per panel, as the paper's t2 < n).
+ * dtype: any tsm_dtype.  Errors: -1..-11 for arguments 1..11. */
 int tsm2r(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
           const void* B, int64_t ldb, void* C, int64_t ldc, int dtype,
           void* stream);
 
-/* TSM2R with a caller workspace (ws, ws_bytes; see "Workspace") and the
- * storage order of A.  order == TSM_ROW_MAJOR: element (i,j) of A is
- * A[i*lda + j], lda >= max(1,k); supported for TSM_F64 and TSM_F32.
- * Arguments: 1 order, 2 m, 3 k, 4 n, 5 A, 6 lda, 7 B, 8 ldb, 9 C, 10 ldc,
- * 11 dtype, 12 ws, 13 ws_bytes, 14 stream.  ws may be NULL when
- * tsm2x_workspace_size() is 0. */
-int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A,
-             int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc,
-             int dtype, void* ws, size_t ws_bytes, void* stream);
-
-/* TSM2L: C = A*B, A m-by-k with k <= 32, B k-by-n with n <= 32 (Algorithm 6:
- * horizontal tiles of A processed by a persistent grid; B is held on chip
- * whole, so C is written exactly once and never re-read).
+/* TSM2L: C = A*B, A m-by-k with k <= 32, B k-by-n (Algorithm 6: horizontal
+ * tiles of A processed by a persistent grid; B is held on chip whole, so C
+ * is written exactly once and never re-read).  k > 32 is computed by the
+ * TSM2R kernels (correct for any shape; TSM2L's kernels need B on chip);
+ * n > 32 in panels of 32 columns.
  * dtype: any tsm_dtype (16-bit forms of A as in tsm2r, B and C float).
- * Errors as tsm2r; TSM_ERR_UNSUPPORTED if k > 32 or n > 32. */
+ * Errors as tsm2r. */
 int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
           const void* B, int64_t ldb, void* C, int64_t ldc, int dtype,
           void* stream);
+
+/* Extended forms: C := beta*C + op(A)*op(B), with a caller workspace.
+ *   transA  0: A is m-by-k (lda >= max(1,m));
+ *           1: A is given as its transpose, a k-by-m matrix (lda >=
+ *              max(1,k)), i.e. A stored row-major.  The 16-bit forms of A
+ *              (planes written by tsm2x_split) must have transA = 0.
+ *   transB  0: B is k-by-n (ldb >= max(1,k));
+ *           1: B is given as its transpose, n-by-k (ldb >= max(1,n)).  The
+ *              TSM2R kernels first copy B into the workspace column-major.
+ *   beta    C is read only when beta != 0.  Where the kernel finishes in
+ *           double (TSM2R, transA = 1) beta*C is added in double and the
+ *           sum rounded once; the TSM2L kernels add it in C's type.
+ *   ws      device workspace, 256-byte aligned, at least
+ *           tsm2x_workspace_size(op, m, k, n, dtype) bytes (op TSM_OP_TSM2R,
+ *           TSM_OP_TSM2R_ROWMAJOR for transA = 1, TSM_OP_TSM2L), any
+ *           contents; NULL: the library's own (see "Workspace").
+ * tsm2r_ex uses the TSM2R kernels (transA = 1: the reduction along the
+ * contiguous dimension, the tn kernel), tsm2l_ex the TSM2L kernels where
+ * they apply (transA = 0, k <= 32) and the TSM2R ones otherwise.
+ * Arguments: 1 transA, 2 transB, 3 m, 4 k, 5 n, 6 A, 7 lda, 8 B, 9 ldb,
+ * 10 beta, 11 C, 12 ldc, 13 dtype, 14 ws, 15 ws_bytes, 16 stream.
+ * Errors: -i for argument i; TSM_ERR_UNSUPPORTED for transA = 1 with a
+ * 16-bit form; TSM_ERR_WORKSPACE if ws is too small or misaligned. */
+int tsm2r_ex(int transA, int transB, int64_t m, int64_t k, int64_t n,
+             const void* A, int64_t lda, const void* B, int64_t ldb,
+             double beta, void* C, int64_t ldc, int dtype, void* ws,
+             size_t ws_bytes, void* stream);
+int tsm2l_ex(int transA, int transB, int64_t m, int64_t k, int64_t n,
+             const void* A, int64_t lda, const void* B, int64_t ldb,
+             double beta, void* C, int64_t ldc, int dtype, void* ws,
+             size_t ws_bytes, void* stream);
+
+/* The same contract, choosing by the paper's two shape classes (Design of
+ * TSM2R / Design of TSM2L): TSM2L for a column-major A with k <= 32, TSM2R
+ * otherwise.  Workspace: tsm2x_workspace_size(TSM_OP_TSM2R or
+ * TSM_OP_TSM2R_ROWMAJOR, ...) covers every case. */
+int tsm2x_gemm(int transA, int transB, int64_t m, int64_t k, int64_t n,
+               const void* A, int64_t lda, const void* B, int64_t ldb,
+               double beta, void* C, int64_t ldc, int dtype, void* ws,
+               size_t ws_bytes, void* stream);
 
 /* Gradient with respect to A of L = <dC, A*B>:  dA = dC * B^T.
  * dC m-by-n (lddc >= max(1,m)), B k-by-n (ldb >= max(1,k)),

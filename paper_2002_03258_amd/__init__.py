@@ -11,10 +11,11 @@ from __future__ import annotations
 import torch
 
 from . import _lib
-from ._lib import (BF16, BF16_SPLIT, COL_MAJOR, F16, F16_SPLIT, F32, F64, OP_GRAD_A,
-                   OP_GRAD_B, OP_TSM2L, OP_TSM2R, OP_TSM2R_ROWMAJOR, ROW_MAJOR, TSMError)
+from ._lib import (BF16, BF16_SPLIT, F16, F16_SPLIT, F32, F64, OP_GRAD_A, OP_GRAD_B, OP_TSM2L,
+                   OP_TSM2R, OP_TSM2R_ROWMAJOR, TSMError)
 
-__all__ = ["tsm2r", "tsm2l", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA", "colmajor",
+__all__ = ["tsm2r", "tsm2l", "gemm", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA",
+           "colmajor",
            "empty_colmajor", "workspace_size", "kernel_name", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
            "BF16_SPLIT", "F16_SPLIT", "OP_TSM2R", "OP_TSM2L", "OP_GRAD_A", "OP_GRAD_B",
            "OP_TSM2R_ROWMAJOR"]
@@ -105,64 +106,83 @@ def split(A: torch.Tensor, fmt: str = "bf16", lo: bool = True) -> SplitA:
     return SplitA(planes, m, k, fmt, lo)
 
 
-def tsm2r(A, B: torch.Tensor, out: torch.Tensor | None = None,
-          workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """C = A*B for a large A (m x k, column- or row-major, or a SplitA) and a
-    skinny B (k x n, n <= 32) -- TSM2R.  For a SplitA, B and C are float32."""
+def _layout(x: torch.Tensor):
+    """(trans, ld) of a 2-D tensor held column-major (trans 0) or row-major
+    (trans 1: the column-major storage of its transpose); None otherwise."""
+    r, c = x.shape
+    if (x.stride(0) == 1 or r <= 1) and (c <= 1 or x.stride(1) >= max(1, r)):
+        return 0, (x.stride(1) if c > 1 else max(1, r))
+    if (x.stride(1) == 1 or c <= 1) and (r <= 1 or x.stride(0) >= max(1, c)):
+        return 1, (x.stride(0) if r > 1 else max(1, c))
+    return None
+
+
+def _operand(x: torch.Tensor):
+    """(tensor, trans, ld): x as it is when column- or row-major, else a
+    column-major copy."""
+    lay = _layout(x)
+    if lay is None:
+        x = colmajor(x)
+        lay = (0, _ld(x))
+    return x, lay[0], lay[1]
+
+
+def _ws(workspace):
+    return (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
+        if workspace is not None else (None, 0)
+
+
+def _product(fn: str, A, B: torch.Tensor, out, beta: float, workspace) -> torch.Tensor:
     if isinstance(A, SplitA):
         _check_device(A.planes, B)
-        m, k = A.shape
-        n = B.shape[1]
         if B.dtype != torch.float32:
             raise ValueError("B must be float32 for the low-precision forms of A")
-        B = colmajor(B)
-        C = out if out is not None else empty_colmajor(m, n, torch.float32, B.device)
-        ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
-            if workspace is not None else (None, 0)
-        _lib.call("tsm2r_ex", COL_MAJOR, m, k, n, A.planes.data_ptr(), A.ld, B.data_ptr(),
-                  _ld(B), C.data_ptr(), _ld(C), A.dtype_code, ws, wsb, _stream())
-        return C
-    _check_device(A, B)
-    dt = _DT[A.dtype]
-    m, k = A.shape
-    n = B.shape[1]
-    B = colmajor(B)
-    C = out if out is not None else empty_colmajor(m, n, A.dtype, A.device)
-    rowA = (not is_colmajor(A)) and A.stride(1) == 1 and k > 1
-    if not rowA:
-        A = colmajor(A)
-        lda = _ld(A)
-    else:
-        lda = max(1, A.stride(0))
-    ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
-        if workspace is not None else (None, 0)
-    _lib.call("tsm2r_ex", ROW_MAJOR if rowA else COL_MAJOR, m, k, n, A.data_ptr(), lda,
-              B.data_ptr(), _ld(B), C.data_ptr(), _ld(C), dt, ws, wsb, _stream())
-    return C
-
-
-def tsm2l(A, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """C = A*B for a tall-and-skinny A (m x k, k <= 32, or a SplitA) and a
-    small B (k x n, n <= 32) -- TSM2L."""
-    if isinstance(A, SplitA):
-        _check_device(A.planes, B)
         m, k = A.shape
-        n = B.shape[1]
-        B = colmajor(B)
-        C = out if out is not None else empty_colmajor(m, n, torch.float32, B.device)
-        _lib.call("tsm2l", m, k, n, A.planes.data_ptr(), A.ld, B.data_ptr(), _ld(B),
-                  C.data_ptr(), _ld(C), A.dtype_code, _stream())
-        return C
-    _check_device(A, B)
-    dt = _DT[A.dtype]
-    A = colmajor(A)
-    B = colmajor(B)
-    m, k = A.shape
+        a_ptr, ta, lda, code, cdt, dev = A.planes.data_ptr(), 0, A.ld, A.dtype_code, \
+            torch.float32, A.device
+    else:
+        _check_device(A, B)
+        if B.dtype != A.dtype:
+            raise ValueError("A and B must have the same dtype")
+        code, cdt, dev = _DT[A.dtype], A.dtype, A.device
+        m, k = A.shape
+        A, ta, lda = _operand(A)
+        a_ptr = A.data_ptr()
+    if B.shape[0] != k:
+        raise ValueError("inner dimensions differ: A has %d columns, B %d rows" % (k, B.shape[0]))
     n = B.shape[1]
-    C = out if out is not None else empty_colmajor(m, n, A.dtype, A.device)
-    _lib.call("tsm2l", m, k, n, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
-              C.data_ptr(), _ld(C), dt, _stream())
-    return C
+    B, tb, ldb = _operand(B)
+    if out is None:
+        if beta != 0:
+            raise ValueError("beta != 0 accumulates into `out`, which must be given")
+        out = empty_colmajor(m, n, cdt, dev)
+    elif not is_colmajor(out) or tuple(out.shape) != (m, n) or out.dtype != cdt:
+        raise ValueError("out must be a column-major %d x %d %s tensor" % (m, n, cdt))
+    ws, wsb = _ws(workspace)
+    _lib.call(fn, ta, tb, m, k, n, a_ptr, lda, B.data_ptr(), ldb, float(beta), out.data_ptr(),
+              _ld(out), code, ws, wsb, _stream())
+    return out
+
+
+def tsm2r(A, B: torch.Tensor, out: torch.Tensor | None = None, beta: float = 0.0,
+          workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """C := beta*C + A*B for a large A (m x k, column- or row-major, or a
+    SplitA) and a skinny B (k x n) -- TSM2R.  For a SplitA, B and C are
+    float32.  C is `out` (column-major); it is read only when beta != 0."""
+    return _product("tsm2r_ex", A, B, out, beta, workspace)
+
+
+def tsm2l(A, B: torch.Tensor, out: torch.Tensor | None = None, beta: float = 0.0,
+          workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """C := beta*C + A*B for a tall-and-skinny A (m x k, k <= 32, or a SplitA)
+    and a small B (k x n) -- TSM2L; other shapes run on the TSM2R kernels."""
+    return _product("tsm2l_ex", A, B, out, beta, workspace)
+
+
+def gemm(A, B: torch.Tensor, out: torch.Tensor | None = None, beta: float = 0.0,
+         workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """C := beta*C + A*B, TSM2L or TSM2R chosen by the shape of A."""
+    return _product("tsm2x_gemm", A, B, out, beta, workspace)
 
 
 def grad_a(dC: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -14,7 +14,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TSM2X_LIBRARY") or os.path.join(HERE, "libtsm2x.so")
 
 F64, F32, BF16, F16, BF16_SPLIT, F16_SPLIT = range(6)
-COL_MAJOR, ROW_MAJOR = 0, 1
 OP_TSM2R, OP_TSM2L, OP_GRAD_A, OP_GRAD_B, OP_TSM2R_ROWMAJOR = range(5)
 
 _lock = threading.Lock()
@@ -46,7 +45,11 @@ def lib():
             mm = [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp]
             L.tsm2r.argtypes = mm
             L.tsm2l.argtypes = mm
-            L.tsm2r_ex.argtypes = [i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
+            ex = [i32, i32, i64, i64, i64, vp, i64, vp, i64, ctypes.c_double, vp, i64, i32, vp,
+                  sz, vp]
+            L.tsm2r_ex.argtypes = ex
+            L.tsm2l_ex.argtypes = ex
+            L.tsm2x_gemm.argtypes = ex
             L.tsm_grad_a.argtypes = mm
             L.tsm_grad_b.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, vp, sz, vp]
             L.tsm2x_split.argtypes = [i64, i64, vp, i64, vp, vp, i64, i32, vp]
@@ -63,7 +66,8 @@ def lib():
             L.tsm2x_version.argtypes = []
             L.tsm2x_finalize.argtypes = []
             L.tsm2x_finalize.restype = None
-            for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm_grad_a", "tsm_grad_b",
+            for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a",
+                      "tsm_grad_b",
                       "tsm2l_backward", "tsm2x_split", "tsm2x_version"):
                 getattr(L, f).restype = i32
             _lib = L
@@ -77,7 +81,8 @@ def call(fn: str, *args) -> None:
         raise TSMError(fn, rc, L)
 
 
-EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm_grad_a", "tsm_grad_b", "tsm2l_backward",
+EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a", "tsm_grad_b",
+           "tsm2l_backward",
            "tsm2x_split",
            "tsm2x_workspace_size", "tsm2x_kernel_name", "tsm2x_error_string", "tsm2x_last_hip_error",
            "tsm2x_version", "tsm2x_finalize")

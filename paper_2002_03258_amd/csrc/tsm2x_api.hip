@@ -69,7 +69,7 @@ int64_t env_int(const char* name, int64_t dflt) {
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-[[maybe_unused]] inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool valid_dtype(int dt) { return dt >= TSM_F64 && dt <= TSM_F16_SPLIT; }
 bool plain_dtype(int dt) { return dt == TSM_F64 || dt == TSM_F32; }
@@ -214,99 +214,193 @@ int check_mm(int base, int64_t m, int64_t k, int64_t n, const void* A, int64_t l
     return TSM_SUCCESS;
 }
 
-}  // namespace
+// Validation for the extended product entry points; argument positions
+// 1 transA, 2 transB, 3 m, 4 k, 5 n, 6 A, 7 lda, 8 B, 9 ldb, 10 beta, 11 C,
+// 12 ldc, 13 dtype.
+int check_ex(int transA, int transB, int64_t m, int64_t k, int64_t n, const void* A,
+             int64_t lda, const void* B, int64_t ldb, const void* C, int64_t ldc, int dtype) {
+    if (transA != 0 && transA != 1) return -1;
+    if (transB != 0 && transB != 1) return -2;
+    if (m < 0) return -3;
+    if (k < 0) return -4;
+    if (n < 0) return -5;
+    if (!A && m > 0 && k > 0) return -6;
+    const int64_t mina = transA ? k : m;
+    if (lda < (mina > 1 ? mina : 1)) return -7;
+    if (!B && k > 0 && n > 0) return -8;
+    const int64_t minb = transB ? n : k;
+    if (ldb < (minb > 1 ? minb : 1)) return -9;
+    if (!C && m > 0 && n > 0) return -11;
+    if (ldc < (m > 1 ? m : 1)) return -12;
+    if (!valid_dtype(dtype)) return -13;
+    return TSM_SUCCESS;
+}
 
-extern "C" {
+// Leading dimension of the column-major copy of a transposed B (k x n), kept
+// a multiple of 16 bytes so the kernels' 16-byte B loads apply.
+int64_t bt_ld(int64_t k, int ce) { return cdiv(k, 16 / ce) * (16 / ce); }
 
-int tsm2r_ex(int order, int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
-             const void* B, int64_t ldb, void* C, int64_t ldc, int dtype, void* ws,
-             size_t ws_bytes, void* stream) {
-    if (order != TSM_COL_MAJOR && order != TSM_ROW_MAJOR) return -1;
-    const bool rowA = order == TSM_ROW_MAJOR;
-    int rc = check_mm(2, m, k, n, A, lda, B, ldb, C, ldc, dtype, rowA);
-    if (rc) return rc;
-    if (n > 32) return TSM_ERR_UNSUPPORTED;
-    if (rowA && !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+// Workspace of a TSM2R-kernel product of at most 32 columns: the split
+// partials of its plan, then room for B when it is given transposed.
+size_t tsm2r_ws(int transA, int64_t m, int64_t k, int64_t n, int dtype, bool transB) {
+    const int cus = cu_count();
+    const int ce = plain_dtype(dtype) ? esize(dtype) : 4;
+    size_t part = 0;
+    if (!plain_dtype(dtype)) {
+        NNPlan P{};
+        plan_tsm2r_lp(m, k, n, dtype, cus, true, &P);
+        part = P.ws;
+    } else if (transA) {
+        part = plan_tn(k, m, n, dtype, cus).ws;
+    } else {
+        NNPlan P{};
+        if (!plan_tsm2r(m, k, n, dtype, cus, true, &P)) part = P.ws;
+    }
+    return align256(part) + (transB ? (size_t)bt_ld(k, ce) * n * ce : 0);
+}
+
+// C := beta*C + op(A)*op(B) on validated arguments.  `lform` asks for the TSM2L
+// kernels (all of B on chip); they need a column-major A and k <= 32, other
+// shapes run on the TSM2R kernels, which are correct for any k.  n > 32 is
+// done in panels of 32 columns of B and C, A being read once per panel.
+int product(bool lform, int transA, int transB, int64_t m, int64_t k, int64_t n, const void* A,
+            int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+            int dtype, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (transA && !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;   // planes are column-major
     if (m == 0 || n == 0) return TSM_SUCCESS;
-    hipStream_t st = (hipStream_t)stream;
+    const int ce = plain_dtype(dtype) ? esize(dtype) : 4;             // element size of B, C
+    const int cdt = plain_dtype(dtype) ? dtype : TSM_F32;
     if (k == 0) {
-        launch_fill_zero(m, n, C, ldc, plain_dtype(dtype) ? dtype : TSM_F32, st);
-        return check_launch("fill_zero");
+        launch_fill_scale(m, n, C, ldc, beta, cdt, st);
+        return check_launch("fill_scale_kernel");
+    }
+    if (n > 32) {
+        for (int64_t p0 = 0; p0 < n; p0 += 32) {
+            const int64_t np = n - p0 < 32 ? n - p0 : 32;
+            const char* Bp = (const char*)B + (transB ? p0 : p0 * ldb) * ce;
+            char* Cp = (char*)C + p0 * ldc * ce;
+            int rc = product(lform, transA, transB, m, k, np, A, lda, Bp, ldb, beta, Cp, ldc,
+                             dtype, ws, ws_bytes, st);
+            if (rc) return rc;
+        }
+        return TSM_SUCCESS;
     }
     const int cus = cu_count();
+    if (lform && !transA && k <= 32) {
+        // B(j, p) at B[j*bsj + p*bsp]: both orders of B are plain strides here
+        const int64_t bsj = transB ? ldb : 1, bsp = transB ? 1 : ldb;
+        if (!plain_dtype(dtype)) {
+            launch_tsm2l_lp(m, k, n, A, lda, (const float*)B, bsj, bsp, (float)beta, (float*)C,
+                            ldc, dtype, cus, st);
+            return check_launch("tsm2l_lp_kernel");
+        }
+        RTPlan P = plan_rowtile(m, k, n, dtype, cus);
+        LaunchRT L{};
+        L.m = m; L.kin = (int)k; L.nout = n; L.X = A; L.ldx = lda; L.Y = B; L.ys_in = bsj;
+        L.ys_out = bsp; L.O = C; L.ldo = ldc; L.kp = P.kp; L.cols_per_block = (int)P.cpb;
+        L.blocks_x = P.bx; L.blocks_y = P.by; L.cus = cus; L.beta = beta;
+        if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
+        return check_launch("rowtile_kernel");
+    }
+    // TSM2R kernels; workspace = [split partials][B copied column-major]
     void* w = nullptr;
+    int rc = get_ws(tsm2r_ws(transA, m, k, n, dtype, transB), ws, ws_bytes, &w);
+    if (rc) return rc;
+    const void* Bk = B;
+    int64_t ldbk = ldb;
+    if (transB) {
+        void* bc = (char*)w + (tsm2r_ws(transA, m, k, n, dtype, false));
+        launch_transpose(k, n, B, ldb, bc, bt_ld(k, ce), cdt, st);
+        rc = check_launch("transpose_kernel");
+        if (rc) return rc;
+        Bk = bc;
+        ldbk = bt_ld(k, ce);
+    }
     if (!plain_dtype(dtype)) {
         // A: 16-bit hi plane (and lo plane lda*k elements after it); B, C float
         NNPlan P{};
         plan_tsm2r_lp(m, k, n, dtype, cus, vec_ok(A, lda, 2), &P);
-        rc = get_ws(P.ws, ws, ws_bytes, &w);
-        if (rc) return rc;
         LaunchNN L{};
         L.fn = P.fn;
-        L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C;
+        L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = Bk; L.ldb = ldbk; L.C = C;
         L.ldc = ldc; L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S;
-        L.kslice = P.kslice;
+        L.kslice = P.kslice; L.beta = beta;
         if (P.S > 1) L.part = (double*)w;
         launch_tsm2r_lp(L, dtype, st);
         return check_launch("tsm2r_lp_kernel");
     }
-    if (rowA) {
-        // A row-major m x k is the column-major k x m matrix X = A^T (ld lda):
+    if (transA) {
+        // A given transposed is the column-major k x m matrix X = A^T (ld lda):
         // C = X^T * B, a reduction along the contiguous dimension.
         TNPlan P = plan_tn(k, m, n, dtype, cus);
-        rc = get_ws(P.ws, ws, ws_bytes, &w);
-        if (rc) return rc;
         LaunchTN L{};
         L.R = k; L.ncols = m; L.n = n;
-        L.X = A; L.ldx = lda; L.Y = B; L.ldy = ldb; L.O = C; L.ldo = ldc;
-        L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg;
+        L.X = A; L.ldx = lda; L.Y = Bk; L.ldy = ldbk; L.O = C; L.ldo = ldc;
+        L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg; L.beta = beta;
         if (P.S > 1) L.part = (double*)w;
         if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_kernel");
     }
     NNPlan P{};
     if (plan_tsm2r(m, k, n, dtype, cus, vec_ok(A, lda, esize(dtype)), &P)) return TSM_ERR_UNSUPPORTED;
-    rc = get_ws(P.ws, ws, ws_bytes, &w);
-    if (rc) return rc;
     LaunchNN L{};
     L.fn = P.fn;
-    L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.C = C; L.ldc = ldc;
+    L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = Bk; L.ldb = ldbk; L.C = C; L.ldc = ldc;
     L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
+    L.beta = beta;
     if (P.S > 1) L.part = (double*)w;
     if (launch_tsm2r_nn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("tsm2r_nn_kernel");
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsm2r_ex(int transA, int transB, int64_t m, int64_t k, int64_t n, const void* A,
+             int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+             int dtype, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_ex(transA, transB, m, k, n, A, lda, B, ldb, C, ldc, dtype);
+    if (rc) return rc;
+    return product(false, transA, transB, m, k, n, A, lda, B, ldb, beta, C, ldc, dtype, ws,
+                   ws_bytes, (hipStream_t)stream);
+}
+
+int tsm2l_ex(int transA, int transB, int64_t m, int64_t k, int64_t n, const void* A,
+             int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+             int dtype, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_ex(transA, transB, m, k, n, A, lda, B, ldb, C, ldc, dtype);
+    if (rc) return rc;
+    return product(true, transA, transB, m, k, n, A, lda, B, ldb, beta, C, ldc, dtype, ws,
+                   ws_bytes, (hipStream_t)stream);
+}
+
+int tsm2x_gemm(int transA, int transB, int64_t m, int64_t k, int64_t n, const void* A,
+               int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+               int dtype, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_ex(transA, transB, m, k, n, A, lda, B, ldb, C, ldc, dtype);
+    if (rc) return rc;
+    // the paper's two shape classes: a tall-and-skinny A (k small, all of B on
+    // chip) goes to TSM2L, a large A to TSM2R
+    const bool lform = transA == 0 && k <= 32;
+    return product(lform, transA, transB, m, k, n, A, lda, B, ldb, beta, C, ldc, dtype, ws,
+                   ws_bytes, (hipStream_t)stream);
 }
 
 int tsm2r(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
           int64_t ldb, void* C, int64_t ldc, int dtype, void* stream) {
     int rc = check_mm(1, m, k, n, A, lda, B, ldb, C, ldc, dtype, false);
     if (rc) return rc;
-    return tsm2r_ex(TSM_COL_MAJOR, m, k, n, A, lda, B, ldb, C, ldc, dtype, nullptr, 0, stream);
+    return product(false, 0, 0, m, k, n, A, lda, B, ldb, 0.0, C, ldc, dtype, nullptr, 0,
+                   (hipStream_t)stream);
 }
 
 int tsm2l(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
           int64_t ldb, void* C, int64_t ldc, int dtype, void* stream) {
     int rc = check_mm(1, m, k, n, A, lda, B, ldb, C, ldc, dtype, false);
     if (rc) return rc;
-    if (k > 32 || n > 32) return TSM_ERR_UNSUPPORTED;
-    if (m == 0 || n == 0) return TSM_SUCCESS;
-    hipStream_t st = (hipStream_t)stream;
-    if (k == 0) {
-        launch_fill_zero(m, n, C, ldc, plain_dtype(dtype) ? dtype : TSM_F32, st);
-        return check_launch("fill_zero");
-    }
-    if (!plain_dtype(dtype)) {
-        launch_tsm2l_lp(m, k, n, A, lda, (const float*)B, ldb, (float*)C, ldc, dtype, cu_count(),
-                        st);
-        return check_launch("tsm2l_lp_kernel");
-    }
-    RTPlan P = plan_rowtile(m, k, n, dtype, cu_count());
-    LaunchRT L{};
-    L.m = m; L.kin = (int)k; L.nout = n; L.X = A; L.ldx = lda; L.Y = B; L.ys_in = 1;
-    L.ys_out = ldb; L.O = C; L.ldo = ldc; L.kp = P.kp; L.cols_per_block = (int)P.cpb;
-    L.blocks_x = P.bx; L.blocks_y = P.by; L.cus = cu_count();
-    if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
-    return check_launch("rowtile_kernel");
+    return product(true, 0, 0, m, k, n, A, lda, B, ldb, 0.0, C, ldc, dtype, nullptr, 0,
+                   (hipStream_t)stream);
 }
 
 int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc, const void* B,
@@ -325,8 +419,8 @@ int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc, co
     if (m == 0 || k == 0) return TSM_SUCCESS;
     hipStream_t st = (hipStream_t)stream;
     if (n == 0) {
-        launch_fill_zero(m, k, dA, ldda, dtype, st);
-        return check_launch("fill_zero");
+        launch_fill_scale(m, k, dA, ldda, 0.0, dtype, st);
+        return check_launch("fill_scale_kernel");
     }
     // dA = dC * B^T: X = dC (m x n), Y(p, j) = B[j + p*ldb].
     RTPlan P = plan_rowtile(m, n, k, dtype, cu_count());
@@ -355,8 +449,8 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     if (k == 0 || n == 0) return TSM_SUCCESS;
     hipStream_t st = (hipStream_t)stream;
     if (m == 0) {
-        launch_fill_zero(k, n, dB, lddb, plain_dtype(dtype) ? dtype : TSM_F32, st);
-        return check_launch("fill_zero");
+        launch_fill_scale(k, n, dB, lddb, 0.0, plain_dtype(dtype) ? dtype : TSM_F32, st);
+        return check_launch("fill_scale_kernel");
     }
     // dB = A^T * dC: X = A (R = m rows, k columns), Y = dC.
     TNPlan P = plan_tn(m, k, n, dtype, cu_count());
@@ -397,9 +491,9 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, 
     hipStream_t st = (hipStream_t)stream;
     if (m == 0 || n == 0) {
         // dA (m x k) is zero when n == 0; dB (k x n) is zero when m == 0
-        if (m > 0) launch_fill_zero(m, k, dA, ldda, dtype, st);
-        if (n > 0) launch_fill_zero(k, n, dB, lddb, dtype, st);
-        return check_launch("fill_zero");
+        if (m > 0) launch_fill_scale(m, k, dA, ldda, 0.0, dtype, st);
+        if (n > 0) launch_fill_scale(k, n, dB, lddb, 0.0, dtype, st);
+        return check_launch("fill_scale_kernel");
     }
     LaunchBwd L{};
     L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = B; L.ldb = ldb; L.dC = dC;
@@ -430,23 +524,14 @@ int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, voi
 }
 
 size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n, int dtype) {
-    if (m <= 0 || k <= 0 || n <= 0 || n > 32 || !valid_dtype(dtype)) return 0;
-    const int cus = cu_count();
-    if (!plain_dtype(dtype)) {
-        if (op == TSM_OP_GRAD_B) return plan_tn(m, k, n, dtype, cus).ws;
-        if (op != TSM_OP_TSM2R) return 0;
-        NNPlan P{};
-        plan_tsm2r_lp(m, k, n, dtype, cus, true, &P);
-        return P.ws;
-    }
+    if (m <= 0 || k <= 0 || n <= 0 || !valid_dtype(dtype)) return 0;
+    const int64_t np = n < 32 ? n : 32;      // panels of 32 columns reuse one workspace
+    // products: enough for a B given transposed as well
     switch (op) {
-        case TSM_OP_TSM2R: {
-            NNPlan P{};
-            // the aligned and unaligned instances share their tiling
-            return plan_tsm2r(m, k, n, dtype, cus, true, &P) ? 0 : P.ws;
-        }
-        case TSM_OP_TSM2R_ROWMAJOR: return plan_tn(k, m, n, dtype, cus).ws;
-        case TSM_OP_GRAD_B: return plan_tn(m, k, n, dtype, cus).ws;
+        case TSM_OP_TSM2R: return tsm2r_ws(0, m, k, np, dtype, true);
+        case TSM_OP_TSM2R_ROWMAJOR: return plain_dtype(dtype) ? tsm2r_ws(1, m, k, np, dtype, true) : 0;
+        case TSM_OP_TSM2L: return k <= 32 ? 0 : tsm2r_ws(0, m, k, np, dtype, true);
+        case TSM_OP_GRAD_B: return n <= 32 ? plan_tn(m, k, n, dtype, cu_count()).ws : 0;
         default: return 0;
     }
 }

@@ -84,15 +84,22 @@ template <> struct Mfma<double> {
     }
 };
 
+// An output element: v, or v + beta * (old value) when beta != 0 (the old
+// value is read only then), added in double and rounded once to T.
+template <typename T>
+__device__ __forceinline__ T beta_out(double v, double beta, const T* p) {
+    return (T)(beta != 0.0 ? v + beta * (double)*p : v);
+}
+
 // Sum of the WK wavefronts' partials (double, wavefront order) for one row
 // tile.  With one k slice the result is the output; otherwise it is this
 // workgroup's partial, part[((tile * nsl + s) * NP + p) * TR + row], and a
 // second kernel (split_reduce_kernel) adds the slices in order.  `red` is LDS
 // scratch of [WK][PG][TR] doubles; put(pg, red) stores this wavefront's values
-// of columns pg .. pg+PG-1.
+// of columns pg .. pg+PG-1.  C := beta*C + sum (C is read only if beta != 0).
 template <typename T, int NP, int WK, int TR, int PG, typename Put>
 __device__ __forceinline__ void nn_finish(int64_t m, int n, T* __restrict__ C, int64_t ldc,
-                                          int64_t tile, int s, int nsl,
+                                          double beta, int64_t tile, int s, int nsl,
                                           double* __restrict__ part, double* red, Put&& put) {
     constexpr int NT = WAVE * WK;
     const int64_t row0 = tile * TR;
@@ -111,7 +118,7 @@ __device__ __forceinline__ void nn_finish(int64_t m, int n, T* __restrict__ C, i
                 for (int ww = 1; ww < WK; ++ww) v += red[(ww * PG + pp) * TR + rr];
                 if (p < n && row < m) {
                     if (nsl == 1)
-                        C[row + p * ldc] = (T)v;
+                        C[row + p * ldc] = beta_out(v, beta, C + row + p * ldc);
                     else
                         part[((tile * nsl + s) * NP + p) * TR + rr] = v;
                 }
@@ -125,7 +132,7 @@ __device__ __forceinline__ void nn_finish(int64_t m, int n, T* __restrict__ C, i
 // part[((ctile * nsl + s) * NP + p) * 16 + c].
 template <typename T, int NT16, int WK, typename Acc, typename MRow>
 __device__ __forceinline__ void tn_finish(int64_t ncols, int n, T* __restrict__ O, int64_t ldo,
-                                          int64_t ctile, int s, int nsl,
+                                          double beta, int64_t ctile, int s, int nsl,
                                           double* __restrict__ part, double (*red)[WAVE][4 * NT16],
                                           const Acc (&acc)[NT16], MRow mrow) {
     constexpr int NV = 4 * NT16;
@@ -147,15 +154,16 @@ __device__ __forceinline__ void tn_finish(int64_t ncols, int n, T* __restrict__ 
         const int64_t col = ctile * 16 + c;
         const int p = 16 * t + (ln & 15);
         if (nsl == 1) {
-            if (col < ncols && p < n) O[col + p * ldo] = (T)v;
+            if (col < ncols && p < n) O[col + p * ldo] = beta_out(v, beta, O + col + p * ldo);
         } else {
             part[((ctile * nsl + s) * NP + p) * 16 + c] = v;
         }
     }
 }
 
-// Ordered sum of split partials: O[g*W + r, p] = sum over s of
-// part[((g * S + s) * NP + p) * W + r], for rows g*W + r < rows and p < n.
+// Ordered sum of split partials: O[g*W + r, p] = beta * O[g*W + r, p] + sum
+// over s of part[((g * S + s) * NP + p) * W + r], for rows g*W + r < rows and
+// p < n (O is read only if beta != 0).
 // One thread per output when S is small.  For many slices one wavefront
 // per output: lane l adds slices l, l+64, ... in order, then a butterfly in a
 // fixed pattern combines the lanes, so the result does not depend on timing.
@@ -163,7 +171,8 @@ template <typename T, bool WIDE>
 __global__ __launch_bounds__(256) void split_reduce_kernel(int64_t groups, int S, int NP, int W,
                                                            int64_t rows, int n,
                                                            const double* __restrict__ part,
-                                                           T* __restrict__ O, int64_t ldo) {
+                                                           T* __restrict__ O, int64_t ldo,
+                                                           double beta) {
     const int64_t E = (int64_t)NP * W;
     const int64_t total = groups * E;
     if (!WIDE) {
@@ -175,7 +184,7 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(int64_t groups, int S
             if (p < n && row < rows) {
                 double v = 0.0;
                 for (int s = 0; s < S; ++s) v += part[(g * S + s) * E + e];
-                O[row + p * ldo] = (T)v;
+                O[row + p * ldo] = beta_out(v, beta, O + row + p * ldo);
             }
         }
     } else {
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(int64_t groups, int S
                 for (int s = lane; s < S; s += WAVE) v += part[(g * S + s) * E + e];
 #pragma unroll
                 for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-                if (lane == 0) O[row + p * ldo] = (T)v;
+                if (lane == 0) O[row + p * ldo] = beta_out(v, beta, O + row + p * ldo);
             }
         }
     }

@@ -225,7 +225,7 @@ static int bwd_launch(const LaunchBwd& L, int64_t* blocks_out, hipStream_t st, b
                            (const T*)L.dC, L.lddc, (T*)L.dA, L.ldda, L.part);
     if (hipGetLastError() != hipSuccess) return 1;
     return launch_split_reduce(sizeof(T) == 8 ? DT_F64 : DT_F32, 1, (int)bx, 16 * NTN, 16 * NTK,
-                               L.k, (int)L.n, L.part, L.dB, L.lddb, st);
+                               L.k, (int)L.n, L.part, L.dB, L.lddb, 0.0, st);
 }
 
 template <typename T>

@@ -37,6 +37,7 @@ struct LaunchNN {           // tsm2r_nn: C = A*B, column-major A
     int S;                  // k slices (gridDim.y)
     int64_t kslice;         // columns per k slice
     double* part;           // S > 1: partial sums (workspace)
+    double beta;            // C := beta*C + A*B (C read only if beta != 0)
 };
 
 struct LaunchRT {           // rowtile: O = X*Y, X m x kin (kin <= 32)
@@ -49,6 +50,7 @@ struct LaunchRT {           // rowtile: O = X*Y, X m x kin (kin <= 32)
     int64_t blocks_x;       // upper bound on gridDim.x (0: none)
     int64_t blocks_y;
     int cus;                // compute units of the device
+    double beta;            // O := beta*O + X*Y (O read only if beta != 0)
 };
 
 struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
@@ -61,6 +63,7 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
     int64_t rslice;
     int rg;                 // stages per wavefront loop iteration (1, 2 or 4)
     double* part;           // S > 1: partial sums (workspace)
+    double beta;            // O := beta*O + X^T*Y (O read only if beta != 0)
 };
 
 // Low-precision storage forms of A (bf16 / f16, single or split planes).
@@ -68,8 +71,10 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
 int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st);
 int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
                  int64_t ldh, int fmt, hipStream_t st);
+// B(j, p) = B[j*bsj + p*bsp]
 int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
-                    int64_t ldb, float* C, int64_t ldc, int dtype, int cus, hipStream_t st);
+                    int64_t bsj, int64_t bsp, float beta, float* C, int64_t ldc, int dtype,
+                    int cus, hipStream_t st);
 
 struct LaunchBwd {          // fused TSM2L backward: dA = dC*B^T, dB = A^T*dC
     int64_t m, k, n;
@@ -90,10 +95,16 @@ struct LaunchTN;
 int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st);
 int launch_rowtile(const LaunchRT& L, int dtype, hipStream_t st);
 int launch_tn(const LaunchTN& L, int dtype, hipStream_t st);
-int launch_fill_zero(int64_t m, int64_t n, void* C, int64_t ldc, int dtype, hipStream_t st);
+// C := beta*C for an m x n matrix (zeros when beta == 0, C then not read)
+int launch_fill_scale(int64_t m, int64_t n, void* C, int64_t ldc, double beta, int dtype,
+                      hipStream_t st);
+// O (k x n, ld ldo) := the transpose of Bt (n x k, ld ldb), for a B given
+// transposed
+int launch_transpose(int64_t k, int64_t n, const void* Bt, int64_t ldb, void* O, int64_t ldo,
+                     int dtype, hipStream_t st);
 // Ordered sum over S slices of double partials laid out [g][s][NP][W] into
-// O[g*W + r + p*ldo] (rows g*W + r < rows, p < n).
+// O[g*W + r + p*ldo] := beta*O + sum (rows g*W + r < rows, p < n).
 int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t rows, int n,
-                        const double* part, void* O, int64_t ldo, hipStream_t st);
+                        const double* part, void* O, int64_t ldo, double beta, hipStream_t st);
 
 }  // namespace tsm

@@ -48,7 +48,7 @@ template <typename T, int KS, int NT16, int RG, bool VEC, bool PF>
 __global__ __launch_bounds__(256) void rowtile_kernel(
     int64_t m, int kin, int64_t nout, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ys_in, int64_t ys_out, T* __restrict__ O,
-    int64_t ldo, int64_t cols_per_block) {
+    int64_t ldo, int64_t cols_per_block, T beta) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -136,6 +136,12 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
                             T v[RL];
 #pragma unroll
                             for (int q = 0; q < RL; ++q) v[q] = acc[g][q][t][rr];
+                            if (beta != T(0)) {     // O is read only then
+                                T o[RL];
+                                load_run<T, RL, VEC>(O + r + col * ldo, m - r, full, o);
+#pragma unroll
+                                for (int q = 0; q < RL; ++q) v[q] = __builtin_fma(beta, o[q], v[q]);
+                            }
                             store_run<T, RL, VEC>(O + r + col * ldo, m - r, full, v);
                         }
                     }
@@ -181,7 +187,7 @@ template <typename T, int NT16, int G, bool VEC>
 __global__ __launch_bounds__(256) void tn_kernel(
     int64_t R, int64_t ncols, int n, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ O, int64_t ldo,
-    int64_t rslice, double* __restrict__ part) {
+    int64_t rslice, double* __restrict__ part, double beta) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -280,17 +286,33 @@ __global__ __launch_bounds__(256) void tn_kernel(
         }
     }
 
-    tn_finish<T, NT16, WK>(ncols, n, O, ldo, ctile, s, nsl, part, red, acc,
+    tn_finish<T, NT16, WK>(ncols, n, O, ldo, beta, ctile, s, nsl, part, red, acc,
                            [](int kq, int r) { return Mfma<T>::mrow(kq, r); });
 }
 
+// C := beta * C (zeros when beta == 0; C is then not read): the product of an
+// empty k dimension.
 template <typename T>
-__global__ void fill_zero_kernel(int64_t m, int64_t n, T* __restrict__ C, int64_t ldc) {
+__global__ void fill_scale_kernel(int64_t m, int64_t n, T* __restrict__ C, int64_t ldc,
+                                  T beta) {
     const int64_t total = m * n;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e % m, p = e / m;
-        C[i + p * ldc] = T(0);
+        C[i + p * ldc] = beta != T(0) ? beta * C[i + p * ldc] : T(0);
+    }
+}
+
+// O (k x n, ld ldo) := transpose of Bt (n x k, ld ldb): a B given transposed,
+// copied once into the workspace in the layout the TSM2R kernels read.
+template <typename T>
+__global__ void transpose_kernel(int64_t k, int64_t n, const T* __restrict__ Bt, int64_t ldb,
+                                 T* __restrict__ O, int64_t ldo) {
+    const int64_t total = k * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e % n, j = e / n;      // consecutive threads read along Bt's column
+        O[j + p * ldo] = Bt[p + j * ldb];
     }
 }
 
@@ -325,11 +347,11 @@ static int rowtile_launch_pf(const LaunchRT& L, bool vec, hipStream_t st) {
     if (vec)
         hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, true, PF>), grid, block, 0, st, L.m,
                            L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
-                           (T*)L.O, L.ldo, (int64_t)L.cols_per_block);
+                           (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
     else
         hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, false, PF>), grid, block, 0, st, L.m,
                            L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in,
-                           L.ys_out, (T*)L.O, L.ldo, (int64_t)L.cols_per_block);
+                           L.ys_out, (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
     return 0;
 }
 
@@ -367,11 +389,11 @@ static int tn_launch(const LaunchTN& L, bool vec, hipStream_t st) {
     if (vec)
         hipLaunchKernelGGL((tn_kernel<T, NT16, G, true>), grid, block, 0, st, L.R, L.ncols,
                            (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
-                           L.rslice, L.part);
+                           L.rslice, L.part, L.beta);
     else
         hipLaunchKernelGGL((tn_kernel<T, NT16, G, false>), grid, block, 0, st, L.R, L.ncols,
                            (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
-                           L.rslice, L.part);
+                           L.rslice, L.part, L.beta);
     return 0;
 }
 
@@ -388,7 +410,8 @@ static int tn_dispatch(const LaunchTN& L, hipStream_t st) {
     else rc = L.n <= 16 ? tn_launch<T, 1, 1>(L, vec, st) : tn_launch<T, 2, 1>(L, vec, st);
     if (rc || L.S <= 1) return rc;
     return launch_split_reduce(sizeof(T) == 8 ? DT_F64 : DT_F32, L.groups, L.S,
-                               L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n, L.part, L.O, L.ldo, st);
+                               L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n, L.part, L.O, L.ldo,
+                               L.beta, st);
 }
 
 int launch_tn(const LaunchTN& L, int dtype, hipStream_t st) {
@@ -398,7 +421,7 @@ int launch_tn(const LaunchTN& L, int dtype, hipStream_t st) {
 }
 
 int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t rows, int n,
-                        const double* part, void* O, int64_t ldo, hipStream_t st) {
+                        const double* part, void* O, int64_t ldo, double beta, hipStream_t st) {
     const int64_t total = groups * NP * W;
     const bool wide = S >= 16;
     int64_t blocks = wide ? (total + 3) / 4 : (total + 255) / 256;
@@ -408,32 +431,49 @@ int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t
     if (dtype == DT_F64) {
         if (wide)
             hipLaunchKernelGGL((split_reduce_kernel<double, true>), g, b, 0, st, groups, S, NP, W,
-                               rows, n, part, (double*)O, ldo);
+                               rows, n, part, (double*)O, ldo, beta);
         else
             hipLaunchKernelGGL((split_reduce_kernel<double, false>), g, b, 0, st, groups, S, NP,
-                               W, rows, n, part, (double*)O, ldo);
+                               W, rows, n, part, (double*)O, ldo, beta);
     } else {
         if (wide)
             hipLaunchKernelGGL((split_reduce_kernel<float, true>), g, b, 0, st, groups, S, NP, W,
-                               rows, n, part, (float*)O, ldo);
+                               rows, n, part, (float*)O, ldo, beta);
         else
             hipLaunchKernelGGL((split_reduce_kernel<float, false>), g, b, 0, st, groups, S, NP, W,
-                               rows, n, part, (float*)O, ldo);
+                               rows, n, part, (float*)O, ldo, beta);
     }
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
-int launch_fill_zero(int64_t m, int64_t n, void* C, int64_t ldc, int dtype, hipStream_t st) {
-    const int64_t total = m * n;
+static dim3 flat_grid(int64_t total) {
     int64_t blocks = (total + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
+    return dim3((unsigned)blocks);
+}
+
+int launch_fill_scale(int64_t m, int64_t n, void* C, int64_t ldc, double beta, int dtype,
+                      hipStream_t st) {
+    const dim3 g = flat_grid(m * n);
     if (dtype == DT_F64)
-        hipLaunchKernelGGL(fill_zero_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, m, n,
-                           (double*)C, ldc);
+        hipLaunchKernelGGL(fill_scale_kernel<double>, g, dim3(256), 0, st, m, n, (double*)C, ldc,
+                           beta);
     else
-        hipLaunchKernelGGL(fill_zero_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, m, n,
-                           (float*)C, ldc);
+        hipLaunchKernelGGL(fill_scale_kernel<float>, g, dim3(256), 0, st, m, n, (float*)C, ldc,
+                           (float)beta);
+    return 0;
+}
+
+int launch_transpose(int64_t k, int64_t n, const void* Bt, int64_t ldb, void* O, int64_t ldo,
+                     int dtype, hipStream_t st) {
+    const dim3 g = flat_grid(k * n);
+    if (dtype == DT_F64)
+        hipLaunchKernelGGL(transpose_kernel<double>, g, dim3(256), 0, st, k, n, (const double*)Bt,
+                           ldb, (double*)O, ldo);
+    else
+        hipLaunchKernelGGL(transpose_kernel<float>, g, dim3(256), 0, st, k, n, (const float*)Bt,
+                           ldb, (float*)O, ldo);
     return 0;
 }
 

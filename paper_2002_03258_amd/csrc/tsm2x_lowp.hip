@@ -153,7 +153,8 @@ template <int FMT, int NT16, bool SPLIT, int WK, bool VEC>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, const float* __restrict__ B, int64_t ldb,
-    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part, int bvec) {
+    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part, int bvec,
+    double beta) {
     constexpr int TR = 128;              // 16 lanes x 8 rows
     constexpr int NP = 16 * NT16;
     constexpr int PG = 4;
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     }
 
     // lane holds C[r + q, 16 t + 4 kk + rr] in acc[q][t][rr]
-    nn_finish<float, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part,
+    nn_finish<float, NP, WK, TR, PG>(m, n, C, ldc, beta, tile, s, nsl, part,
                                      reinterpret_cast<double*>(smem), [&](int pg, double* red) {
         const int t = pg / 16;
 #pragma unroll
@@ -360,7 +361,8 @@ template <int FMT, int KS, int NT16, bool SPLIT, bool VEC>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_kernel(
     int64_t m, int k, int n, const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
-    int64_t lda, const float* __restrict__ B, int64_t ldb, float* __restrict__ C, int64_t ldc) {
+    int64_t lda, const float* __restrict__ B, int64_t bsj, int64_t bsp, float beta,
+    float* __restrict__ C, int64_t ldc) {
     typedef Mfma<float> M;
     constexpr int RL = 8;                // rows per 16-byte run of 16-bit values
     constexpr int TR = 16 * RL;
@@ -377,7 +379,7 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 #pragma unroll
         for (int t = 0; t < NT16; ++t) {
             const int j = 4 * st + kk, p = 16 * t + rl;
-            bv[st][t] = (j < k && p < n) ? B[j + (int64_t)p * ldb] : 0.f;
+            bv[st][t] = (j < k && p < n) ? B[j * bsj + (int64_t)p * bsp] : 0.f;
         }
 
     auto load = [&](int64_t tile, uint32_t (&raw)[KS][NPL][4]) {
@@ -435,10 +437,20 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
                         v0[q] = acc[q][t][rr];
                         v1[q] = acc[4 + q][t][rr];
                     }
+                    float* c = C + r + (int64_t)col * ldc;
+                    if (beta != 0.f) {
+                        float o0[4], o1[4];
+                        load_run<float, 4, VEC>(c, m - r, full, o0);
+                        load_run<float, 4, VEC>(c + 4, m - r - 4, full, o1);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            v0[q] = __builtin_fmaf(beta, o0[q], v0[q]);
+                            v1[q] = __builtin_fmaf(beta, o1[q], v1[q]);
+                        }
+                    }
                     // the two stores fill alternate 16-byte halves of the lines
-                    store_run<float, 4, VEC, false>(C + r + (int64_t)col * ldc, m - r, full, v0);
-                    store_run<float, 4, VEC, false>(C + r + 4 + (int64_t)col * ldc, m - r - 4, full,
-                                                    v1);
+                    store_run<float, 4, VEC, false>(c, m - r, full, v0);
+                    store_run<float, 4, VEC, false>(c + 4, m - r - 4, full, v1);
                 }
             }
         if (more) {
@@ -589,7 +601,7 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
         }
     }
 
-    tn_finish<float, NT16, WK>(ncols, n, O, ldo, ctile, s, nsl, part, red, acc,
+    tn_finish<float, NT16, WK>(ncols, n, O, ldo, 0.0, ctile, s, nsl, part, red, acc,
                                [](int kq, int r) { return Mfma<float>::mrow(kq, r); });
 }
 
@@ -663,23 +675,24 @@ int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st) {
     int n32 = (int)L.n;
     // 16-byte loads of B's column runs need an aligned B with ldb % 4 == 0
     int bvec = ((uintptr_t)L.B & 15u) == 0 && (L.ldb % 4) == 0;
+    double beta = L.beta;
     void* args[] = {(void*)&L.m,   (void*)&L.k,   (void*)&n32,      (void*)&ah,
                     (void*)&al,    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,
                     (void*)&L.C,   (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part,
-                    (void*)&bvec};
+                    (void*)&bvec,  (void*)&beta};
     hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
                                    0, st);
     if (e != hipSuccess) return 1;
     if (L.S > 1)
         return launch_split_reduce(DT_F32, L.tiles, L.S, L.np, 128, L.m, (int)L.n, L.part, L.C,
-                                   L.ldc, st);
+                                   L.ldc, L.beta, st);
     return 0;
 }
 
 template <int FMT, int KS, int NT16, bool SPLIT>
 static void tsm2l_lp_go(int64_t m, int k, int n, const uint16_t* ah, const uint16_t* al,
-                        int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
-                        bool vec, int cus, hipStream_t st) {
+                        int64_t lda, const float* B, int64_t bsj, int64_t bsp, float beta,
+                        float* C, int64_t ldc, bool vec, int cus, hipStream_t st) {
     // k <= 16: one 128-row tile per wavefront (measured faster); k = 32: a
     // persistent grid of as many workgroups as fit at once, each wavefront
     // prefetching its next tile.  Never more than there are groups of 4 tiles.
@@ -695,18 +708,19 @@ static void tsm2l_lp_go(int64_t m, int k, int n, const uint16_t* ah, const uint1
     dim3 g((unsigned)blocks), b(256);
     if (vec)
         hipLaunchKernelGGL((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, true>), g, b, 0, st, m, k, n, ah,
-                           al, lda, B, ldb, C, ldc);
+                           al, lda, B, bsj, bsp, beta, C, ldc);
     else
         hipLaunchKernelGGL((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, false>), g, b, 0, st, m, k, n,
-                           ah, al, lda, B, ldb, C, ldc);
+                           ah, al, lda, B, bsj, bsp, beta, C, ldc);
 }
 
 template <int FMT, bool SPLIT>
 static void tsm2l_lp_ks(int64_t m, int k, int n, const uint16_t* ah, const uint16_t* al,
-                        int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc, bool vec,
-                        int cus, hipStream_t st) {
-#define TSM_L(KS, NT)                                                                       \
-    tsm2l_lp_go<FMT, KS, NT, SPLIT>(m, k, n, ah, al, lda, B, ldb, C, ldc, vec, cus, st); \
+                        int64_t lda, const float* B, int64_t bsj, int64_t bsp, float beta,
+                        float* C, int64_t ldc, bool vec, int cus, hipStream_t st) {
+#define TSM_L(KS, NT)                                                                          \
+    tsm2l_lp_go<FMT, KS, NT, SPLIT>(m, k, n, ah, al, lda, B, bsj, bsp, beta, C, ldc, vec, cus, \
+                                    st);                                                        \
     return
     if (k <= 8) { if (n <= 16) { TSM_L(2, 1); } TSM_L(2, 2); }
     if (k <= 16) { if (n <= 16) { TSM_L(4, 1); } TSM_L(4, 2); }
@@ -716,7 +730,8 @@ static void tsm2l_lp_ks(int64_t m, int k, int n, const uint16_t* ah, const uint1
 }
 
 int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const float* B,
-                    int64_t ldb, float* C, int64_t ldc, int dtype, int cus, hipStream_t st) {
+                    int64_t bsj, int64_t bsp, float beta, float* C, int64_t ldc, int dtype,
+                    int cus, hipStream_t st) {
     const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
     const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
     const bool vec = ((uintptr_t)A & 15u) == 0 && (lda % 8) == 0 && ((uintptr_t)C & 15u) == 0 &&
@@ -725,11 +740,15 @@ int launch_tsm2l_lp(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
     const uint16_t* al = split ? ah + lda * k : nullptr;
     const int ki = (int)k, ni = (int)n;
     if (fmt == FMT_BF16) {
-        if (split) tsm2l_lp_ks<FMT_BF16, true>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
-        else tsm2l_lp_ks<FMT_BF16, false>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
+        if (split)
+            tsm2l_lp_ks<FMT_BF16, true>(m, ki, ni, ah, al, lda, B, bsj, bsp, beta, C, ldc, vec, cus, st);
+        else
+            tsm2l_lp_ks<FMT_BF16, false>(m, ki, ni, ah, al, lda, B, bsj, bsp, beta, C, ldc, vec, cus, st);
     } else {
-        if (split) tsm2l_lp_ks<FMT_F16, true>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
-        else tsm2l_lp_ks<FMT_F16, false>(m, ki, ni, ah, al, lda, B, ldb, C, ldc, vec, cus, st);
+        if (split)
+            tsm2l_lp_ks<FMT_F16, true>(m, ki, ni, ah, al, lda, B, bsj, bsp, beta, C, ldc, vec, cus, st);
+        else
+            tsm2l_lp_ks<FMT_F16, false>(m, ki, ni, ah, al, lda, B, bsj, bsp, beta, C, ldc, vec, cus, st);
     }
     return 0;
 }
@@ -770,7 +789,7 @@ int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st) {
     const int rc = launch_tn_lp_main(L, dtype, st);
     if (rc || L.S <= 1) return rc;
     return launch_split_reduce(DT_F32, L.groups, L.S, L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n,
-                               L.part, L.O, L.ldo, st);
+                               L.part, L.O, L.ldo, 0.0, st);
 }
 
 int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,

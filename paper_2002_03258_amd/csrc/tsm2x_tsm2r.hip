@@ -41,7 +41,7 @@ __global__ __launch_bounds__(WAVE * WK)
 __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kernel(
     int64_t m, int64_t k, int n, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
-    int64_t kslice, double* __restrict__ part, int bvec) {
+    int64_t kslice, double* __restrict__ part, int bvec, double beta) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -154,7 +154,7 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
         }
     }
 
-    nn_finish<T, NP, WK, TR, PG>(m, n, C, ldc, tile, s, nsl, part,
+    nn_finish<T, NP, WK, TR, PG>(m, n, C, ldc, beta, tile, s, nsl, part,
                                  reinterpret_cast<double*>(smem), [&](int pg, double* red) {
         const int t = pg / 16;
 #pragma unroll
@@ -294,15 +294,17 @@ int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
     // 16-byte loads of B's column runs need an aligned B with ldb*size % 16 == 0
     const int es = dtype == DT_F64 ? 8 : 4;
     int bvec = aligned16(L.B) && ((L.ldb * es) % 16 == 0);
+    double beta = L.beta;
     void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&n32,    (void*)&L.A,
                     (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,
-                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&bvec};
+                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&bvec,
+                    (void*)&beta};
     hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
                                    0, st);
     if (e != hipSuccess) return 1;
     if (L.S > 1)
         return launch_split_reduce(dtype, L.tiles, L.S, L.np, L.tile_rows, L.m, (int)L.n, L.part,
-                                   L.C, L.ldc, st);
+                                   L.C, L.ldc, L.beta, st);
     return 0;
 }
 

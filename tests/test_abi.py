@@ -54,24 +54,44 @@ P = 4096  # a non-null dummy address: never dereferenced, validation fails first
     ((4, 4, 4, P, 4, P, 4, NULL, 4, 0, NULL), -8),
     ((4, 4, 4, P, 4, P, 4, P, 3, 0, NULL), -9),
     ((4, 4, 4, P, 4, P, 4, P, 4, 9, NULL), -10),
-    ((4, 4, 33, P, 4, P, 4, P, 4, 0, NULL), 1),
 ])
 def test_tsm2r_argument_checks(args, expect):
     assert _lib.lib().tsm2r(*args) == expect
 
 
-def test_tsm2l_limits_and_checks():
+def test_tsm2l_checks():
     L = _lib.lib()
-    assert L.tsm2l(8, 33, 4, P, 8, P, 33, P, 8, 0, NULL) == 1
-    assert L.tsm2l(8, 4, 33, P, 8, P, 4, P, 8, 0, NULL) == 1
     assert L.tsm2l(8, 4, 4, P, 7, P, 4, P, 8, 0, NULL) == -5
+    assert L.tsm2l(8, 4, 4, P, 8, P, 3, P, 8, 0, NULL) == -7
 
 
-def test_rowmajor_lda_check():
-    L = _lib.lib()
-    # row-major A needs lda >= k
-    assert L.tsm2r_ex(1, 8, 16, 4, P, 15, P, 16, P, 8, 0, NULL, 0, NULL) == -6
-    assert L.tsm2r_ex(2, 8, 16, 4, P, 16, P, 16, P, 8, 0, NULL, 0, NULL) == -1
+# extended forms: 1 transA, 2 transB, 3 m, 4 k, 5 n, 6 A, 7 lda, 8 B, 9 ldb,
+# 10 beta, 11 C, 12 ldc, 13 dtype, 14 ws, 15 ws_bytes, 16 stream
+EX_OK = [0, 0, 8, 16, 4, P, 8, P, 16, 0.0, P, 8, 0, NULL, 0, NULL]
+
+
+@pytest.mark.parametrize("fn", ["tsm2r_ex", "tsm2l_ex", "tsm2x_gemm"])
+@pytest.mark.parametrize("pos,bad,expect", [
+    (0, 2, -1), (1, -1, -2), (2, -1, -3), (3, -1, -4), (4, -1, -5), (5, NULL, -6),
+    (6, 7, -7), (7, NULL, -8), (8, 15, -9), (10, NULL, -11), (11, 7, -12), (12, 9, -13),
+])
+def test_extended_argument_checks(fn, pos, bad, expect):
+    args = list(EX_OK)
+    args[pos] = bad
+    assert getattr(_lib.lib(), fn)(*args) == expect
+
+
+@pytest.mark.parametrize("fn", ["tsm2r_ex", "tsm2l_ex", "tsm2x_gemm"])
+def test_extended_transposed_leading_dimensions(fn):
+    L = getattr(_lib.lib(), fn)
+    # transA = 1: A is k x m, lda >= k; transB = 1: B is n x k, ldb >= n
+    assert L(1, 0, 8, 16, 4, P, 15, P, 16, 0.0, P, 8, 0, NULL, 0, NULL) == -7
+    assert L(0, 1, 8, 16, 4, P, 8, P, 3, 0.0, P, 8, 0, NULL, 0, NULL) == -9
+    # a 16-bit form of A must not be transposed (valid arguments otherwise)
+    assert L(1, 0, 8, 16, 4, P, 16, P, 16, 0.0, P, 8, 2, NULL, 0, NULL) == 1
+    # empty products: no work, no GPU needed
+    assert L(0, 0, 0, 16, 4, NULL, 1, P, 16, 1.0, NULL, 1, 0, NULL, 0, NULL) == 0
+    assert L(0, 1, 8, 16, 0, P, 8, NULL, 1, 0.0, NULL, 8, 1, NULL, 0, NULL) == 0
 
 
 def test_grad_argument_checks():

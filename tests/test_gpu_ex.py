@@ -1,0 +1,161 @@
+"""The extended product forms C := beta*C + op(A)*op(B): beta, A and B given
+transposed (row-major tensors), n > 32 in panels, TSM2L shapes with k > 32
+and the shape-class dispatch of tsm2x_gemm, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2002_03258_amd as tsm
+import seeded_inputs as si
+
+from helpers import TOL, dev_matrix, err, host_matrix, to_np
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32]
+STREAM_C0 = si.STREAM_V
+
+
+def _rowmajor(seed, stream, rows, cols, dtype, dev, dist="uniform", r=8):
+    """The same values as dev_matrix, stored row-major (a contiguous tensor)."""
+    return dev_matrix(seed, stream, rows, cols, dtype, dev, dist=dist, r=r).contiguous()
+
+
+def _ref(Ah, Bh, C0h, beta):
+    ref = oracle.matmul(Ah, Bh)
+    return ref + beta * C0h.astype(np.float64) if beta != 0 else ref
+
+
+CASES = [(1000, 3000, 16), (4097, 700, 5), (300, 20000, 8), (9, 70, 3), (2000, 16, 16),
+         (70001, 8, 8), (129, 33, 32)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fn", ["tsm2r", "tsm2l", "gemm"])
+@pytest.mark.parametrize("m,k,n", CASES)
+@pytest.mark.parametrize("beta", [1.0, -0.5])
+def test_beta_accumulates(dev, dtype, fn, m, k, n, beta):
+    seed = 1100 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, dtype, dev)
+    B = dev_matrix(seed, si.STREAM_B, k, n, dtype, dev)
+    C = dev_matrix(seed, STREAM_C0, m, n, dtype, dev)
+    getattr(tsm, fn)(A, B, out=C, beta=beta)
+    ref = _ref(host_matrix(seed, si.STREAM_A, m, k, dtype), host_matrix(seed, si.STREAM_B, k, n, dtype),
+               host_matrix(seed, STREAM_C0, m, n, dtype), beta)
+    assert err(to_np(C), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fn", ["tsm2r", "tsm2l"])
+def test_beta_zero_does_not_read_c(dev, dtype, fn):
+    m, k, n = 3000, 16, 16
+    A = dev_matrix(5, si.STREAM_A, m, k, dtype, dev)
+    B = dev_matrix(5, si.STREAM_B, k, n, dtype, dev)
+    C = tsm.empty_colmajor(m, n, dtype, dev)
+    C.fill_(float("nan"))
+    getattr(tsm, fn)(A, B, out=C, beta=0.0)
+    assert torch.isfinite(C).all()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fn", ["tsm2r", "tsm2l", "gemm"])
+def test_beta_integer_bit_exact(dev, dtype, fn):
+    for (m, k, n) in [(3000, 5000, 16), (5000, 16, 16)]:
+        A = dev_matrix(9, si.STREAM_A, m, k, dtype, dev, dist="int", r=8)
+        B = dev_matrix(9, si.STREAM_B, k, n, dtype, dev, dist="int", r=8)
+        C = dev_matrix(9, STREAM_C0, m, n, dtype, dev, dist="int", r=64)
+        getattr(tsm, fn)(A, B, out=C, beta=-2.0)
+        ref = _ref(host_matrix(9, si.STREAM_A, m, k, dtype, dist="int", r=8),
+                   host_matrix(9, si.STREAM_B, k, n, dtype, dist="int", r=8),
+                   host_matrix(9, STREAM_C0, m, n, dtype, dist="int", r=64), -2.0)
+        assert np.array_equal(to_np(C), ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fn", ["tsm2r", "tsm2l", "gemm"])
+@pytest.mark.parametrize("m,k,n", [(1000, 3000, 16), (4097, 700, 5), (2000, 16, 16), (65, 9, 31),
+                                   (129, 33, 32)])
+@pytest.mark.parametrize("rowA", [False, True])
+def test_transposed_operands(dev, dtype, fn, m, k, n, rowA):
+    """B (and A) as row-major tensors: passed as the transposes they store."""
+    seed = 1300 + m + k + n
+    A = _rowmajor(seed, si.STREAM_A, m, k, dtype, dev) if rowA else \
+        dev_matrix(seed, si.STREAM_A, m, k, dtype, dev)
+    B = _rowmajor(seed, si.STREAM_B, k, n, dtype, dev)
+    C = getattr(tsm, fn)(A, B)
+    ref = oracle.matmul(host_matrix(seed, si.STREAM_A, m, k, dtype),
+                        host_matrix(seed, si.STREAM_B, k, n, dtype))
+    assert err(to_np(C), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("fn", ["tsm2r", "tsm2l", "gemm"])
+@pytest.mark.parametrize("m,k,n", [(1000, 3000, 33), (300, 5000, 70), (20000, 16, 40),
+                                   (777, 40, 64), (5000, 100, 3)])
+def test_wide_b_and_deep_tsm2l(dev, dtype, fn, m, k, n):
+    """n > 32 in panels of 32; TSM2L shapes with k > 32 on the TSM2R kernels."""
+    seed = 1500 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, dtype, dev)
+    B = dev_matrix(seed, si.STREAM_B, k, n, dtype, dev)
+    C = dev_matrix(seed, STREAM_C0, m, n, dtype, dev)
+    getattr(tsm, fn)(A, B, out=C, beta=1.0)
+    ref = _ref(host_matrix(seed, si.STREAM_A, m, k, dtype), host_matrix(seed, si.STREAM_B, k, n, dtype),
+               host_matrix(seed, STREAM_C0, m, n, dtype), 1.0)
+    assert err(to_np(C), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_empty_k_scales_c(dev, dtype):
+    C = dev_matrix(3, STREAM_C0, 500, 7, dtype, dev)
+    C0 = to_np(C).copy()
+    A = torch.empty((500, 0), dtype=dtype, device=dev)
+    B = torch.empty((0, 7), dtype=dtype, device=dev)
+    tsm.tsm2r(A, B, out=C, beta=3.0)
+    nd = np.float64 if dtype == torch.float64 else np.float32
+    assert np.array_equal(to_np(C), (nd(3.0) * C0.astype(nd)).astype(np.float64))
+    tsm.tsm2l(A, B, out=C, beta=0.0)
+    assert not to_np(C).any()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_caller_workspace_transposed_b(dev, dtype):
+    m, k, n = 3000, 20000, 16
+    A = dev_matrix(21, si.STREAM_A, m, k, dtype, dev)
+    B = _rowmajor(21, si.STREAM_B, k, n, dtype, dev)
+    code = tsm.F64 if dtype == torch.float64 else tsm.F32
+    nb = tsm.workspace_size(tsm.OP_TSM2R, m, k, n, code)
+    assert nb > 0
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    C = tsm.tsm2r(A, B, workspace=ws)
+    ref = oracle.matmul(host_matrix(21, si.STREAM_A, m, k, dtype),
+                        host_matrix(21, si.STREAM_B, k, n, dtype))
+    assert err(to_np(C), ref) <= TOL[dtype]
+    with pytest.raises(tsm.TSMError):
+        tsm.tsm2r(A, B, workspace=ws[: nb - 256])
+
+
+# the precision form: beta, a transposed B, TSM2L with k > 32, panels
+TOL_LP = 1e-5
+
+
+def _stored(Ah, code, lo):
+    hi, lo_ = oracle.split(np.asfortranarray(Ah.astype(np.float32)), code)
+    v = oracle.decode_plane(hi, code)
+    return v + oracle.decode_plane(lo_, code) if lo else v
+
+
+@pytest.mark.parametrize("fn", ["tsm2r", "tsm2l", "gemm"])
+@pytest.mark.parametrize("m,k,n", [(2000, 3000, 16), (5000, 16, 16), (1000, 48, 40), (129, 8, 33)])
+@pytest.mark.parametrize("lo", [False, True])
+def test_lowp_beta_and_transposed_b(dev, fn, m, k, n, lo):
+    seed = 1700 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, torch.float32, dev)
+    S = tsm.split(A, "bf16", lo=lo)
+    B = _rowmajor(seed, si.STREAM_B, k, n, torch.float32, dev)
+    C = dev_matrix(seed, STREAM_C0, m, n, torch.float32, dev)
+    getattr(tsm, fn)(S, B, out=C, beta=0.75)
+    Ah = host_matrix(seed, si.STREAM_A, m, k, torch.float32)
+    ref = _ref(_stored(Ah, oracle.BF16, lo), host_matrix(seed, si.STREAM_B, k, n, torch.float32),
+               host_matrix(seed, STREAM_C0, m, n, torch.float32), 0.75)
+    assert err(to_np(C), ref) <= TOL_LP

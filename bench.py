@@ -209,6 +209,45 @@ def rows_tsm2l(dev):
     return out
 
 
+def rows_general(dev):
+    """Shapes beyond one kernel launch: n > 32 in 32-column panels (A read once
+    per panel, the paper's t2 < n), a TSM2L-class product with k > 32 (on the
+    TSM2R kernels), and the dispatching gemm with a row-major B and beta = 1.
+    GB/s counts the bytes each product moves."""
+    import oracle
+    out = []
+    seed = si.config_seed(6)
+    cases = [("TSM2R n = 64 in two panels", "tsm2r", torch.float64, 20480, 20480, 64, False, 0.0),
+             ("TSM2L class with k = 64", "tsm2l", torch.float64, 1 << 22, 64, 16, False, 0.0),
+             ("gemm, row-major B, beta = 1", "gemm", torch.float32, 30720, 30720, 16, True, 1.0)]
+    for name, fn, dtype, m, k, n, rowB, beta in cases:
+        A = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
+        B = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype, device=dev)
+        if rowB:
+            B = B.contiguous()
+        C0 = si.matrix(seed, si.STREAM_V, m, n, dtype=dtype, device=dev)
+        C = C0.clone() if beta != 0 else tsm.empty_colmajor(m, n, dtype, dev)
+        f = getattr(tsm, fn)
+        f(A, B, out=C, beta=beta)            # checked on this first call (from C0)
+        rows = [0, m // 2, m - 1]
+        Ar = si.matrix_rows(seed, si.STREAM_A, m, k, rows, dtype=dtype).double().numpy()
+        Bh = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype).double().numpy()
+        ref = oracle.matmul(Ar, Bh)
+        if beta != 0:
+            ref = ref + beta * C0[rows].double().cpu().numpy()
+        e = oracle.normwise_error(C[rows].double().cpu().numpy(), ref)
+        t = timed(lambda: f(A, B, out=C, beta=beta))
+        panels = (n + 31) // 32 if fn == "tsm2r" else 1
+        nb = (panels * m * k + k * n + (2 if beta != 0 else 1) * m * n) * es(dtype)
+        out.append({"row": "general shapes: %s (m=%d k=%d n=%d)" % (name, m, k, n),
+                    "dtype": str(dtype).replace("torch.", ""), "GBps": nb / t / 1e9,
+                    "frac_of_8TBps": nb / t / 1e9 / PEAK_HBM_GBS,
+                    "kernel_A_reads": panels, "max_normwise_err": e, "tol": TOL[dtype]})
+        del A, B, C, C0
+        torch.cuda.empty_cache()
+    return out
+
+
 def rows_lowp(dev):
     """Precision form of TSM2R on A 32768 x 32768: bf16 / f16 planes, single
     and split, against plain FP32 on the same A (ratio of times vs ratio of
@@ -439,7 +478,7 @@ def main():
     del calls
     torch.cuda.empty_cache()
     if not args.no_rows:
-        line["rows"] = rows_tsm2l(dev) + rows_lowp(dev) + rows_autograd(dev)
+        line["rows"] = rows_tsm2l(dev) + rows_lowp(dev) + rows_autograd(dev) + rows_general(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

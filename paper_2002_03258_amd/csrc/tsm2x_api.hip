@@ -131,26 +131,31 @@ RTPlan plan_rowtile(int64_t m, int64_t kin, int64_t nout, int dt, int cus) {
 }
 
 struct TNPlan {
-    int64_t groups;
+    int64_t groups;         // 16-column output tiles (a multiple of ct)
     int S;
     int64_t rslice;
     int rg;
+    int ct;                 // output tiles per workgroup
     size_t ws;
 };
 
-// tn: one workgroup per 16 output rows (columns of X) and slice of R; the
-// WK = 4 wavefronts split the slice.
+// tn: one workgroup per ct 16-row output tiles (columns of X) and slice of
+// R; the WK = 4 wavefronts split the slice.
 TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     TNPlan P{};
+    // output tiles per workgroup: two share each staged Y tile when there
+    // are several column groups (Y is then re-read by every group)
+    P.ct = (plain_dtype(dt) && ncols > 16) ? (int)env_int("TSM2X_TN_CT", 2) : 1;
+    if (P.ct != 1 && P.ct != 2) P.ct = 1;
     // rows per wavefront loop iteration: G stages of 16*RL rows for the
-    // float kernels, 128 for the 16-bit form
-    P.rg = (int)env_int("TSM2X_TN_G", 2);
+    // float kernels (one stage with two output tiles), 128 for the 16-bit form
+    P.rg = P.ct == 2 ? 1 : (int)env_int("TSM2X_TN_G", 2);
     if (P.rg != 1 && P.rg != 2 && P.rg != 4) P.rg = 2;
     const int64_t RB = plain_dtype(dt) ? 16 * (16 / esize(dt)) * P.rg : 128;
     const int NT16 = n <= 16 ? 1 : 2;
-    P.groups = cdiv(ncols, 16);
+    P.groups = cdiv(cdiv(ncols, 16), P.ct) * P.ct;
     const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * 2);
-    int64_t S = cdiv(target, P.groups);
+    int64_t S = cdiv(target, P.groups / P.ct);
     const int64_t s_len = R / (RB * 4 * 8);   // >= 8 steps per wavefront
     if (S > s_len) S = s_len;
     if (S < 1) S = 1;
@@ -336,7 +341,8 @@ int product(bool lform, int transA, int transB, int64_t m, int64_t k, int64_t n,
         LaunchTN L{};
         L.R = k; L.ncols = m; L.n = n;
         L.X = A; L.ldx = lda; L.Y = Bk; L.ldy = ldbk; L.O = C; L.ldo = ldc;
-        L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg; L.beta = beta;
+        L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg; L.ct = P.ct;
+        L.beta = beta;
         if (P.S > 1) L.part = (double*)w;
         if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_kernel");
@@ -459,7 +465,7 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     if (rc) return rc;
     LaunchTN L{};
     L.R = m; L.ncols = k; L.n = n; L.X = A; L.ldx = lda; L.Y = dC; L.ldy = lddc; L.O = dB;
-    L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg;
+    L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg; L.ct = P.ct;
     if (P.S > 1) L.part = (double*)w;
     if (!plain_dtype(dtype)) {
         if (launch_tn_lp(L, dtype, st)) return TSM_ERR_UNSUPPORTED;

@@ -62,6 +62,7 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
     int S;                  // reduction slices (gridDim.y)
     int64_t rslice;
     int rg;                 // stages per wavefront loop iteration (1, 2 or 4)
+    int ct;                 // 16-column output tiles per workgroup (1 or 2)
     double* part;           // S > 1: partial sums (workspace)
     double beta;            // O := beta*O + X^T*Y (O read only if beta != 0)
 };

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
 // fixed order (workgroup level here, across workgroups by
 // split_reduce_kernel).
 // --------------------------------------------------------------------------
-template <typename T, int NT16, int G, bool VEC>
+template <typename T, int NT16, int G, int CT, bool VEC, bool YC>
 __global__ __launch_bounds__(256) void tn_kernel(
     int64_t R, int64_t ncols, int n, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ O, int64_t ldo,
@@ -194,7 +194,8 @@ __global__ __launch_bounds__(256) void tn_kernel(
     constexpr int WK = 4;
     constexpr int SR = 16 * RL;                // rows per stage
     constexpr int SROW = SR + RL;              // padded LDS column (16 more bytes)
-    constexpr int NC = 16 + 16 * NT16;         // staged columns: X tile, then Y tiles
+    constexpr int NX = 16 * CT;                // staged X columns (CT output tiles)
+    constexpr int NC = NX + 16 * NT16;         // then the Y columns
     constexpr int NV = 4 * NT16;
     __shared__ __align__(16) T lds[WK][NC][SROW];
     __shared__ double red[WK][WAVE][NV];
@@ -202,8 +203,7 @@ __global__ __launch_bounds__(256) void tn_kernel(
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
-    const int64_t ctile = blockIdx.x;
-    const int64_t c0 = ctile * 16;
+    const int64_t c0 = (int64_t)blockIdx.x * NX;
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t sb0 = (int64_t)s * rslice;
     const int64_t sb1 = (sb0 + rslice < R) ? sb0 + rslice : R;
@@ -212,11 +212,13 @@ __global__ __launch_bounds__(256) void tn_kernel(
     const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
     T (*tile)[SROW] = lds[w];
 
-    Acc acc[NT16];
+    Acc acc[CT][NT16];
 #pragma unroll
-    for (int t = 0; t < NT16; ++t) acc[t] = Acc{0, 0, 0, 0};
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) acc[ct][t] = Acc{0, 0, 0, 0};
 
-    // staged column sc: sc < 16 -> X column c0 + sc, else Y column sc - 16
+    // staged column sc: sc < NX -> X column c0 + sc, else Y column sc - NX
     auto load = [&](int64_t rb, T (&v)[G][NC / 4][RL]) {
 #pragma unroll
         for (int gs = 0; gs < G; ++gs) {
@@ -226,20 +228,26 @@ __global__ __launch_bounds__(256) void tn_kernel(
 #pragma unroll
             for (int cg = 0; cg < NC / 4; ++cg) {
                 const int sc = 4 * cg + kk;
-                const T* src;
-                bool ok;
-                if (sc < 16) {
-                    src = X + r + (c0 + sc) * ldx;
-                    ok = c0 + sc < ncols;
-                } else {
-                    src = Y + r + (int64_t)(sc - 16) * ldy;
-                    ok = sc - 16 < n;
-                }
-                if (ok)
-                    load_run<T, RL, VEC>(src, valid, full, v[gs][cg]);
-                else
+                if (cg < NX / 4) {
+                    if (c0 + sc < ncols)
+                        load_run<T, RL, VEC>(X + r + (c0 + sc) * ldx, valid, full, v[gs][cg]);
+                    else
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) v[gs][cg][q] = T(0);
+                        for (int q = 0; q < RL; ++q) v[gs][cg][q] = T(0);
+                } else {
+                    const T* src = Y + r + (int64_t)(sc - NX) * ldy;
+                    if (YC && VEC && sc - NX < n && full) {
+                        typedef typename VecOf<T, RL>::type V;
+                        const V y = *reinterpret_cast<const V*>(src);
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) v[gs][cg][q] = y[q];
+                    } else if (sc - NX < n) {
+                        load_run<T, RL, VEC>(src, valid, full, v[gs][cg]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) v[gs][cg][q] = T(0);
+                    }
+                }
             }
         }
     };
@@ -262,18 +270,23 @@ __global__ __launch_bounds__(256) void tn_kernel(
                     for (int q = 0; q < RL; ++q) x[q] = v[gs][cg][q];
                     *reinterpret_cast<V*>(&tile[4 * cg + kk][RL * rl]) = x;
                 }
-                // read back in four blocks of 4*RL rows: X column rl and Y
-                // columns 16 t + rl, rows 4*RL*h + RL*kk + q
+                // read back in four blocks of 4*RL rows: X columns 16 ct + rl
+                // and Y columns NX + 16 t + rl, rows 4*RL*h + RL*kk + q
                 typedef typename VecOf<T, RL>::type V;
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
-                    const V xs = *reinterpret_cast<const V*>(&tile[rl][4 * RL * h + RL * kk]);
+                    V ys[NT16];
 #pragma unroll
-                    for (int t = 0; t < NT16; ++t) {
-                        const V ys =
-                            *reinterpret_cast<const V*>(&tile[16 + 16 * t + rl][4 * RL * h + RL * kk]);
+                    for (int t = 0; t < NT16; ++t)
+                        ys[t] = *reinterpret_cast<const V*>(&tile[NX + 16 * t + rl][4 * RL * h + RL * kk]);
 #pragma unroll
-                        for (int q = 0; q < RL; ++q) acc[t] = M::op(xs[q], ys[q], acc[t]);
+                    for (int ct = 0; ct < CT; ++ct) {
+                        const V xs = *reinterpret_cast<const V*>(&tile[16 * ct + rl][4 * RL * h + RL * kk]);
+#pragma unroll
+                        for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                            for (int q = 0; q < RL; ++q)
+                                acc[ct][t] = M::op(xs[q], ys[t][q], acc[ct][t]);
                     }
                 }
             }
@@ -286,8 +299,13 @@ __global__ __launch_bounds__(256) void tn_kernel(
         }
     }
 
-    tn_finish<T, NT16, WK>(ncols, n, O, ldo, beta, ctile, s, nsl, part, red, acc,
-                           [](int kq, int r) { return Mfma<T>::mrow(kq, r); });
+    // one 16-column output tile at a time (global tile index blockIdx.x*CT + ct)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        if (ct > 0) __syncthreads();           // red is reused
+        tn_finish<T, NT16, WK>(ncols, n, O, ldo, beta, (int64_t)blockIdx.x * CT + ct, s, nsl, part,
+                               red, acc[ct], [](int kq, int r) { return Mfma<T>::mrow(kq, r); });
+    }
 }
 
 // C := beta * C (zeros when beta == 0; C is then not read): the product of an
@@ -383,17 +401,25 @@ int launch_rowtile(const LaunchRT& L, int dtype, hipStream_t st) {
     return 1;
 }
 
-template <typename T, int NT16, int G>
+template <typename T, int NT16, int G, int CT>
 static int tn_launch(const LaunchTN& L, bool vec, hipStream_t st) {
-    dim3 grid((unsigned)L.groups, (unsigned)L.S), block(256);
-    if (vec)
-        hipLaunchKernelGGL((tn_kernel<T, NT16, G, true>), grid, block, 0, st, L.R, L.ncols,
-                           (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
-                           L.rslice, L.part, L.beta);
+    // L.groups 16-column tiles, a multiple of CT: CT of them per workgroup.
+    // Y is read by every column group: cached loads when there are several
+    // (YC), non-temporal ones when it is streamed once.
+    const int64_t gx = L.groups / CT;
+    dim3 grid((unsigned)gx, (unsigned)L.S), block(256);
+    if (vec && gx > 1)
+        hipLaunchKernelGGL((tn_kernel<T, NT16, G, CT, true, true>), grid, block, 0, st, L.R,
+                           L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
+                           L.ldo, L.rslice, L.part, L.beta);
+    else if (vec)
+        hipLaunchKernelGGL((tn_kernel<T, NT16, G, CT, true, false>), grid, block, 0, st, L.R,
+                           L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
+                           L.ldo, L.rslice, L.part, L.beta);
     else
-        hipLaunchKernelGGL((tn_kernel<T, NT16, G, false>), grid, block, 0, st, L.R, L.ncols,
-                           (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O, L.ldo,
-                           L.rslice, L.part, L.beta);
+        hipLaunchKernelGGL((tn_kernel<T, NT16, G, CT, false, false>), grid, block, 0, st, L.R,
+                           L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
+                           L.ldo, L.rslice, L.part, L.beta);
     return 0;
 }
 
@@ -403,11 +429,19 @@ static int tn_dispatch(const LaunchTN& L, hipStream_t st) {
                      ((L.ldx * (int64_t)sizeof(T)) % 16 == 0) &&
                      ((L.ldy * (int64_t)sizeof(T)) % 16 == 0);
     // G stages of 16*RL rows per loop iteration (loads for the next iteration
-    // are in flight while the current one is staged and multiplied)
+    // are in flight while the current one is staged and multiplied); CT
+    // 16-column output tiles per wavefront share each staged Y tile
     int rc = 1;
-    if (L.rg == 4) rc = L.n <= 16 ? tn_launch<T, 1, 4>(L, vec, st) : tn_launch<T, 2, 4>(L, vec, st);
-    else if (L.rg == 2) rc = L.n <= 16 ? tn_launch<T, 1, 2>(L, vec, st) : tn_launch<T, 2, 2>(L, vec, st);
-    else rc = L.n <= 16 ? tn_launch<T, 1, 1>(L, vec, st) : tn_launch<T, 2, 1>(L, vec, st);
+    const bool wide = L.n > 16;
+    if (L.ct == 2) {
+        rc = wide ? tn_launch<T, 2, 1, 2>(L, vec, st) : tn_launch<T, 1, 1, 2>(L, vec, st);
+    } else if (L.rg == 4) {
+        rc = wide ? tn_launch<T, 2, 4, 1>(L, vec, st) : tn_launch<T, 1, 4, 1>(L, vec, st);
+    } else if (L.rg == 2) {
+        rc = wide ? tn_launch<T, 2, 2, 1>(L, vec, st) : tn_launch<T, 1, 2, 1>(L, vec, st);
+    } else {
+        rc = wide ? tn_launch<T, 2, 1, 1>(L, vec, st) : tn_launch<T, 1, 1, 1>(L, vec, st);
+    }
     if (rc || L.S <= 1) return rc;
     return launch_split_reduce(sizeof(T) == 8 ? DT_F64 : DT_F32, L.groups, L.S,
                                L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n, L.part, L.O, L.ldo,

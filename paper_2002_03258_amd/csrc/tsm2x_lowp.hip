@@ -475,7 +475,7 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // float 16x16x4 matrix cores.  Reduction across wavefronts and workgroups
 // as in tn_kernel.
 // --------------------------------------------------------------------------
-template <int FMT, int NT16, bool SPLIT, bool VEC>
+template <int FMT, int NT16, bool SPLIT, bool VEC, bool YC>
 __global__ __launch_bounds__(256) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
@@ -534,7 +534,12 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
 #pragma unroll
             for (int cg = 0; cg < YG; ++cg) {
                 const int p = 4 * cg + kk;
-                if (p < n)
+                if (YC && VEC && p < n && full) {
+                    // Y re-read by every column group: through the cache
+                    const f32x4 y = *reinterpret_cast<const f32x4*>(Y + r + (int64_t)p * ldy);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) yv[h][cg][q] = y[q];
+                } else if (p < n)
                     load_run<float, 4, VEC>(Y + r + (int64_t)p * ldy, valid, full, yv[h][cg]);
                 else
 #pragma unroll
@@ -762,17 +767,23 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
     const uint16_t* xl = split ? xh + L.ldx * L.ncols : nullptr;
     dim3 g((unsigned)L.groups, (unsigned)L.S), b(256);
     const int ni = (int)L.n;
-#define TSM_T(F, NT, SP)                                                                          \
-    {                                                                                             \
-        if (vec)                                                                                  \
-            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, true>), g, b, 0, st, L.R, L.ncols, ni, xh,  \
-                               xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo, L.rslice, \
-                               L.part);                                                           \
-        else                                                                                      \
-            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, false>), g, b, 0, st, L.R, L.ncols, ni,     \
-                               xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,       \
-                               L.rslice, L.part);                                                 \
-        return 0;                                                                                 \
+    // Y is re-read by every column group: cached loads when there are several
+    const bool yc = L.groups > 1;
+#define TSM_T(F, NT, SP)                                                                           \
+    {                                                                                              \
+        if (vec && yc)                                                                             \
+            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, true, true>), g, b, 0, st, L.R, L.ncols,   \
+                               ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,    \
+                               L.rslice, L.part);                                                  \
+        else if (vec)                                                                              \
+            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, true, false>), g, b, 0, st, L.R, L.ncols,  \
+                               ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,    \
+                               L.rslice, L.part);                                                  \
+        else                                                                                       \
+            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, false, false>), g, b, 0, st, L.R, L.ncols, \
+                               ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,    \
+                               L.rslice, L.part);                                                  \
+        return 0;                                                                                  \
     }
     if (fmt == FMT_BF16) {
         if (split) { if (L.n <= 16) TSM_T(FMT_BF16, 1, true) else TSM_T(FMT_BF16, 2, true) }

@@ -104,10 +104,13 @@ RTPlan plan_rowtile(int64_t m, int64_t kin, int64_t nout, int dt, int cus) {
     const int64_t TR = 16 * RL * RG;
     const int64_t ntiles = cdiv(m, TR);
     const int64_t wblocks = cdiv(ntiles, 4);
-    // workgroups resident at once (the rowtile instances fit 2-4 per CU): the
-    // output columns are split so that one round covers them, each wavefront
-    // keeping one row tile for its whole column range
-    const int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cus * 4);
+    // nout <= 32 (TSM2L): the persistent grid is capped by occupancy at launch.
+    // Wide outputs (dA of TSM2R, write-bound): one workgroup per CU, each
+    // wavefront keeping one row tile for a long column range.  Measured: the
+    // fewer column ranges are written at once, the closer together in time
+    // each column's row tiles are written (256 workgroups: FP32 6.0 TB/s;
+    // 1024: 4.9 TB/s)
+    const int64_t cap = env_int("TSM2X_RT_BLOCKS", (int64_t)cus * (nout > 32 ? 1 : 4));
     if (nout <= 32) {
         P.cpb = nout;
         P.by = 1;

@@ -42,6 +42,9 @@ import paper_2002_03258_amd as tsm  # noqa: E402
 import seeded_inputs as si  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+# streaming-read ceiling measured on MI355X with a 16-byte non-temporal
+# linear-read probe (reported beside the datasheet peak)
+READ_CEILING_GBS = 7090.0
 R_SIZES = (10240, 20480, 30720)
 R_NS = (2, 4, 8, 16)
 R_DTYPES = (torch.float64, torch.float32)
@@ -109,28 +112,54 @@ def check_calls(calls):
                 "ok": v <= TOL[getattr(torch, k)]} for k, v in worst.items()}
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The FP64 oracle on a row sample of the largest TSM2R workload."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline():
+    """The FP64 oracle on a row sample of the largest TSM2R workload, on all
+    of the host's cores and on one (each sample sized for about 10 s)."""
     import oracle
     m = k = R_SIZES[-1]
     n = 16
     seed = si.config_seed(1)
     B = si.matrix(seed + n, si.STREAM_B, k, n).numpy()
-    rows = 64
-    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(rows))).numpy()
-    t0 = time.perf_counter()
-    oracle.matmul(Ar, B)
-    dt = time.perf_counter() - t0
-    rows = int(min(m, max(64, rows * seconds_target / max(dt, 1e-3))))
-    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(rows))).numpy()
-    t0 = time.perf_counter()
-    oracle.matmul(Ar, B)
-    dt = time.perf_counter() - t0
-    nbytes = (rows * k + k * n + rows * n) * 8
-    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": oracle.threads(),
-            "kind": "oracle", "seconds": dt,
-            "sample": "FP64 TSM2R C = A*B on the first %d of %d rows of A (k = %d, n = %d); "
-                      "algorithmic bytes of the sample over the oracle's time" % (rows, m, k, n)}
+    cores = oracle.threads()
+
+    def probe_rows(target_s):
+        # rows of A the oracle gets through in about target_s seconds
+        Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(64))).numpy()
+        t0 = time.perf_counter()
+        oracle.matmul(Ar, B)
+        return int(min(m, max(64, 64 * target_s / max(time.perf_counter() - t0, 1e-3))))
+
+    rows_all = probe_rows(10.0)
+    oracle.set_threads(1)
+    rows_one = min(rows_all, probe_rows(6.0))
+    oracle.set_threads(cores)
+    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(rows_all))).numpy()
+
+    def rate(rows):
+        t0 = time.perf_counter()
+        oracle.matmul(Ar[:rows], B)
+        dt = time.perf_counter() - t0
+        return (rows * k + k * n + rows * n) * 8 / dt / 1e9, dt
+
+    v_all, dt = rate(rows_all)
+    oracle.set_threads(1)
+    v_one, dt1 = rate(rows_one)
+    oracle.set_threads(cores)
+    return {"value": v_all, "unit": "GB/s", "cores": cores, "kind": "oracle", "seconds": dt,
+            "single_thread_value": v_one, "single_thread_seconds": dt1, "cpu_model": _cpu_model(),
+            "sample": "FP64 TSM2R C = A*B on the first %d (all cores) and %d (one core) of %d "
+                      "rows of A (k = %d, n = %d); algorithmic bytes of the sample over the "
+                      "oracle's time" % (rows_all, rows_one, m, k, n)}
 
 
 def traffic_for(kernel: str, launches):
@@ -440,6 +469,7 @@ def main():
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     step_bytes = sum(c["bytes"] for c in calls)
+    step_flops = sum(2.0 * c["m"] * c["k"] * c["n"] for c in calls)
     value = step_bytes * args.steps / (total_ms / 1e3) / 1e9
 
     per_kernel = {}
@@ -470,7 +500,9 @@ def main():
         "data": "synthetic (seeded counter-based uniform[-1,1])",
         "config": {"workload": "TSM2R plain FP64 and FP32: square A m=k in {10240,20480,30720}, "
                                "B k x n with n in {2,4,8,16}, column-major (24 products per step)",
-                   "bytes_per_step": step_bytes, "frac_of_8TBps": value / PEAK_HBM_GBS},
+                   "bytes_per_step": step_bytes, "frac_of_8TBps": value / PEAK_HBM_GBS,
+                   "frac_of_measured_read_ceiling": value / READ_CEILING_GBS,
+                   "gflop_per_s": step_flops * args.steps / (total_ms / 1e3) / 1e9},
         "roofline": roofline,
     }
     if not args.no_check:

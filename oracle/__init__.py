@@ -79,6 +79,8 @@ def _load():
             lib.tsm_oracle_split.restype = None
             lib.tsm_oracle_threads.argtypes = []
             lib.tsm_oracle_threads.restype = ctypes.c_int
+            lib.tsm_oracle_set_threads.argtypes = [ctypes.c_int]
+            lib.tsm_oracle_set_threads.restype = None
             _lib = lib
     return _lib
 
@@ -182,6 +184,11 @@ def decode_plane(h: np.ndarray, fmt: int) -> np.ndarray:
 
 def threads() -> int:
     return int(_load().tsm_oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads the oracle's row loops use from now on (timing only)."""
+    _load().tsm_oracle_set_threads(int(n))
 
 
 def t2_threshold(peak_perf_gflops: float, peak_bw_gbs: float,

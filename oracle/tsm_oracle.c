@@ -176,3 +176,14 @@ int tsm_oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the row loops from now on (timing only; results do not depend
+   on it: each output is summed by one thread in j order). */
+void tsm_oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -45,6 +45,20 @@ PEAK_HBM_GBS = 8000.0
 # streaming-read ceiling measured on MI355X with a 16-byte non-temporal
 # linear-read probe (reported beside the datasheet peak)
 READ_CEILING_GBS = 7090.0
+# read + write ceiling measured the same way: a 1 GiB copy with 16-byte
+# non-temporal loads and stores
+COPY_CEILING_GBS = 6385.0
+
+
+def attach_ceilings(rows):
+    """Each row's fraction of the measured ceiling of its traffic mix: the
+    copy ceiling for products that write about as much as they read (TSM2L,
+    the backward passes), the streaming-read ceiling otherwise."""
+    for r in rows:
+        rw = r["row"].startswith("TSM2L forward") or r["row"].startswith("autograd")
+        r["measured_ceiling_GBps"] = COPY_CEILING_GBS if rw else READ_CEILING_GBS
+        r["frac_of_measured_ceiling"] = r["GBps"] / r["measured_ceiling_GBps"]
+    return rows
 R_SIZES = (10240, 20480, 30720)
 R_NS = (2, 4, 8, 16)
 R_DTYPES = (torch.float64, torch.float32)
@@ -510,7 +524,8 @@ def main():
     del calls
     torch.cuda.empty_cache()
     if not args.no_rows:
-        line["rows"] = rows_tsm2l(dev) + rows_lowp(dev) + rows_autograd(dev) + rows_general(dev)
+        line["rows"] = attach_ceilings(rows_tsm2l(dev) + rows_lowp(dev) + rows_autograd(dev) +
+                                       rows_general(dev))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -181,10 +181,12 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
  * dA = dC * B^T (m x k, ldda) and dB = A^T * dC (k x n, lddb); B is k x n
  * (ldb).  A, dC and dA each cross HBM once (the separate tsm_grad_a and
  * tsm_grad_b read dC twice).  dB is reduced in double precision in a fixed
- * order.  dtype: TSM_F64 or TSM_F32.  ws/ws_bytes as in tsm_grad_b (NULL:
- * library buffer).  Arguments: 1 m, 2 k, 3 n, 4 A, 5 lda, 6 B, 7 ldb, 8 dC,
+ * order.  dtype: any tsm_dtype; for the 16-bit forms A is the plane(s) of
+ * tsm2x_split (lo plane lda*k elements after hi), widened to float, and B,
+ * dC, dA, dB are float.  ws/ws_bytes as in tsm_grad_b (NULL: library
+ * buffer).  Arguments: 1 m, 2 k, 3 n, 4 A, 5 lda, 6 B, 7 ldb, 8 dC,
  * 9 lddc, 10 dA, 11 ldda, 12 dB, 13 lddb, 14 dtype, 15 ws, 16 ws_bytes,
- * 17 stream.  TSM_ERR_UNSUPPORTED if k > 32, n > 32 or dtype is 16-bit. */
+ * 17 stream.  TSM_ERR_UNSUPPORTED if k > 32 or n > 32. */
 int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
                    const void* B, int64_t ldb, const void* dC, int64_t lddc,
                    void* dA, int64_t ldda, void* dB, int64_t lddb, int dtype,

@@ -227,18 +227,29 @@ def grad_b(A, dC: torch.Tensor, out: torch.Tensor | None = None,
     return dB
 
 
-def tsm2l_backward(A: torch.Tensor, B: torch.Tensor, dC: torch.Tensor):
+def tsm2l_backward(A, B: torch.Tensor, dC: torch.Tensor):
     """(dA, dB) = (dC*B^T, A^T*dC) for a TSM2L product (k, n <= 32) in one
-    fused pass over A and dC."""
-    _check_device(A, B, dC)
-    dt = _DT[A.dtype]
-    A, B, dC = colmajor(A), colmajor(B), colmajor(dC)
-    m, k = A.shape
+    fused pass over A and dC.  A may be a SplitA (B, dC float32): dB then
+    uses the stored values hi (+ lo), as the forward did."""
+    if isinstance(A, SplitA):
+        _check_device(A.planes, B, dC)
+        if B.dtype != torch.float32 or dC.dtype != torch.float32:
+            raise ValueError("B and dC must be float32 for the low-precision forms of A")
+        a_ptr, lda, code, odt, dev = A.planes.data_ptr(), A.ld, A.dtype_code, torch.float32, \
+            A.device
+        m, k = A.shape
+    else:
+        _check_device(A, B, dC)
+        code, odt, dev = _DT[A.dtype], A.dtype, A.device
+        A = colmajor(A)
+        m, k = A.shape
+        a_ptr, lda = A.data_ptr(), _ld(A)
+    B, dC = colmajor(B), colmajor(dC)
     n = B.shape[1]
-    dA = empty_colmajor(m, k, A.dtype, A.device)
-    dB = empty_colmajor(k, n, A.dtype, A.device)
-    _lib.call("tsm2l_backward", m, k, n, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
-              dC.data_ptr(), _ld(dC), dA.data_ptr(), _ld(dA), dB.data_ptr(), _ld(dB), dt,
+    dA = empty_colmajor(m, k, odt, dev)
+    dB = empty_colmajor(k, n, odt, dev)
+    _lib.call("tsm2l_backward", m, k, n, a_ptr, lda, B.data_ptr(), _ld(B),
+              dC.data_ptr(), _ld(dC), dA.data_ptr(), _ld(dA), dB.data_ptr(), _ld(dB), code,
               None, 0, _stream())
     return dA, dB
 

@@ -495,13 +495,14 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, 
     if (!dB && k > 0 && n > 0) return -12;
     if (lddb < (k > 1 ? k : 1)) return -13;
     if (!valid_dtype(dtype)) return -14;
-    if (k > 32 || n > 32 || !plain_dtype(dtype)) return TSM_ERR_UNSUPPORTED;
+    if (k > 32 || n > 32) return TSM_ERR_UNSUPPORTED;
     if (k == 0) return TSM_SUCCESS;
     hipStream_t st = (hipStream_t)stream;
+    const int odt = plain_dtype(dtype) ? dtype : TSM_F32;      // B, dC, dA, dB
     if (m == 0 || n == 0) {
         // dA (m x k) is zero when n == 0; dB (k x n) is zero when m == 0
-        if (m > 0) launch_fill_scale(m, k, dA, ldda, 0.0, dtype, st);
-        if (n > 0) launch_fill_scale(k, n, dB, lddb, 0.0, dtype, st);
+        if (m > 0) launch_fill_scale(m, k, dA, ldda, 0.0, odt, st);
+        if (n > 0) launch_fill_scale(k, n, dB, lddb, 0.0, odt, st);
         return check_launch("fill_scale_kernel");
     }
     LaunchBwd L{};

@@ -1,4 +1,5 @@
-// Fused backward of a TSM2L product C = A*B (A m x k, B k x n, k, n <= 32):
+// Fused backward of a TSM2L product C = A*B (A m x k, B k x n, k, n <= 32;
+// A plain, or the 16-bit planes of the precision form with float B, dC):
 // one pass over the rows reads A and dC once and produces
 //   dA = dC * B^T   (written row tile by row tile, a TSM2L product with B^T)
 //   dB = A^T * dC   (accumulated in registers, reduced in double at the end)
@@ -20,15 +21,19 @@
 #include <stdint.h>
 
 #include "tsm2x_device.h"
+#include "tsm2x_half.h"
 #include "tsm2x_internal.h"
 
 namespace tsm {
 
-template <typename T, int NTK, int NTN, int RG, bool VEC>
+// AF < 0: A holds T.  AF = FMT_BF16 / FMT_F16 (T = float): A is the 16-bit hi
+// plane and, with ASPLIT, Alo the lo plane; a lane's 4 rows of a column are
+// one 8-byte run per plane, widened to float (hi + lo is exact in float).
+template <typename T, int NTK, int NTN, int RG, bool VEC, int AF, bool ASPLIT>
 __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
-    int64_t m, int k, int n, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
-    int64_t ldb, const T* __restrict__ dC, int64_t lddc, T* __restrict__ dA, int64_t ldda,
-    double* __restrict__ part) {
+    int64_t m, int k, int n, const void* __restrict__ Av, const uint16_t* __restrict__ Alo,
+    int64_t lda, const T* __restrict__ B, int64_t ldb, const T* __restrict__ dC, int64_t lddc,
+    T* __restrict__ dA, int64_t ldda, double* __restrict__ part) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     typedef typename VecOf<T, 16 / sizeof(T)>::type V;
@@ -48,6 +53,39 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
     const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
     T (*tile)[SROW] = lds[w];
+    static_assert(AF < 0 || (sizeof(T) == 4 && RL == 4), "16-bit A with float operands");
+
+    // the RL rows r .. r + RL - 1 of column c of A, as T
+    auto loadA = [&](int64_t r, int c, bool full, T (&out)[RL]) {
+        if (AF < 0) {
+            load_run<T, RL, VEC>((const T*)Av + r + (int64_t)c * lda, m - r, full, out);
+        } else {
+            const int64_t off = r + (int64_t)c * lda;
+            uint32_t d[2][2];
+#pragma unroll
+            for (int pl = 0; pl < (ASPLIT ? 2 : 1); ++pl) {
+                const uint16_t* h = (pl == 0 ? (const uint16_t*)Av : Alo) + off;
+                if (VEC && full) {
+                    const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(h));
+                    d[pl][0] = v[0];
+                    d[pl][1] = v[1];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const uint32_t x0 = (2 * e < m - r) ? h[2 * e] : 0u;
+                        const uint32_t x1 = (2 * e + 1 < m - r) ? h[2 * e + 1] : 0u;
+                        d[pl][e] = x0 | (x1 << 16);
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RL; ++q) {
+                float a = half_val<(AF < 0 ? 0 : AF)>(d[0][q >> 1], q & 1);
+                if (ASPLIT) a += half_val<(AF < 0 ? 0 : AF)>(d[1][q >> 1], q & 1);
+                out[q] = (T)a;
+            }
+        }
+    };
 
     // B^T as the S operand of the dA part: yv[st][t] = B[16 t + rl, 4 st + kk]
     T yv[KSN][NTK];
@@ -89,7 +127,7 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
             for (int st = 0; st < KSK; ++st) {
                 const int c = 4 * st + kk;
                 if (c < k)
-                    load_run<T, RL, VEC>(A + r + (int64_t)c * lda, m - r, full, xa[st][g]);
+                    loadA(r, c, full, xa[st][g]);
                 else
 #pragma unroll
                     for (int q = 0; q < RL; ++q) xa[st][g][q] = T(0);
@@ -198,11 +236,11 @@ static int fused_occupancy(K kernel) {
     return nb;
 }
 
-template <typename T, int NTK, int NTN>
+template <typename T, int NTK, int NTN, int AF, bool ASPLIT>
 static int bwd_launch(const LaunchBwd& L, int64_t* blocks_out, hipStream_t st, bool plan_only) {
     constexpr int RG = 2;
     constexpr int64_t TR = 16 * (16 / (int64_t)sizeof(T)) * RG;
-    static const int occ = fused_occupancy(tsm2l_bwd_kernel<T, NTK, NTN, RG, true>);
+    static const int occ = fused_occupancy(tsm2l_bwd_kernel<T, NTK, NTN, RG, true, AF, ASPLIT>);
     const int64_t ntiles = (L.m + TR - 1) / TR;
     int64_t bx = (int64_t)L.cus * occ;
     const int64_t need = (ntiles + 3) / 4;
@@ -210,37 +248,46 @@ static int bwd_launch(const LaunchBwd& L, int64_t* blocks_out, hipStream_t st, b
     if (bx < 1) bx = 1;
     *blocks_out = bx;
     if (plan_only) return 0;
-    const bool vec = ((uintptr_t)L.A & 15u) == 0 && ((uintptr_t)L.dC & 15u) == 0 &&
-                     ((uintptr_t)L.dA & 15u) == 0 && (L.lda * (int64_t)sizeof(T)) % 16 == 0 &&
+    // A: 16-byte runs of T, or 8-byte runs of the 16-bit planes
+    const bool avec = AF < 0 ? ((uintptr_t)L.A & 15u) == 0 && (L.lda * (int64_t)sizeof(T)) % 16 == 0
+                             : ((uintptr_t)L.A & 7u) == 0 && L.lda % 4 == 0;
+    const bool vec = avec && ((uintptr_t)L.dC & 15u) == 0 && ((uintptr_t)L.dA & 15u) == 0 &&
                      (L.lddc * (int64_t)sizeof(T)) % 16 == 0 &&
                      (L.ldda * (int64_t)sizeof(T)) % 16 == 0;
+    const uint16_t* alo = ASPLIT ? (const uint16_t*)L.A + L.lda * L.k : nullptr;
     dim3 g((unsigned)bx), b(256);
     if (vec)
-        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, true>), g, b, 0, st, L.m, (int)L.k,
-                           (int)L.n, (const T*)L.A, L.lda, (const T*)L.B, L.ldb, (const T*)L.dC,
-                           L.lddc, (T*)L.dA, L.ldda, L.part);
+        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, true, AF, ASPLIT>), g, b, 0, st,
+                           L.m, (int)L.k, (int)L.n, L.A, alo, L.lda, (const T*)L.B, L.ldb,
+                           (const T*)L.dC, L.lddc, (T*)L.dA, L.ldda, L.part);
     else
-        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, false>), g, b, 0, st, L.m,
-                           (int)L.k, (int)L.n, (const T*)L.A, L.lda, (const T*)L.B, L.ldb,
+        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, false, AF, ASPLIT>), g, b, 0, st,
+                           L.m, (int)L.k, (int)L.n, L.A, alo, L.lda, (const T*)L.B, L.ldb,
                            (const T*)L.dC, L.lddc, (T*)L.dA, L.ldda, L.part);
     if (hipGetLastError() != hipSuccess) return 1;
     return launch_split_reduce(sizeof(T) == 8 ? DT_F64 : DT_F32, 1, (int)bx, 16 * NTN, 16 * NTK,
                                L.k, (int)L.n, L.part, L.dB, L.lddb, 0.0, st);
 }
 
-template <typename T>
+template <typename T, int AF, bool ASPLIT>
 static int bwd_dispatch(const LaunchBwd& L, int64_t* blocks, hipStream_t st, bool plan_only) {
     if (L.k <= 16)
-        return L.n <= 16 ? bwd_launch<T, 1, 1>(L, blocks, st, plan_only)
-                         : bwd_launch<T, 1, 2>(L, blocks, st, plan_only);
-    return L.n <= 16 ? bwd_launch<T, 2, 1>(L, blocks, st, plan_only)
-                     : bwd_launch<T, 2, 2>(L, blocks, st, plan_only);
+        return L.n <= 16 ? bwd_launch<T, 1, 1, AF, ASPLIT>(L, blocks, st, plan_only)
+                         : bwd_launch<T, 1, 2, AF, ASPLIT>(L, blocks, st, plan_only);
+    return L.n <= 16 ? bwd_launch<T, 2, 1, AF, ASPLIT>(L, blocks, st, plan_only)
+                     : bwd_launch<T, 2, 2, AF, ASPLIT>(L, blocks, st, plan_only);
 }
 
 int launch_tsm2l_bwd(const LaunchBwd& L, int dtype, int64_t* blocks, hipStream_t st,
                      bool plan_only) {
-    if (dtype == DT_F64) return bwd_dispatch<double>(L, blocks, st, plan_only);
-    if (dtype == DT_F32) return bwd_dispatch<float>(L, blocks, st, plan_only);
+    switch (dtype) {
+        case DT_F64: return bwd_dispatch<double, -1, false>(L, blocks, st, plan_only);
+        case DT_F32: return bwd_dispatch<float, -1, false>(L, blocks, st, plan_only);
+        case DT_BF16: return bwd_dispatch<float, FMT_BF16, false>(L, blocks, st, plan_only);
+        case DT_BF16_SPLIT: return bwd_dispatch<float, FMT_BF16, true>(L, blocks, st, plan_only);
+        case DT_F16: return bwd_dispatch<float, FMT_F16, false>(L, blocks, st, plan_only);
+        case DT_F16_SPLIT: return bwd_dispatch<float, FMT_F16, true>(L, blocks, st, plan_only);
+    }
     return 1;
 }
 

@@ -31,35 +31,13 @@
 #include <cstdlib>
 
 #include "tsm2x_device.h"
+#include "tsm2x_half.h"
 #include "tsm2x_internal.h"
 
 namespace tsm {
 
-enum { FMT_BF16 = 0, FMT_F16 = 1 };
-
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Round-to-nearest-even of a float to the 16-bit format, as its bit pattern.
-template <int FMT>
-__device__ __forceinline__ uint32_t rne16(float x) {
-    if (FMT == FMT_BF16) {
-        uint32_t u = __float_as_uint(x);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;   // NaN stays NaN
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return u >> 16;
-    } else {
-        _Float16 h = (_Float16)x;                                       // v_cvt_f16_f32, RNE
-        return (uint32_t)__builtin_bit_cast(uint16_t, h);
-    }
-}
-
-template <int FMT>
-__device__ __forceinline__ float val16(uint32_t h) {
-    if (FMT == FMT_BF16) return __uint_as_float(h << 16);
-    return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
-}
 
 template <int FMT>
 __device__ __forceinline__ f32x4 mfma32(u32x4 s, u32x4 t, f32x4 d) {
@@ -323,13 +301,6 @@ __device__ __forceinline__ void split_terms8(const float (&v)[8], u32x4 (&out)[N
     for (int c = 0; c < NBT; ++c)
 #pragma unroll
         for (int e = 0; e < 4; ++e) out[c][e] = h[c][2 * e] | (h[c][2 * e + 1] << 16);
-}
-
-// Float value of the 16-bit element h (0: low half, 1: high half) of a dword.
-template <int FMT>
-__device__ __forceinline__ float half_val(uint32_t d, int h) {
-    if (FMT == FMT_BF16) return __uint_as_float(h ? (d & 0xffff0000u) : (d << 16));
-    return (float)__builtin_bit_cast(_Float16, (uint16_t)(h ? (d >> 16) : (d & 0xffffu)));
 }
 
 // Value of row q (0..7) of a lane's 16-byte run of each plane: hi, or hi + lo.

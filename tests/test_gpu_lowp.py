@@ -185,3 +185,24 @@ def test_tsm2l_grad_b_lowp_deterministic(dev, fmt, code):
     S = tsm.split(A, fmt)
     assert torch.equal(tsm.tsm2l(S, B).clone(), tsm.tsm2l(S, B))
     assert torch.equal(tsm.grad_b(S, dC).clone(), tsm.grad_b(S, dC))
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("with_lo", [False, True])
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (1000, 16, 16), (4133, 9, 30), (70001, 32, 8),
+                                   (300000, 16, 16)])
+def test_fused_backward_lowp(dev, fmt, code, with_lo, m, k, n):
+    """dA = dC*B^T and dB = planes^T*dC in one pass over the planes and dC."""
+    seed = 1900 + m + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, torch.float32, dev)
+    B = dev_matrix(seed, si.STREAM_B, k, n, torch.float32, dev)
+    dC = dev_matrix(seed, si.STREAM_DC, m, n, torch.float32, dev, dist="normal")
+    S = tsm.split(A, fmt, lo=with_lo)
+    dA, dB = tsm.tsm2l_backward(S, B, dC)
+    Ah = host_matrix(seed, si.STREAM_A, m, k, torch.float32)
+    Bh = host_matrix(seed, si.STREAM_B, k, n, torch.float32)
+    dCh = host_matrix(seed, si.STREAM_DC, m, n, torch.float32, dist="normal")
+    assert err(to_np(dA), oracle.matmul(dCh, Bh.T)) <= TOL_STORED
+    assert err(to_np(dB), oracle.matmul(_stored_value(Ah, code, with_lo).T, dCh)) <= TOL_STORED
+    # the same as the two separate kernels
+    assert err(to_np(dB), to_np(tsm.grad_b(S, dC))) <= TOL_STORED

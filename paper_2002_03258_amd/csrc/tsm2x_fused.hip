@@ -26,9 +26,20 @@
 
 namespace tsm {
 
+// Orders this wavefront's LDS stores and loads around a hand-over between its
+// lanes.  Each lane reads the staged tile at the same addresses for every
+// block; without the fence the compiler may reuse an earlier load in a lane
+// that stored nothing in between.  At wavefront scope no instruction is
+// needed (a wavefront's LDS operations complete in order).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
 // AF < 0: A holds T.  AF = FMT_BF16 / FMT_F16 (T = float): A is the 16-bit hi
-// plane and, with ASPLIT, Alo the lo plane; a lane's 4 rows of a column are
-// one 8-byte run per plane, widened to float (hi + lo is exact in float).
+// plane and, with ASPLIT, Alo the lo plane.  A only feeds dB, which is staged
+// through LDS, so a lane loads 8 rows of a column (one 16-byte run per plane)
+// and writes them, widened to float (hi + lo is exact in float), into the
+// staged block they belong to.
 template <typename T, int NTK, int NTN, int RG, bool VEC, int AF, bool ASPLIT>
 __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
     int64_t m, int k, int n, const void* __restrict__ Av, const uint16_t* __restrict__ Alo,
@@ -55,34 +66,23 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
     T (*tile)[SROW] = lds[w];
     static_assert(AF < 0 || (sizeof(T) == 4 && RL == 4), "16-bit A with float operands");
 
-    // the RL rows r .. r + RL - 1 of column c of A, as T
-    auto loadA = [&](int64_t r, int c, bool full, T (&out)[RL]) {
-        if (AF < 0) {
-            load_run<T, RL, VEC>((const T*)Av + r + (int64_t)c * lda, m - r, full, out);
-        } else {
-            const int64_t off = r + (int64_t)c * lda;
-            uint32_t d[2][2];
+    // 16-bit A: rows r .. r + 7 of column c, one 16-byte run per plane
+    auto loadA16 = [&](int64_t r, int c, bool full, uint32_t (&d)[2][4]) {
+        const int64_t off = r + (int64_t)c * lda;
 #pragma unroll
-            for (int pl = 0; pl < (ASPLIT ? 2 : 1); ++pl) {
-                const uint16_t* h = (pl == 0 ? (const uint16_t*)Av : Alo) + off;
-                if (VEC && full) {
-                    const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(h));
-                    d[pl][0] = v[0];
-                    d[pl][1] = v[1];
-                } else {
+        for (int pl = 0; pl < (ASPLIT ? 2 : 1); ++pl) {
+            const uint16_t* h = (pl == 0 ? (const uint16_t*)Av : Alo) + off;
+            if (VEC && full) {
+                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(h));
 #pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const uint32_t x0 = (2 * e < m - r) ? h[2 * e] : 0u;
-                        const uint32_t x1 = (2 * e + 1 < m - r) ? h[2 * e + 1] : 0u;
-                        d[pl][e] = x0 | (x1 << 16);
-                    }
+                for (int e = 0; e < 4; ++e) d[pl][e] = v[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t x0 = (2 * e < m - r) ? h[2 * e] : 0u;
+                    const uint32_t x1 = (2 * e + 1 < m - r) ? h[2 * e + 1] : 0u;
+                    d[pl][e] = x0 | (x1 << 16);
                 }
-            }
-#pragma unroll
-            for (int q = 0; q < RL; ++q) {
-                float a = half_val<(AF < 0 ? 0 : AF)>(d[0][q >> 1], q & 1);
-                if (ASPLIT) a += half_val<(AF < 0 ? 0 : AF)>(d[1][q >> 1], q & 1);
-                out[q] = (T)a;
             }
         }
     };
@@ -110,7 +110,24 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
         const bool full = (row0 + TR <= m);
         // rows RL*rl + q of each 16*RL-row block g, columns 4 st + kk: the
         // 4-columns-x-256-bytes load pattern, for dC and for A
-        T xv[KSN][RG][RL], xa[KSK][RG][RL];
+        T xv[KSN][RG][RL], xa[AF < 0 ? KSK : 1][RG][RL];
+        // 16-bit A: lane rl holds rows 8 rl .. 8 rl + 7 of the tile, i.e. rows
+        // 8 (rl % 8) .. of staged block rl / 8
+        uint32_t x16[AF < 0 ? 1 : KSK][2][4];
+        if (AF >= 0) {
+            const int64_t r = row0 + 8 * rl;
+#pragma unroll
+            for (int st = 0; st < KSK; ++st) {
+                const int c = 4 * st + kk;
+                if (c < k)
+                    loadA16(r, c, full, x16[AF < 0 ? 0 : st]);
+                else
+#pragma unroll
+                    for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) x16[AF < 0 ? 0 : st][pl][e] = 0u;
+            }
+        }
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
             const int64_t r = row0 + SR * g + RL * rl;
@@ -123,14 +140,17 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
 #pragma unroll
                     for (int q = 0; q < RL; ++q) xv[st][g][q] = T(0);
             }
+            if (AF < 0) {
 #pragma unroll
-            for (int st = 0; st < KSK; ++st) {
-                const int c = 4 * st + kk;
-                if (c < k)
-                    loadA(r, c, full, xa[st][g]);
-                else
+                for (int st = 0; st < KSK; ++st) {
+                    const int c = 4 * st + kk;
+                    if (c < k)
+                        load_run<T, RL, VEC>((const T*)Av + r + (int64_t)c * lda, m - r, full,
+                                             xa[AF < 0 ? st : 0][g]);
+                    else
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) xa[st][g][q] = T(0);
+                        for (int q = 0; q < RL; ++q) xa[AF < 0 ? st : 0][g][q] = T(0);
+                }
             }
         }
         // ---- dA = dC * B^T for this tile
@@ -171,12 +191,35 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
         // columns) and read it back with the reduction index on kk
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
+            wave_lds_fence();
+            if (AF < 0) {
 #pragma unroll
-            for (int st = 0; st < KSK; ++st) {
-                V x;
+                for (int st = 0; st < KSK; ++st) {
+                    V x;
 #pragma unroll
-                for (int q = 0; q < RL; ++q) x[q] = xa[st][g][q];
-                *reinterpret_cast<V*>(&tile[4 * st + kk][RL * rl]) = x;
+                    for (int q = 0; q < RL; ++q) x[q] = xa[AF < 0 ? st : 0][g][q];
+                    *reinterpret_cast<V*>(&tile[4 * st + kk][RL * rl]) = x;
+                }
+            } else if ((rl >> 3) == g) {
+                // widen this lane's 8 rows (hi + lo is exact in float)
+#pragma unroll
+                for (int st = 0; st < KSK; ++st) {
+                    V x0, x1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t(&d)[2][4] = x16[AF < 0 ? 0 : st];
+                        float a0 = half_val<(AF < 0 ? 0 : AF)>(d[0][q >> 1], q & 1);
+                        float a1 = half_val<(AF < 0 ? 0 : AF)>(d[0][2 + (q >> 1)], q & 1);
+                        if (ASPLIT) {
+                            a0 += half_val<(AF < 0 ? 0 : AF)>(d[1][q >> 1], q & 1);
+                            a1 += half_val<(AF < 0 ? 0 : AF)>(d[1][2 + (q >> 1)], q & 1);
+                        }
+                        x0[q] = (T)a0;
+                        x1[q] = (T)a1;
+                    }
+                    *reinterpret_cast<V*>(&tile[4 * st + kk][8 * (rl & 7)]) = x0;
+                    *reinterpret_cast<V*>(&tile[4 * st + kk][8 * (rl & 7) + 4]) = x1;
+                }
             }
 #pragma unroll
             for (int st = 0; st < KSN; ++st) {
@@ -185,6 +228,7 @@ __global__ __launch_bounds__(256) void tsm2l_bwd_kernel(
                 for (int q = 0; q < RL; ++q) x[q] = xv[st][g][q];
                 *reinterpret_cast<V*>(&tile[KP + 4 * st + kk][RL * rl]) = x;
             }
+            wave_lds_fence();
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 V xs[NTK], ys[NTN];
@@ -248,9 +292,9 @@ static int bwd_launch(const LaunchBwd& L, int64_t* blocks_out, hipStream_t st, b
     if (bx < 1) bx = 1;
     *blocks_out = bx;
     if (plan_only) return 0;
-    // A: 16-byte runs of T, or 8-byte runs of the 16-bit planes
+    // A: 16-byte runs of T, or of the 16-bit planes
     const bool avec = AF < 0 ? ((uintptr_t)L.A & 15u) == 0 && (L.lda * (int64_t)sizeof(T)) % 16 == 0
-                             : ((uintptr_t)L.A & 7u) == 0 && L.lda % 4 == 0;
+                             : ((uintptr_t)L.A & 15u) == 0 && L.lda % 8 == 0;
     const bool vec = avec && ((uintptr_t)L.dC & 15u) == 0 && ((uintptr_t)L.dA & 15u) == 0 &&
                      (L.lddc * (int64_t)sizeof(T)) % 16 == 0 &&
                      (L.ldda * (int64_t)sizeof(T)) % 16 == 0;

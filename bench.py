@@ -39,6 +39,8 @@ import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 import paper_2002_03258_amd as tsm  # noqa: E402
+from paper_2002_03258_amd import model as perf_model  # noqa: E402
+from paper_2002_03258_amd import tune  # noqa: E402
 import seeded_inputs as si  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
@@ -109,6 +111,60 @@ def run_step(calls, evs=None):
         tsm.tsm2r(c["A"], c["B"], out=c["C"])
         if evs is not None:
             evs[i][1].record()
+
+
+def _plan_prediction(c):
+    p = tsm.tsm2r_plan(c["m"], c["k"], c["n"], tsm.F64 if c["dtype"] == torch.float64 else tsm.F32)
+    return perf_model.predict_tsm2r(c["m"], c["k"], c["n"], es(c["dtype"]), p["slices"],
+                                    p["tiles"], p["tile_rows"], p["occupancy"])
+
+
+def model_summary(calls, evs, step_bytes, value):
+    """The performance model's prediction for the plans the step ran, against
+    the HIP-event time of each product (median over the timed steps)."""
+    pred_t, errs = 0.0, []
+    for i, c in enumerate(calls):
+        t_pred = _plan_prediction(c).seconds
+        t_meas = float(np.median([evs[s][i][0].elapsed_time(evs[s][i][1]) / 1e3
+                                  for s in range(len(evs))]))
+        pred_t += t_pred
+        errs.append((t_pred - t_meas) / t_meas)
+    dev = perf_model.MI355X
+    return {"predicted_GBps": step_bytes / pred_t / 1e9, "measured_GBps": value,
+            "time_rel_err_mean": float(np.mean(errs)),
+            "time_rel_err_max_abs": float(np.max(np.abs(errs))),
+            "latency_us": dev.latency_us, "stream_GBps": dev.stream_gbs,
+            "knee_workgroups": perf_model.knee_workgroups(dev)}
+
+
+def model_report(calls):
+    """Every candidate plan of each workload: predicted and measured GB/s;
+    then the model's constants fitted to all of them."""
+    print("%-14s %4s %3s %5s %6s %9s %9s %7s" % ("workload", "tall", "S", "WGs", "rounds",
+                                                 "pred GB/s", "meas GB/s", "pred/meas"))
+    samples = []
+    for c in calls:
+        r = tune.autotune_tsm2r(c["A"], c["B"], top=1000, reps=3, pin=False)
+        d = r["default"]
+        for e in sorted(r["report"], key=lambda e: (e["tall"], e["slices"])):
+            pr = perf_model.predict_tsm2r(c["m"], c["k"], c["n"], es(c["dtype"]), e["slices"],
+                                          e["tiles"], e["tile_rows"], e["occupancy"])
+            mark = " planner" if (e["tall"], e["slices"]) == (d["tall"], d["slices"]) else ""
+            mark += " best" if e is r["best"] else ""
+            print("%-14s %4d %3d %5d %6d %9.0f %9.0f %7.2f%s" % (
+                c["workload"], e["tall"], e["slices"], e["workgroups"], pr.rounds,
+                e["pred_gbs"], e["gbs"], e["pred_gbs"] / e["gbs"], mark), flush=True)
+            samples.append(dict(m=c["m"], k=c["k"], n=c["n"], es=es(c["dtype"]),
+                                slices=e["slices"], tiles=e["tiles"], tile_rows=e["tile_rows"],
+                                occupancy=e["occupancy"], seconds=e["seconds"]))
+
+    def rms(dev):
+        return float(np.sqrt(np.mean([np.log(perf_model.predict_tsm2r(
+            s["m"], s["k"], s["n"], s["es"], s["slices"], s["tiles"], s["tile_rows"],
+            s["occupancy"], dev).seconds / s["seconds"]) ** 2 for s in samples])))
+    fitted = perf_model.fit(samples)
+    print("plans %d; rms log(pred/meas) with the built-in constants %.3f, refitted %.3f: %s"
+          % (len(samples), rms(perf_model.MI355X), rms(fitted), fitted), flush=True)
 
 
 def check_calls(calls):
@@ -445,6 +501,11 @@ def main():
                          "(for rocprofv3 counters), e.g. f64:30720:16")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a 1 GiB device copy 5 times (counter calibration)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the plan of each TSM2R workload before the warmup steps")
+    ap.add_argument("--model-report", action="store_true",
+                    help="only time every candidate plan of each TSM2R workload beside the "
+                         "performance model's prediction, and print the table")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
@@ -479,6 +540,18 @@ def main():
     calls = make_r_inputs(dev)
     torch.cuda.synchronize()
     print("inputs ready in %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
+    if args.model_report:
+        model_report(calls)
+        return
+    tuned = None
+    if args.tune:
+        tuned = {}
+        for c in calls:
+            r = tune.autotune_tsm2r(c["A"], c["B"], top=4, reps=3)
+            tuned[c["workload"]] = {"slices": r["best"]["slices"], "tall": r["best"]["tall"],
+                                    "gain": r["best"]["gbs"] / r["default"]["gbs"]}
+            c["kernel"] = r["best"]["kernel"]
+        print("tuned %d workloads" % len(calls), file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         run_step(calls)
     torch.cuda.synchronize()
@@ -529,6 +602,9 @@ def main():
                    "gflop_per_s": step_flops * args.steps / (total_ms / 1e3) / 1e9},
         "roofline": roofline,
     }
+    line["model"] = model_summary(calls, evs, step_bytes, value)
+    if tuned is not None:
+        line["config"]["tuned_plans"] = tuned
     if not args.no_check:
         line["check"] = check_calls(calls)
     del calls

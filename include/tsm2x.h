@@ -212,6 +212,41 @@ size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n,
  * unsupported shapes. */
 const char* tsm2x_kernel_name(int op, int64_t m, int64_t k, int64_t n, int dtype);
 
+/* Launch plan of a TSM2R product (tsm2r, or a TSM2R-class call of
+ * tsm2x_gemm) of column-major F64/F32 A, m-by-k, and n <= 32 columns, on the
+ * current device.  The paper sizes its kernel from a performance model and
+ * offline profiling (Section 3.6, Algorithm 5, and the t1 choice that
+ * follows it); here the planner sizes the grid from the runtime's occupancy
+ * query and a measured target, and a caller may replace its two choices per
+ * shape (tsm2x_tsm2r_pin).  Outputs (each may be NULL):
+ *   slices     k split S (gridDim.y): each workgroup streams k/S columns;
+ *   tall       0: tiles of 16*RL*2 rows with 16-column chunks per
+ *              wavefront; 1: twice the rows with 8-column chunks (RL = 16
+ *              bytes / element size); both keep 8 KB of A in flight per
+ *              wavefront;
+ *   tiles      row tiles (gridDim.x); tile_rows: rows per tile;
+ *   occupancy  resident workgroups per CU of the chosen kernel instance;
+ *   cus        compute units of the device.
+ * Returns 0; -1 m <= 0, -2 k <= 0, -3 n outside 1..32, -4 dtype not
+ * F64/F32; TSM_ERR_UNSUPPORTED if no kernel instance covers the request. */
+int tsm2x_tsm2r_plan(int64_t m, int64_t k, int64_t n, int dtype, int* slices, int* tall,
+                     int64_t* tiles, int* tile_rows, int* occupancy, int* cus);
+
+/* Pin the plan of later TSM2R products of exactly (m, k, n <= 32, dtype
+ * F64/F32), on every device (the table is process-wide and thread-safe):
+ * slices >= 1 forces the k split (rounded, like the planner's own choice,
+ * so that every slice is a whole number of wavefront chunks; the plan query
+ * reports the result), tall 0 / 1 forces the tile height, tall = -1 leaves
+ * it to the planner; slices = 0 with tall = -1 removes the pin.  Results
+ * are the same product for any plan, up to the order of the k sums (the
+ * split sums are added in slice order, in double).  A larger S needs more
+ * workspace: query tsm2x_workspace_size after pinning.  Products wider than
+ * 32 columns run in panels of 32 columns, each looked up by its own width.
+ * Host only, no HIP call.  Returns 0; -1 m <= 0, -2 k <= 0, -3 n outside
+ * 1..32, -4 dtype not F64/F32, -5 slices outside 0..k, -6 tall outside
+ * -1..1. */
+int tsm2x_tsm2r_pin(int64_t m, int64_t k, int64_t n, int dtype, int slices, int tall);
+
 /* Static description of an error code (never NULL). */
 const char* tsm2x_error_string(int code);
 

@@ -16,7 +16,8 @@ from ._lib import (BF16, BF16_SPLIT, F16, F16_SPLIT, F32, F64, OP_GRAD_A, OP_GRA
 
 __all__ = ["tsm2r", "tsm2l", "gemm", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA",
            "colmajor",
-           "empty_colmajor", "workspace_size", "kernel_name", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
+           "empty_colmajor", "workspace_size", "kernel_name", "tsm2r_plan", "pin_tsm2r",
+           "unpin_tsm2r", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
            "BF16_SPLIT", "F16_SPLIT", "OP_TSM2R", "OP_TSM2L", "OP_GRAD_A", "OP_GRAD_B",
            "OP_TSM2R_ROWMAJOR"]
 
@@ -262,6 +263,32 @@ def kernel_name(op: int, m: int, k: int, n: int, dtype: int):
     """Name of the main kernel the call launches (TSM2R, plain types), or None."""
     r = _lib.lib().tsm2x_kernel_name(op, m, k, n, dtype)
     return r.decode() if r else None
+
+
+def tsm2r_plan(m: int, k: int, n: int, dtype: int) -> dict:
+    """Launch plan of a TSM2R product on the current device (F64/F32, n <= 32):
+    k split ``slices``, tile height ``tall`` (0/1), ``tiles``, ``tile_rows``,
+    resident workgroups per CU ``occupancy``, ``cus`` and the kernel name."""
+    import ctypes
+    S, tall, rows, occ, cus = (ctypes.c_int() for _ in range(5))
+    tiles = ctypes.c_int64()
+    _lib.call("tsm2x_tsm2r_plan", m, k, n, dtype, ctypes.byref(S), ctypes.byref(tall),
+              ctypes.byref(tiles), ctypes.byref(rows), ctypes.byref(occ), ctypes.byref(cus))
+    return {"slices": S.value, "tall": tall.value, "tiles": tiles.value,
+            "tile_rows": rows.value, "occupancy": occ.value, "cus": cus.value,
+            "workgroups": tiles.value * S.value,
+            "kernel": kernel_name(OP_TSM2R, m, k, n, dtype)}
+
+
+def pin_tsm2r(m: int, k: int, n: int, dtype: int, slices: int = 0, tall: int = -1) -> None:
+    """Pin the TSM2R plan of shape (m, k, n, dtype) for later calls (slices 0 /
+    tall -1 leave that choice to the planner; both remove the pin)."""
+    _lib.call("tsm2x_tsm2r_pin", m, k, n, dtype, slices, tall)
+
+
+def unpin_tsm2r(m: int, k: int, n: int, dtype: int) -> None:
+    """Remove a pinned TSM2R plan."""
+    pin_tsm2r(m, k, n, dtype, 0, -1)
 
 
 from .autograd import TSMMatmul, matmul  # noqa: E402,F401

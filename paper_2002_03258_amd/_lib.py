@@ -59,6 +59,9 @@ def lib():
             L.tsm2x_workspace_size.restype = sz
             L.tsm2x_kernel_name.argtypes = [i32, i64, i64, i64, i32]
             L.tsm2x_kernel_name.restype = ctypes.c_char_p
+            pi, p64 = ctypes.POINTER(i32), ctypes.POINTER(i64)
+            L.tsm2x_tsm2r_plan.argtypes = [i64, i64, i64, i32, pi, pi, p64, pi, pi, pi]
+            L.tsm2x_tsm2r_pin.argtypes = [i64, i64, i64, i32, i32, i32]
             L.tsm2x_error_string.argtypes = [i32]
             L.tsm2x_error_string.restype = ctypes.c_char_p
             L.tsm2x_last_hip_error.argtypes = []
@@ -68,7 +71,8 @@ def lib():
             L.tsm2x_finalize.restype = None
             for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a",
                       "tsm_grad_b",
-                      "tsm2l_backward", "tsm2x_split", "tsm2x_version"):
+                      "tsm2l_backward", "tsm2x_split", "tsm2x_version", "tsm2x_tsm2r_plan",
+                      "tsm2x_tsm2r_pin"):
                 getattr(L, f).restype = i32
             _lib = L
     return _lib
@@ -84,5 +88,6 @@ def call(fn: str, *args) -> None:
 EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a", "tsm_grad_b",
            "tsm2l_backward",
            "tsm2x_split",
-           "tsm2x_workspace_size", "tsm2x_kernel_name", "tsm2x_error_string", "tsm2x_last_hip_error",
+           "tsm2x_workspace_size", "tsm2x_kernel_name", "tsm2x_tsm2r_plan", "tsm2x_tsm2r_pin",
+           "tsm2x_error_string", "tsm2x_last_hip_error",
            "tsm2x_version", "tsm2x_finalize")

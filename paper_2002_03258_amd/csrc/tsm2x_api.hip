@@ -5,7 +5,9 @@
 #include <stdint.h>
 
 #include <cstdlib>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -86,6 +88,22 @@ int pow2_ge(int64_t n) {
 }
 
 // ------------------------------------------------------------- plans
+// TSM2R plans pinned by the caller, per (m, k, n, dtype); shared by all devices
+typedef std::tuple<int64_t, int64_t, int64_t, int> PinKey;
+std::mutex g_pin_mu;
+std::map<PinKey, NNPin> g_pins;
+
+NNPin pin_of(int64_t m, int64_t k, int64_t n, int dtype) {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pins.find(PinKey(m, k, n, dtype));
+    return it == g_pins.end() ? NNPin{0, -1} : it->second;
+}
+
+int plan_nn(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P) {
+    const NNPin pin = pin_of(m, k, n, dtype);
+    return plan_tsm2r(m, k, n, dtype, cus, vec, P, &pin);
+}
+
 struct RTPlan {
     int kp;
     int64_t cpb;
@@ -262,7 +280,7 @@ size_t tsm2r_ws(int transA, int64_t m, int64_t k, int64_t n, int dtype, bool tra
         part = plan_tn(k, m, n, dtype, cus).ws;
     } else {
         NNPlan P{};
-        if (!plan_tsm2r(m, k, n, dtype, cus, true, &P)) part = P.ws;
+        if (!plan_nn(m, k, n, dtype, cus, true, &P)) part = P.ws;
     }
     return align256(part) + (transB ? (size_t)bt_ld(k, ce) * n * ce : 0);
 }
@@ -351,7 +369,7 @@ int product(bool lform, int transA, int transB, int64_t m, int64_t k, int64_t n,
         return check_launch("tn_kernel");
     }
     NNPlan P{};
-    if (plan_tsm2r(m, k, n, dtype, cus, vec_ok(A, lda, esize(dtype)), &P)) return TSM_ERR_UNSUPPORTED;
+    if (plan_nn(m, k, n, dtype, cus, vec_ok(A, lda, esize(dtype)), &P)) return TSM_ERR_UNSUPPORTED;
     LaunchNN L{};
     L.fn = P.fn;
     L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = Bk; L.ldb = ldbk; L.C = C; L.ldc = ldc;
@@ -550,7 +568,40 @@ const char* tsm2x_kernel_name(int op, int64_t m, int64_t k, int64_t n, int dtype
     if (op != TSM_OP_TSM2R || m <= 0 || k <= 0 || n <= 0 || n > 32 || !plain_dtype(dtype))
         return nullptr;
     NNPlan P{};
-    return plan_tsm2r(m, k, n, dtype, cu_count(), true, &P) ? nullptr : P.name;
+    return plan_nn(m, k, n, dtype, cu_count(), true, &P) ? nullptr : P.name;
+}
+
+int tsm2x_tsm2r_plan(int64_t m, int64_t k, int64_t n, int dtype, int* slices, int* tall,
+                     int64_t* tiles, int* tile_rows, int* occupancy, int* cus) {
+    if (m <= 0) return -1;
+    if (k <= 0) return -2;
+    if (n <= 0 || n > 32) return -3;
+    if (!plain_dtype(dtype)) return -4;
+    const int c = cu_count();
+    NNPlan P{};
+    if (plan_nn(m, k, n, dtype, c, true, &P)) return TSM_ERR_UNSUPPORTED;
+    if (slices) *slices = P.S;
+    if (tall) *tall = P.tall;
+    if (tiles) *tiles = P.tiles;
+    if (tile_rows) *tile_rows = P.tile_rows;
+    if (occupancy) *occupancy = P.occ;
+    if (cus) *cus = c;
+    return TSM_SUCCESS;
+}
+
+int tsm2x_tsm2r_pin(int64_t m, int64_t k, int64_t n, int dtype, int slices, int tall) {
+    if (m <= 0) return -1;
+    if (k <= 0) return -2;
+    if (n <= 0 || n > 32) return -3;
+    if (!plain_dtype(dtype)) return -4;
+    if (slices < 0 || slices > k) return -5;
+    if (tall < -1 || tall > 1) return -6;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (slices == 0 && tall == -1)
+        g_pins.erase(PinKey(m, k, n, dtype));
+    else
+        g_pins[PinKey(m, k, n, dtype)] = NNPin{slices, tall};
+    return TSM_SUCCESS;
 }
 
 const char* tsm2x_error_string(int code) {

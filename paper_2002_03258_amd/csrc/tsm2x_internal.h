@@ -18,12 +18,23 @@ struct NNPlan {             // TSM2R launch plan (column-major A)
     int S;                  // k slices (gridDim.y)
     int64_t kslice;         // columns per k slice
     size_t ws;              // workspace bytes (0 when S == 1)
+    int tall;               // 1: the taller of the two tile heights
+    int occ;                // resident workgroups per CU of the instance
+};
+
+// A plan fixed by the caller for one shape: S >= 1 forces the k split (rounded
+// as the planner rounds it), tall >= 0 forces the tile height.
+struct NNPin {
+    int S;
+    int tall;
 };
 
 // Plan of tsm2r for (m, k, n, dtype) on a device with `cus` compute units;
-// `vec`: A is 16-byte aligned with a 16-byte multiple leading dimension.
+// `vec`: A is 16-byte aligned with a 16-byte multiple leading dimension;
+// `pin` (may be null) overrides the planner's choices.
 // Returns nonzero if no kernel instance covers the request.
-int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P);
+int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P,
+               const NNPin* pin);
 
 struct LaunchNN {           // tsm2r_nn: C = A*B, column-major A
     const void* fn;

@@ -234,8 +234,10 @@ static inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // workgroup more than others runs at the pace of those CUs.  For each tile
 // height the k split S is the one that brings tiles * S closest to that
 // target; the tile height whose grid lands closer wins, ties going to fewer
-// slices (longer streams per wavefront).
-int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P) {
+// slices (longer streams per wavefront).  A pin from the caller (an
+// autotuner) replaces either choice.
+int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P,
+               const NNPin* pin) {
     // partial sums are stored at the kernel's padded width (16 or 32 columns)
     const int np = n <= 16 ? 16 : 32;
     const int es = dtype == DT_F64 ? 8 : 4;
@@ -246,7 +248,10 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
     const char* fs = std::getenv("TSM2X_NN_S");
     const int64_t s_force = (fs && *fs) ? std::strtoll(fs, nullptr, 10) : 0;
     const char* fh = std::getenv("TSM2X_NN_TALL");     // 0 or 1 forces a tile height
-    const int64_t tall_force = (fh && *fh) ? std::strtoll(fh, nullptr, 10) : -1;
+    int64_t tall_force = (fh && *fh) ? std::strtoll(fh, nullptr, 10) : -1;
+    int64_t s_pin = s_force;
+    if (pin && pin->S > 0) s_pin = pin->S;
+    if (pin && pin->tall >= 0) tall_force = pin->tall;
 
     bool found = false;
     double best_dev = 0;
@@ -264,7 +269,7 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
         if (S > s_len) S = s_len;
         if (S > s_cost) S = s_cost;
         if (S < 1) S = 1;
-        if (s_force > 0) S = s_force;
+        if (s_pin > 0) S = s_pin;
         const int64_t gran = (int64_t)WK * I.chunk;
         int64_t ks = cdiv64(k, S);
         ks = cdiv64(ks, gran) * gran;
@@ -284,6 +289,8 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
             P->kslice = ks;
             P->S = (int)S;
             P->ws = S > 1 ? (size_t)tiles * S * np * I.tile_rows * 8 : 0;
+            P->tall = tall;
+            P->occ = I.occ;
         }
     }
     return found ? 0 : 1;

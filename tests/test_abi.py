@@ -160,3 +160,27 @@ def test_kernel_name_query():
     assert tsm.kernel_name(tsm.OP_TSM2R, 0, 4096, 8, tsm.F64) is None
     assert tsm.kernel_name(tsm.OP_TSM2L, 4096, 8, 8, tsm.F64) is None
     assert tsm.kernel_name(tsm.OP_TSM2R, 4096, 4096, 8, tsm.BF16) is None
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((0, 100, 8, 0, 1, 0), -1), ((100, 0, 8, 0, 1, 0), -2), ((100, 100, 0, 0, 1, 0), -3),
+    ((100, 100, 33, 0, 1, 0), -3), ((100, 100, 8, 2, 1, 0), -4), ((100, 100, 8, 9, 1, 0), -4),
+    ((100, 100, 8, 0, -1, 0), -5), ((100, 100, 8, 0, 101, 0), -5), ((100, 100, 8, 0, 1, 2), -6),
+    ((100, 100, 8, 0, 1, -2), -6)])
+def test_tsm2r_pin_argument_checks(args, expect):
+    assert _lib.lib().tsm2x_tsm2r_pin(*args) == expect
+
+
+def test_tsm2r_pin_and_unpin_on_host():
+    L = _lib.lib()
+    assert L.tsm2x_tsm2r_pin(1000, 2000, 8, 0, 3, 1) == 0
+    assert L.tsm2x_tsm2r_pin(1000, 2000, 8, 0, 0, -1) == 0      # removes it
+    assert L.tsm2x_tsm2r_pin(1000, 2000, 8, 0, 0, -1) == 0      # removing twice is fine
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((0, 100, 8, 0), -1), ((100, 0, 8, 0), -2), ((100, 100, 0, 0), -3), ((100, 100, 40, 0), -3),
+    ((100, 100, 8, 4), -4)])
+def test_tsm2r_plan_argument_checks(args, expect):
+    n = None
+    assert _lib.lib().tsm2x_tsm2r_plan(*args, n, n, n, n, n, n) == expect

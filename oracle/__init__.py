@@ -18,6 +18,9 @@ unblocked, sequential sums) with numpy marshalling:
   compute-bound regimes (Design of TSM2R, "Determine compute-bound or
   memory-bound"): t2 = PeakPerf / PeakBand * bytes_per_element.
 - :func:`normwise_error` -- ||C - C_ref||_F / ||C_ref||_F.
+- :func:`kmeans_assign` -- the K-means assignment step named in the paper's
+  Introduction: nearest centroid by squared Euclidean distance, from its
+  definition.
 """
 from __future__ import annotations
 
@@ -77,6 +80,9 @@ def _load():
             lib.tsm_oracle_split.argtypes = [ctypes.c_void_p, i64, ctypes.c_int,
                                              ctypes.c_void_p, ctypes.c_void_p]
             lib.tsm_oracle_split.restype = None
+            lib.tsm_oracle_kmeans_assign.argtypes = [i64, i64, i64, dp, i64, i64, dp, i64, i64,
+                                                     ctypes.c_void_p, ctypes.c_void_p]
+            lib.tsm_oracle_kmeans_assign.restype = None
             lib.tsm_oracle_threads.argtypes = []
             lib.tsm_oracle_threads.restype = ctypes.c_int
             lib.tsm_oracle_set_threads.argtypes = [ctypes.c_int]
@@ -116,6 +122,26 @@ def matmul(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     lib.tsm_oracle_matmul(m, k, n, _dptr(A), ars, acs, _dptr(B), brs, bcs,
                           _dptr(C), crs, ccs)
     return C
+
+
+def kmeans_assign(X: np.ndarray, Mu: np.ndarray):
+    """(labels, dist) for points X (m x k, one point per row) and centroids Mu
+    (k x n, one centroid per column): labels[i] is the smallest c minimising
+    sum_j (X[i,j] - Mu[j,c])^2 (NaN distances skipped; label 0 if all are
+    NaN), dist[i] that minimum, in double precision."""
+    lib = _load()
+    X = np.asarray(X, dtype=np.float64)
+    Mu = np.asarray(Mu, dtype=np.float64)
+    m, k = X.shape
+    k2, n = Mu.shape
+    assert k == k2 and n >= 1, (X.shape, Mu.shape)
+    labels = np.empty(m, dtype=np.int32)
+    dist = np.empty(m, dtype=np.float64)
+    xrs, xcs = _strides(X)
+    mrs, mcs = _strides(Mu)
+    lib.tsm_oracle_kmeans_assign(m, k, n, _dptr(X), xrs, xcs, _dptr(Mu), mrs, mcs,
+                                 labels.ctypes.data, dist.ctypes.data)
+    return labels, dist
 
 
 def grad(A: np.ndarray, B: np.ndarray, dC: np.ndarray):

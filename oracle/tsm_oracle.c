@@ -25,6 +25,11 @@
  *  - tsm_oracle_split: the storage form of A used by the low-precision path:
  *    hi = round(a), lo = round(a - hi).  a - hi is formed in double, where it
  *    is exact.
+ *  - tsm_oracle_kmeans_assign: the assignment step of K-means, the
+ *    application the paper's Introduction names as a tall-and-skinny GEMM
+ *    user (many points, few centroids): each point goes to the centroid at
+ *    the smallest squared Euclidean distance, sum over j of
+ *    (x[i,j] - mu[j,c])^2, taken here as that definition (not expanded).
  */
 #include <math.h>
 #include <stdint.h>
@@ -186,4 +191,45 @@ void tsm_oracle_set_threads(int n)
 #else
     (void)n;
 #endif
+}
+
+/* Points X (m-by-k, element (i,j) at X[i*x_rs + j*x_cs]) and centroids
+ * (k-by-n, centroid c is column c, element (j,c) at Mu[j*m_rs + c*m_cs]).
+ * label[i] = the smallest c with the smallest D[i,c] = sum_j (x_ij - mu_jc)^2
+ * (NaN distances never compare smaller; a row with no non-NaN distance gets
+ * label 0); dist[i] = D[i, label[i]] (dist may be NULL). */
+void tsm_oracle_kmeans_assign(int64_t m, int64_t k, int64_t n,
+                              const double* X, int64_t x_rs, int64_t x_cs,
+                              const double* Mu, int64_t m_rs, int64_t m_cs,
+                              int32_t* label, double* dist)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < m; ++i) {
+        int64_t best = -1;
+        double bd = 0.0;
+        for (int64_t c = 0; c < n; ++c) {
+            double d = 0.0;
+            for (int64_t j = 0; j < k; ++j) {
+                const double e = X[i * x_rs + j * x_cs] - Mu[j * m_rs + c * m_cs];
+                d += e * e;
+            }
+            if (d != d) continue;
+            if (best < 0 || d < bd) {
+                best = c;
+                bd = d;
+            }
+        }
+        if (best < 0) {                 /* every distance is NaN */
+            double d = 0.0;
+            for (int64_t j = 0; j < k; ++j) {
+                const double e = X[i * x_rs + j * x_cs] - Mu[j * m_rs];
+                d += e * e;
+            }
+            best = 0;
+            bd = d;
+        }
+        label[i] = (int32_t)best;
+        if (dist) dist[i] = bd;
+    }
 }

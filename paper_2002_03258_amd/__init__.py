@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (BF16, BF16_SPLIT, F16, F16_SPLIT, F32, F64, OP_GRAD_A, OP_GRAD_B, OP_TSM2L,
                    OP_TSM2R, OP_TSM2R_ROWMAJOR, TSMError)
 
-__all__ = ["tsm2r", "tsm2l", "gemm", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA",
+__all__ = ["tsm2r", "tsm2l", "gemm", "tsmttsm", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA",
            "colmajor",
            "empty_colmajor", "workspace_size", "kernel_name", "tsm2r_plan", "pin_tsm2r",
            "unpin_tsm2r", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
@@ -184,6 +184,17 @@ def gemm(A, B: torch.Tensor, out: torch.Tensor | None = None, beta: float = 0.0,
          workspace: torch.Tensor | None = None) -> torch.Tensor:
     """C := beta*C + A*B, TSM2L or TSM2R chosen by the shape of A."""
     return _product("tsm2x_gemm", A, B, out, beta, workspace)
+
+
+def tsmttsm(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
+            beta: float = 0.0, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """C := beta*C + A^T*B for two tall matrices that share their long
+    dimension (A m x k and B m x n, F64/F32, m large): the TSMTTSM form the
+    paper names in its related work.  C is k x n; it runs on the reduction
+    kernel of dB = A^T*dC (n in panels of 32 columns)."""
+    if A.dim() != 2 or B.dim() != 2 or A.shape[0] != B.shape[0]:
+        raise ValueError("tsmttsm: A (m x k) and B (m x n) must share m")
+    return gemm(A.t(), B, out=out, beta=beta, workspace=workspace)
 
 
 def grad_a(dC: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

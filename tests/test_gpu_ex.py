@@ -159,3 +159,38 @@ def test_lowp_beta_and_transposed_b(dev, fn, m, k, n, lo):
     ref = _ref(_stored(Ah, oracle.BF16, lo), host_matrix(seed, si.STREAM_B, k, n, torch.float32),
                host_matrix(seed, STREAM_C0, m, n, torch.float32), 0.75)
     assert err(to_np(C), ref) <= TOL_LP
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,k,n", [(1 << 20, 16, 16), (300001, 8, 40), (100003, 64, 8),
+                                   (4097, 3, 1), (77, 20, 33)])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_tsmttsm(dev, dtype, m, k, n, beta):
+    seed = 2300 + m % 1000 + k + n
+    A = dev_matrix(seed, si.STREAM_A, m, k, dtype, dev)
+    B = dev_matrix(seed, si.STREAM_B, m, n, dtype, dev, dist="normal")
+    C0 = dev_matrix(seed, STREAM_C0, k, n, dtype, dev)
+    C = tsm.tsmttsm(A, B, out=C0.clone(), beta=beta)
+    Ah = host_matrix(seed, si.STREAM_A, m, k, dtype)
+    Bh = host_matrix(seed, si.STREAM_B, m, n, dtype, dist="normal")
+    ref = _ref(np.ascontiguousarray(Ah.T), Bh, host_matrix(seed, STREAM_C0, k, n, dtype), beta)
+    assert err(to_np(C), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_tsmttsm_integer_bit_exact_and_deterministic(dev, dtype):
+    m, k, n = 500001, 16, 24
+    A = dev_matrix(71, si.STREAM_A, m, k, dtype, dev, dist="int", r=2)
+    B = dev_matrix(71, si.STREAM_B, m, n, dtype, dev, dist="int", r=2)
+    C = tsm.tsmttsm(A, B)
+    ref = oracle.matmul(np.ascontiguousarray(host_matrix(71, si.STREAM_A, m, k, dtype, dist="int",
+                                                         r=2).T),
+                        host_matrix(71, si.STREAM_B, m, n, dtype, dist="int", r=2))
+    assert np.array_equal(to_np(C), ref)
+    assert torch.equal(C, tsm.tsmttsm(A, B))
+
+
+def test_tsmttsm_shape_check(dev):
+    A = torch.zeros(10, 3, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        tsm.tsmttsm(A, torch.zeros(11, 2, dtype=torch.float64, device=dev))

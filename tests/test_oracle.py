@@ -277,3 +277,85 @@ def test_normwise_error():
     assert oracle.normwise_error([[3.0, 4.0]], [[0.0, 0.0]]) == 5.0
     assert oracle.normwise_error([[1.0, 1.0]], [[1.0, 1.0]]) == 0.0
     assert abs(oracle.normwise_error([[1.1]], [[1.0]]) - 0.1) < 1e-12
+
+
+# ------------------------------------------------------------ k-means assignment
+def _kmeans_brute(X, Mu):
+    """Exact rational distances, first index among equal minima."""
+    from fractions import Fraction
+    m, k = X.shape
+    n = Mu.shape[1]
+    labels, dists = [], []
+    for i in range(m):
+        best, bd = None, None
+        for c in range(n):
+            d = sum((Fraction(X[i, j]) - Fraction(Mu[j, c])) ** 2 for j in range(k))
+            if bd is None or d < bd:
+                best, bd = c, d
+        labels.append(best)
+        dists.append(bd)
+    return np.array(labels), dists
+
+
+@pytest.mark.parametrize("m,k,n,seed", [(7, 3, 4, 1), (9, 1, 5, 2), (5, 6, 1, 3), (12, 4, 9, 4),
+                                        (3, 9, 2, 5)])
+def test_kmeans_oracle_against_exact_brute_force(m, k, n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.integers(-32, 33, (m, k)) / 8.0          # dyadic: every distance exact in double
+    Mu = rng.integers(-32, 33, (k, n)) / 8.0
+    lab, dist = oracle.kmeans_assign(X, Mu)
+    blab, bdist = _kmeans_brute(X, Mu)
+    assert np.array_equal(lab, blab)
+    assert [float(d) for d in bdist] == dist.tolist()
+
+
+def test_kmeans_oracle_one_dimension_matches_sorted_search():
+    rng = np.random.default_rng(11)
+    cents = np.sort(rng.choice(np.arange(-1000, 1000), 40, replace=False)).astype(np.float64)
+    pts = rng.integers(-1100, 1100, 5000) + 0.25        # never on a midpoint of integers
+    lab, dist = oracle.kmeans_assign(pts[:, None], cents[None, :])
+    pos = np.clip(np.searchsorted(cents, pts), 1, len(cents) - 1)
+    left, right = cents[pos - 1], cents[pos]
+    want = np.where(pts - left <= right - pts, pos - 1, pos)
+    want[pts < cents[0]] = 0
+    want[pts > cents[-1]] = len(cents) - 1
+    assert np.array_equal(lab, want)
+    assert np.array_equal(dist, (pts - cents[want]) ** 2)
+
+
+def test_kmeans_oracle_points_on_centroids_and_ties():
+    rng = np.random.default_rng(12)
+    Mu = rng.standard_normal((5, 6))
+    Mu[:, 4] = Mu[:, 1]                               # a duplicate centroid: ties go to 1
+    X = np.ascontiguousarray(Mu.T)                     # point c sits on centroid c
+    lab, dist = oracle.kmeans_assign(X, Mu)
+    assert lab.tolist() == [0, 1, 2, 3, 1, 5]
+    assert np.all(dist == 0)
+
+
+def test_kmeans_oracle_permutation_and_translation():
+    rng = np.random.default_rng(13)
+    X = rng.integers(-8, 9, (400, 7)).astype(np.float64)
+    Mu = rng.integers(-8, 9, (7, 10)).astype(np.float64) + 0.5
+    lab, dist = oracle.kmeans_assign(X, Mu)
+    perm = rng.permutation(10)
+    lab_p, dist_p = oracle.kmeans_assign(X, Mu[:, perm])
+    # the distance is unique; the label is a minimiser, and the same centroid
+    # wherever the minimiser is unique
+    assert np.array_equal(dist_p, dist)
+    D = ((X[:, :, None] - Mu[None, :, :]) ** 2).sum(axis=1)
+    assert np.all(D[np.arange(400), perm[lab_p]] == dist)
+    unique = (D == dist[:, None]).sum(axis=1) == 1
+    assert unique.sum() > 200
+    assert np.array_equal(perm[lab_p][unique], lab[unique])
+    v = rng.integers(-50, 50, 7).astype(np.float64)
+    lab_t, dist_t = oracle.kmeans_assign(X + v, Mu + v[:, None])
+    assert np.array_equal(lab_t, lab) and np.array_equal(dist_t, dist)
+
+
+def test_kmeans_oracle_nan_handling():
+    X = np.array([[0.0, 0.0], [np.nan, 1.0], [5.0, 5.0]])
+    Mu = np.array([[np.nan, 1.0, 4.0], [0.0, 1.0, 4.0]])    # centroid 0 has a NaN coordinate
+    lab, dist = oracle.kmeans_assign(X, Mu)
+    assert lab.tolist() == [1, 0, 2]                   # row 1: every distance NaN -> label 0
+    assert dist[0] == 2.0 and np.isnan(dist[1]) and dist[2] == 2.0

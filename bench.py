@@ -308,6 +308,58 @@ def rows_tsm2l(dev):
     return out
 
 
+def rows_kmeans(dev):
+    """K-means assignment (the Introduction's tall-and-skinny GEMM user):
+    m = 2^24 points, k = 16 coordinates, n = 16 centroids, points stored
+    column-major.  GB/s counts X and the centroids read once and the labels
+    and distances written once.  For comparison, the same result composed of
+    unfused steps: the cross terms by the library's TSM2L product (an m x n
+    matrix written), then the scores and the argmin by torch (that matrix
+    read back)."""
+    import oracle
+    from paper_2002_03258_amd import kmeans
+    out = []
+    seed = si.config_seed(7)
+    m, k, n = 1 << 24, 16, 16
+    for dtype in R_DTYPES:
+        X = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
+        Mu = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype, device=dev)
+        cent = Mu.t()
+        flush = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+        res = {}
+
+        def fused():
+            res["r"] = kmeans.assign(X, cent)
+        t = timed(fused, flush=flush.zero_)
+        lab, dist = res["r"]
+        mu2 = (Mu * Mu).sum(dim=0)
+
+        def unfused():
+            G = tsm.tsm2l(X, Mu)
+            return torch.min(mu2[None, :] - 2 * G, dim=1)
+        t_unf = timed(unfused, flush=flush.zero_)
+        nb = (m * k + k * n + m) * es(dtype) + 4 * m
+        rows = [0, 1, m // 3, m // 2 + 7, m - 1]
+        Xr = si.matrix_rows(seed, si.STREAM_A, m, k, rows, dtype=dtype).double().numpy()
+        rlab, rdist = oracle.kmeans_assign(Xr, Mu.double().cpu().numpy())
+        got = lab[rows].cpu().numpy()
+        D = ((Xr[:, :, None] - Mu.double().cpu().numpy()[None]) ** 2).sum(axis=1)
+        u = torch.finfo(dtype).eps / 2
+        tol = 4 * (k + 2) * u * (np.sqrt((Xr ** 2).sum(1))[:, None]
+                                 + np.sqrt((Mu.double().cpu().numpy() ** 2).sum(0))[None]).max(1) ** 2
+        ok = bool(np.all(D[np.arange(len(rows)), got] <= rdist + tol) and
+                  np.all(np.abs(dist[rows].double().cpu().numpy() - D[np.arange(len(rows)), got])
+                         <= tol))
+        out.append({"row": "kmeans assignment, m = 2^24 points, k = 16, n = 16 centroids (fused)",
+                    "dtype": str(dtype).replace("torch.", ""), "GBps": nb / t / 1e9,
+                    "frac_of_8TBps": nb / t / 1e9 / PEAK_HBM_GBS, "ms": t * 1e3,
+                    "unfused_ms": t_unf * 1e3, "speedup_vs_unfused": t_unf / t,
+                    "sampled_rows_ok": ok, "labels_equal_oracle_on_sample": bool(np.array_equal(got, rlab))})
+        del X, Mu, cent, flush, res, lab, dist
+        torch.cuda.empty_cache()
+    return out
+
+
 def rows_general(dev):
     """Shapes beyond one kernel launch: n > 32 in 32-column panels (A read once
     per panel, the paper's t2 < n), a TSM2L-class product with k > 32 (on the
@@ -611,7 +663,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_rows:
         line["rows"] = attach_ceilings(rows_tsm2l(dev) + rows_lowp(dev) + rows_autograd(dev) +
-                                       rows_general(dev))
+                                       rows_general(dev) + rows_kmeans(dev))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -11,8 +11,8 @@ from __future__ import annotations
 import torch
 
 from . import _lib
-from ._lib import (BF16, BF16_SPLIT, F16, F16_SPLIT, F32, F64, OP_GRAD_A, OP_GRAD_B, OP_TSM2L,
-                   OP_TSM2R, OP_TSM2R_ROWMAJOR, TSMError)
+from ._lib import (BF16, BF16_SPLIT, F16, F16_SPLIT, F32, F64, OP_GRAD_A, OP_GRAD_B, OP_KMEANS,
+                   OP_TSM2L, OP_TSM2R, OP_TSM2R_ROWMAJOR, TSMError)
 
 __all__ = ["tsm2r", "tsm2l", "gemm", "tsmttsm", "grad_a", "grad_b", "tsm2l_backward", "split", "SplitA",
            "colmajor",

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TSM2X_LIBRARY") or os.path.join(HERE, "libtsm2x.so")
 
 F64, F32, BF16, F16, BF16_SPLIT, F16_SPLIT = range(6)
-OP_TSM2R, OP_TSM2L, OP_GRAD_A, OP_GRAD_B, OP_TSM2R_ROWMAJOR = range(5)
+OP_TSM2R, OP_TSM2L, OP_GRAD_A, OP_GRAD_B, OP_TSM2R_ROWMAJOR, OP_KMEANS = range(6)
 
 _lock = threading.Lock()
 _lib = None
@@ -55,6 +55,8 @@ def lib():
             L.tsm2x_split.argtypes = [i64, i64, vp, i64, vp, vp, i64, i32, vp]
             L.tsm2l_backward.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                                          i32, vp, sz, vp]
+            L.tsm_kmeans_assign.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, vp, i32, vp, sz,
+                                            vp]
             L.tsm2x_workspace_size.argtypes = [i32, i64, i64, i64, i32]
             L.tsm2x_workspace_size.restype = sz
             L.tsm2x_kernel_name.argtypes = [i32, i64, i64, i64, i32]
@@ -72,6 +74,7 @@ def lib():
             for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a",
                       "tsm_grad_b",
                       "tsm2l_backward", "tsm2x_split", "tsm2x_version", "tsm2x_tsm2r_plan",
+                      "tsm_kmeans_assign",
                       "tsm2x_tsm2r_pin"):
                 getattr(L, f).restype = i32
             _lib = L
@@ -86,7 +89,7 @@ def call(fn: str, *args) -> None:
 
 
 EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a", "tsm_grad_b",
-           "tsm2l_backward",
+           "tsm2l_backward", "tsm_kmeans_assign",
            "tsm2x_split",
            "tsm2x_workspace_size", "tsm2x_kernel_name", "tsm2x_tsm2r_plan", "tsm2x_tsm2r_pin",
            "tsm2x_error_string", "tsm2x_last_hip_error",

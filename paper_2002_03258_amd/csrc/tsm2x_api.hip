@@ -551,7 +551,35 @@ int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, voi
     return check_launch("split_kernel");
 }
 
+int tsm_kmeans_assign(int64_t m, int64_t k, int64_t n, const void* X, int64_t ldx,
+                      const void* Mu, int64_t ldm, int32_t* labels, void* dist, int dtype,
+                      void* ws, size_t ws_bytes, void* stream) {
+    if (m < 0) return -1;
+    if (k < 1 || k > INT32_MAX) return -2;
+    if (n < 1 || n > INT32_MAX) return -3;
+    if (!X && m > 0) return -4;
+    if (ldx < (m > 1 ? m : 1)) return -5;
+    if (!Mu) return -6;
+    if (ldm < k) return -7;
+    if (!labels && m > 0) return -8;
+    if (!plain_dtype(dtype)) return -10;
+    if (m == 0) return TSM_SUCCESS;
+    void* w = nullptr;
+    int rc = get_ws(align256((size_t)n * esize(dtype)), ws, ws_bytes, &w);
+    if (rc) return rc;
+    LaunchKM L{};
+    L.m = m; L.k = k; L.n = n; L.X = X; L.ldx = ldx; L.Mu = Mu; L.ldm = ldm; L.mu2 = w;
+    L.labels = labels; L.dist = dist; L.cus = cu_count();
+    if (launch_kmeans_assign(L, dtype, (hipStream_t)stream)) {
+        g_last_hip = "kmeans_assign_kernel: launch failed";
+        return TSM_ERR_HIP;
+    }
+    return TSM_SUCCESS;
+}
+
 size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n, int dtype) {
+    if (op == TSM_OP_KMEANS)
+        return (m >= 0 && k >= 1 && n >= 1 && plain_dtype(dtype)) ? align256((size_t)n * esize(dtype)) : 0;
     if (m <= 0 || k <= 0 || n <= 0 || !valid_dtype(dtype)) return 0;
     const int64_t np = n < 32 ? n : 32;      // panels of 32 columns reuse one workspace
     // products: enough for a B given transposed as well

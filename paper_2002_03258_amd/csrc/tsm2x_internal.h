@@ -119,4 +119,15 @@ int launch_transpose(int64_t k, int64_t n, const void* Bt, int64_t ldb, void* O,
 int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t rows, int n,
                         const double* part, void* O, int64_t ldo, double beta, hipStream_t st);
 
+struct LaunchKM {           // K-means assignment: points X (m x k), centroids Mu (k x n)
+    int64_t m, k, n;
+    const void* X; int64_t ldx;
+    const void* Mu; int64_t ldm;
+    void* mu2;              // n values of the dtype (workspace): ||mu_c||^2
+    int32_t* labels;        // m
+    void* dist;             // m, or null
+    int cus;
+};
+int launch_kmeans_assign(const LaunchKM& L, int dtype, hipStream_t st);
+
 }  // namespace tsm

@@ -184,3 +184,23 @@ def test_tsm2r_pin_and_unpin_on_host():
 def test_tsm2r_plan_argument_checks(args, expect):
     n = None
     assert _lib.lib().tsm2x_tsm2r_plan(*args, n, n, n, n, n, n) == expect
+
+
+def test_kmeans_argument_checks():
+    L = _lib.lib()
+    p = 4096                                    # never dereferenced: the checks come first
+    ok = [1000, 16, 8, p, 1000, p, 16, p, None, 0, None, 0, None]
+    for pos, bad in [(1, -1), (2, 0), (3, 0), (4, None), (5, 999), (6, None), (7, 15), (8, None),
+                     (10, 2)]:
+        args = list(ok)
+        args[pos - 1] = bad
+        assert L.tsm_kmeans_assign(*args) == -pos, pos
+    empty = list(ok)
+    empty[0] = 0
+    assert L.tsm_kmeans_assign(*empty) == 0     # no points: nothing to do, no GPU call
+
+
+def test_kmeans_workspace_size():
+    assert tsm.workspace_size(tsm.OP_KMEANS, 1000, 16, 8, tsm.F64) == 256
+    assert tsm.workspace_size(tsm.OP_KMEANS, 1000, 16, 100, tsm.F32) == 512
+    assert tsm.workspace_size(tsm.OP_KMEANS, 1000, 16, 8, tsm.BF16) == 0

@@ -311,7 +311,7 @@ def rows_tsm2l(dev):
 def rows_kmeans(dev):
     """K-means assignment (the Introduction's tall-and-skinny GEMM user):
     m = 2^24 points, k = 16 coordinates, n = 16 centroids, points stored
-    column-major.  GB/s counts X and the centroids read once and the labels
+    column-major and row-major.  GB/s counts X and the centroids read once and the labels
     and distances written once.  For comparison, the same result composed of
     unfused steps: the cross terms by the library's TSM2L product (an m x n
     matrix written), then the scores and the argmin by torch (that matrix
@@ -321,8 +321,10 @@ def rows_kmeans(dev):
     out = []
     seed = si.config_seed(7)
     m, k, n = 1 << 24, 16, 16
-    for dtype in R_DTYPES:
+    for dtype, layout in [(d, lay) for d in R_DTYPES for lay in ("column-major", "row-major")]:
         X = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
+        if layout == "row-major":
+            X = X.contiguous()
         Mu = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype, device=dev)
         cent = Mu.t()
         flush = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
@@ -350,7 +352,8 @@ def rows_kmeans(dev):
         ok = bool(np.all(D[np.arange(len(rows)), got] <= rdist + tol) and
                   np.all(np.abs(dist[rows].double().cpu().numpy() - D[np.arange(len(rows)), got])
                          <= tol))
-        out.append({"row": "kmeans assignment, m = 2^24 points, k = 16, n = 16 centroids (fused)",
+        out.append({"row": "kmeans assignment, m = 2^24 points (%s), k = 16, n = 16 centroids "
+                           "(fused)" % layout,
                     "dtype": str(dtype).replace("torch.", ""), "GBps": nb / t / 1e9,
                     "frac_of_8TBps": nb / t / 1e9 / PEAK_HBM_GBS, "ms": t * 1e3,
                     "unfused_ms": t_unf * 1e3, "speedup_vs_unfused": t_unf / t,

@@ -195,9 +195,10 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
 
 /* K-means assignment step.  The paper's Introduction names K-means as a
  * tall-and-skinny GEMM application (far fewer centroids than points).  For
- * points X (m-by-k, column-major: point i is row i, ldx >= max(1,m)) and
- * centroids Mu (k-by-n, column-major: centroid c is column c, ldm >= k)
- * it writes
+ * points X, m-by-k, either column-major (x_rowmajor 0: point i is row i,
+ * ldx >= max(1,m)) or row-major (x_rowmajor 1: point i at X + i*ldx, its k
+ * values contiguous, ldx >= k), and centroids Mu (k-by-n, column-major:
+ * centroid c is column c, ldm >= k) it writes
  *   labels[i] = the smallest c with the smallest ||x_i - mu_c||^2  (int32),
  *   dist[i]   = that squared distance (dtype; dist may be NULL).
  * The distance is evaluated as ||x||^2 - 2 x.mu_c + ||mu_c||^2 (clamped at
@@ -209,12 +210,15 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
  * Any k >= 1 and n >= 1.  dtype: TSM_F64 or TSM_F32 (X, Mu, dist).
  * Workspace: tsm2x_workspace_size(TSM_OP_KMEANS, m, k, n, dtype) bytes,
  * 256-byte aligned (ws NULL: the library's buffer).
- * Arguments: 1 m, 2 k, 3 n, 4 X, 5 ldx, 6 Mu, 7 ldm, 8 labels, 9 dist,
- * 10 dtype, 11 ws, 12 ws_bytes, 13 stream.  Errors: -i for argument i
- * (k and n must be >= 1); TSM_ERR_WORKSPACE for a small or misaligned ws. */
+ * Row-major X is loaded as one contiguous stream per wavefront tile and
+ * transposed through LDS; column-major X as k column streams.
+ * Arguments: 1 m, 2 k, 3 n, 4 X, 5 ldx, 6 x_rowmajor, 7 Mu, 8 ldm,
+ * 9 labels, 10 dist, 11 dtype, 12 ws, 13 ws_bytes, 14 stream.  Errors: -i
+ * for argument i (k and n must be >= 1); TSM_ERR_WORKSPACE for a small or
+ * misaligned ws. */
 int tsm_kmeans_assign(int64_t m, int64_t k, int64_t n, const void* X, int64_t ldx,
-                      const void* Mu, int64_t ldm, int32_t* labels, void* dist, int dtype,
-                      void* ws, size_t ws_bytes, void* stream);
+                      int x_rowmajor, const void* Mu, int64_t ldm, int32_t* labels, void* dist,
+                      int dtype, void* ws, size_t ws_bytes, void* stream);
 
 /* Low-precision storage form of A: from a float m-by-k matrix A (lda),
  * write hi = RNE(a) and, if lo != NULL, lo = RNE(a - hi) (a - hi is exact in

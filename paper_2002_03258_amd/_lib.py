@@ -55,8 +55,8 @@ def lib():
             L.tsm2x_split.argtypes = [i64, i64, vp, i64, vp, vp, i64, i32, vp]
             L.tsm2l_backward.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                                          i32, vp, sz, vp]
-            L.tsm_kmeans_assign.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, vp, i32, vp, sz,
-                                            vp]
+            L.tsm_kmeans_assign.argtypes = [i64, i64, i64, vp, i64, i32, vp, i64, vp, vp, i32, vp,
+                                            sz, vp]
             L.tsm2x_workspace_size.argtypes = [i32, i64, i64, i64, i32]
             L.tsm2x_workspace_size.restype = sz
             L.tsm2x_kernel_name.argtypes = [i32, i64, i64, i64, i32]

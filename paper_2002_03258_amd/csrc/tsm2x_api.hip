@@ -552,23 +552,25 @@ int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, voi
 }
 
 int tsm_kmeans_assign(int64_t m, int64_t k, int64_t n, const void* X, int64_t ldx,
-                      const void* Mu, int64_t ldm, int32_t* labels, void* dist, int dtype,
-                      void* ws, size_t ws_bytes, void* stream) {
+                      int x_rowmajor, const void* Mu, int64_t ldm, int32_t* labels, void* dist,
+                      int dtype, void* ws, size_t ws_bytes, void* stream) {
     if (m < 0) return -1;
     if (k < 1 || k > INT32_MAX) return -2;
     if (n < 1 || n > INT32_MAX) return -3;
     if (!X && m > 0) return -4;
-    if (ldx < (m > 1 ? m : 1)) return -5;
-    if (!Mu) return -6;
-    if (ldm < k) return -7;
-    if (!labels && m > 0) return -8;
-    if (!plain_dtype(dtype)) return -10;
+    if (x_rowmajor != 0 && x_rowmajor != 1) return -6;
+    if (ldx < (x_rowmajor ? k : (m > 1 ? m : 1))) return -5;
+    if (!Mu) return -7;
+    if (ldm < k) return -8;
+    if (!labels && m > 0) return -9;
+    if (!plain_dtype(dtype)) return -11;
     if (m == 0) return TSM_SUCCESS;
     void* w = nullptr;
     int rc = get_ws(align256((size_t)n * esize(dtype)), ws, ws_bytes, &w);
     if (rc) return rc;
     LaunchKM L{};
-    L.m = m; L.k = k; L.n = n; L.X = X; L.ldx = ldx; L.Mu = Mu; L.ldm = ldm; L.mu2 = w;
+    L.m = m; L.k = k; L.n = n; L.X = X; L.ldx = ldx; L.x_rowmajor = x_rowmajor; L.Mu = Mu;
+    L.ldm = ldm; L.mu2 = w;
     L.labels = labels; L.dist = dist; L.cus = cu_count();
     if (launch_kmeans_assign(L, dtype, (hipStream_t)stream)) {
         g_last_hip = "kmeans_assign_kernel: launch failed";

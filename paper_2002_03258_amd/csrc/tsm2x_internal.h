@@ -122,6 +122,7 @@ int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t
 struct LaunchKM {           // K-means assignment: points X (m x k), centroids Mu (k x n)
     int64_t m, k, n;
     const void* X; int64_t ldx;
+    int x_rowmajor;         // 0: point i is row i of a column-major X; 1: X + i*ldx
     const void* Mu; int64_t ldm;
     void* mu2;              // n values of the dtype (workspace): ||mu_c||^2
     int32_t* labels;        // m

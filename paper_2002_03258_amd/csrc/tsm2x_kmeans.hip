@@ -26,6 +26,12 @@
 //    NaN distance.
 // More than 16*NT16 centroids are taken in panels with a running minimum
 // (X is read once per panel).  A persistent grid walks the row tiles.
+//
+// Row-major X (ROWX: point i at X + i*ldx, its k values contiguous): a
+// wavefront's tile is then one contiguous range, loaded in consecutive
+// 16-byte pieces (1 KB per instruction) and written into a wavefront-private
+// LDS tile [feature][point], from which each lane reads back the same
+// registers as in the column-major case.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -49,6 +55,13 @@ __global__ void kmeans_norms_kernel(int k, int n, const T* __restrict__ Mu, int6
         s = fma_t(v, v, s);
     }
     mu2[c] = s;
+}
+
+// Orders this wavefront's LDS stores and loads around a hand-over between its
+// lanes (the compiler may otherwise reuse an earlier load in a lane that
+// stored nothing in between); no instruction at wavefront scope.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
 // (v, c) replaces (bv, bc) when smaller, or equal with a smaller index
@@ -87,7 +100,7 @@ __device__ __forceinline__ void scatter_step(T (&v)[2 * H], int (&c)[2 * H], T (
 // RES: one chunk and one panel cover Mu (k <= 4*KS, n <= 16*NT16); Mu and
 // its norms then stay in registers for the whole walk, and the next tile's
 // rows of X are requested before the current tile is reduced.
-template <typename T, int KS, int NT16, int RG, bool VEC, bool RES>
+template <typename T, int KS, int NT16, int RG, bool VEC, bool RES, bool ROWX>
 __global__ __launch_bounds__(256) void kmeans_assign_kernel(
     int64_t m, int k, int n, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Mu,
     int64_t ldm, const T* __restrict__ mu2, int32_t* __restrict__ labels,
@@ -101,11 +114,16 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
     constexpr int CW = 16 * NT16;       // centroids per panel
     constexpr int KC = 4 * KS;          // columns of X per chunk
     constexpr int NONE = 0x7fffffff;
+    constexpr int NP = RG * KS;         // 16-byte pieces per lane and tile (either layout)
+    constexpr int PPP = KC / RL;        // pieces per point of a chunk (ROWX)
+    constexpr int SROW = TR + RL;       // padded LDS row (ROWX)
+    __shared__ __align__(16) T lds[ROWX ? WPB : 1][ROWX ? KC : 1][ROWX ? SROW : 1];
     const T inf = __builtin_inf();
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
+    typedef T Raw[NP][RL];
 
     T yv[KS][NT16], cn[NT16][4];
     auto loadY = [&](int kc, int c0) {
@@ -126,21 +144,78 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
                 cn[t][r] = c < n ? mu2[c] : T(__builtin_nan(""));   // never a minimum
             }
     };
-    // rows RL*rl + q of each 16*RL-row block g of the tile, columns kc + 4 st + kk
-    auto loadX = [&](int64_t tile, int kc, T (&xv)[KS][RG][RL]) {
+    // fetch: this lane's pieces of a tile's chunk kc .. kc + KC - 1 of X.
+    // Column-major: piece st*RG + g is rows RL*rl + q of block g, column
+    // kc + 4 st + kk.  Row-major: piece i is the i-th of the lane's 16-byte
+    // pieces in the tile's (point, feature) order.
+    auto fetch = [&](int64_t tile, int kc, Raw& raw) {
         const int64_t row0 = tile * TR;
         const bool full = row0 + TR <= m;
+        if (!ROWX) {
 #pragma unroll
-        for (int st = 0; st < KS; ++st) {
-            const int j = kc + 4 * st + kk;
+            for (int st = 0; st < KS; ++st) {
+                const int j = kc + 4 * st + kk;
+#pragma unroll
+                for (int g = 0; g < RG; ++g) {
+                    const int64_t r = row0 + 16 * RL * g + RL * rl;
+                    if (j < k)
+                        load_run<T, RL, VEC>(X + r + (int64_t)j * ldx, m - r, full,
+                                             raw[st * RG + g]);
+                    else
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) raw[st * RG + g][q] = T(0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const int pc = lane + WAVE * i;
+                const int p = pc / PPP, f0 = kc + (pc % PPP) * RL;
+                const int64_t pt = row0 + p;
+                const T* src = X + pt * ldx + f0;
+                if (VEC && pt < m && f0 + RL <= k) {
+                    typedef typename VecOf<T, RL>::type V;
+                    const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(src));
+#pragma unroll
+                    for (int e = 0; e < RL; ++e) raw[i][e] = v[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < RL; ++e)
+                        raw[i][e] = (pt < m && f0 + e < k) ? src[e] : T(0);
+                }
+            }
+        }
+    };
+    // stage: the registers of the MFMA layout, xv[st][g][q] = X[row, kc + 4 st + kk]
+    // with row = row0 + 16*RL*g + RL*rl + q
+    auto stage = [&](const Raw& raw, T (&xv)[KS][RG][RL]) {
+        if constexpr (!ROWX) {
+#pragma unroll
+            for (int st = 0; st < KS; ++st)
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) xv[st][g][q] = raw[st * RG + g][q];
+            return;
+        } else {
+        T (*tl)[SROW] = lds[w];
+        wave_lds_fence();
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int pc = lane + WAVE * i;
+            const int p = pc / PPP, f = (pc % PPP) * RL;
+#pragma unroll
+            for (int e = 0; e < RL; ++e) tl[f + e][p] = raw[i][e];
+        }
+        wave_lds_fence();
+        typedef typename VecOf<T, RL>::type V;
+#pragma unroll
+        for (int st = 0; st < KS; ++st)
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
-                const int64_t r = row0 + 16 * RL * g + RL * rl;
-                if (j < k)
-                    load_run<T, RL, VEC>(X + r + (int64_t)j * ldx, m - r, full, xv[st][g]);
-                else
+                const V v = *reinterpret_cast<const V*>(&tl[4 * st + kk][16 * RL * g + RL * rl]);
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) xv[st][g][q] = T(0);
+                for (int q = 0; q < RL; ++q) xv[st][g][q] = v[q];
             }
         }
     };
@@ -227,12 +302,14 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
     if (RES) {
         loadY(0, 0);
         loadN(0);
-        T xv[KS][RG][RL];
-        if (tile < ntiles) loadX(tile, 0, xv);
+        Raw cur;
+        if (tile < ntiles) fetch(tile, 0, cur);
         for (; tile < ntiles; tile += stride) {
             const bool more = tile + stride < ntiles;
-            T xn[KS][RG][RL];
-            if (more) loadX(tile + stride, 0, xn);
+            Raw nxt;
+            if (more) fetch(tile + stride, 0, nxt);
+            T xv[KS][RG][RL];
+            stage(cur, xv);
             T bv[R], x2[R];
             int bc[R];
             init(bv, bc, x2);
@@ -248,11 +325,9 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
             finish(tile, bv, bc, x2);
             if (more) {
 #pragma unroll
-                for (int st = 0; st < KS; ++st)
+                for (int i = 0; i < NP; ++i)
 #pragma unroll
-                    for (int g = 0; g < RG; ++g)
-#pragma unroll
-                        for (int q = 0; q < RL; ++q) xv[st][g][q] = xn[st][g][q];
+                    for (int e = 0; e < RL; ++e) cur[i][e] = nxt[i][e];
             }
         }
         return;
@@ -272,8 +347,10 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
                     for (int t = 0; t < NT16; ++t) acc[g][q][t] = Acc{0, 0, 0, 0};
             for (int kc = 0; kc < k; kc += KC) {
                 loadY(kc, c0);
+                Raw raw;
+                fetch(tile, kc, raw);
                 T xv[KS][RG][RL];
-                loadX(tile, kc, xv);
+                stage(raw, xv);
                 accumulate(xv, acc, x2, c0 == 0);
             }
             panel_min(acc, c0, bv, bc);
@@ -290,11 +367,11 @@ static int km_occupancy(K kernel) {
     return nb;
 }
 
-template <typename T, int KS, int NT16, bool RES>
+template <typename T, int KS, int NT16, bool RES, bool ROWX>
 static int km_launch(const LaunchKM& L, hipStream_t st) {
     constexpr int RG = 2;
     constexpr int64_t TR = 16 * (16 / (int64_t)sizeof(T)) * RG;
-    static const int occ = km_occupancy(kmeans_assign_kernel<T, KS, NT16, RG, true, RES>);
+    static const int occ = km_occupancy(kmeans_assign_kernel<T, KS, NT16, RG, true, RES, ROWX>);
     const int64_t ntiles = (L.m + TR - 1) / TR;
     int64_t bx = (int64_t)L.cus * occ;
     const int64_t need = (ntiles + 3) / 4;
@@ -304,17 +381,18 @@ static int km_launch(const LaunchKM& L, hipStream_t st) {
     hipLaunchKernelGGL(kmeans_norms_kernel<T>, dim3(nb), dim3(256), 0, st, (int)L.k, (int)L.n,
                        (const T*)L.Mu, L.ldm, (T*)L.mu2);
     if (hipGetLastError() != hipSuccess) return 1;
-    // 16-byte runs of X; the outputs in runs of 4 * RL / 4 bytes and more
+    // 16-byte runs of X (row-major: the last piece of a point whose k values
+    // end inside it is read element-wise) and of the outputs
     const int es = (int)sizeof(T);
     const bool vec = ((uintptr_t)L.X & 15u) == 0 && (L.ldx * es) % 16 == 0 &&
                      ((uintptr_t)L.labels & 15u) == 0 && ((uintptr_t)L.dist & 15u) == 0;
     dim3 g((unsigned)bx), b(256);
     if (vec)
-        hipLaunchKernelGGL((kmeans_assign_kernel<T, KS, NT16, RG, true, RES>), g, b, 0, st, L.m,
+        hipLaunchKernelGGL((kmeans_assign_kernel<T, KS, NT16, RG, true, RES, ROWX>), g, b, 0, st, L.m,
                            (int)L.k, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Mu, L.ldm,
                            (const T*)L.mu2, L.labels, (T*)L.dist);
     else
-        hipLaunchKernelGGL((kmeans_assign_kernel<T, KS, NT16, RG, false, RES>), g, b, 0, st, L.m,
+        hipLaunchKernelGGL((kmeans_assign_kernel<T, KS, NT16, RG, false, RES, ROWX>), g, b, 0, st, L.m,
                            (int)L.k, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Mu, L.ldm,
                            (const T*)L.mu2, L.labels, (T*)L.dist);
     return hipGetLastError() != hipSuccess;
@@ -322,8 +400,12 @@ static int km_launch(const LaunchKM& L, hipStream_t st) {
 
 template <typename T, int KS, int NT16>
 static int km_res(const LaunchKM& L, hipStream_t st) {
-    if (L.k <= 4 * KS && L.n <= 16 * NT16) return km_launch<T, KS, NT16, true>(L, st);
-    return km_launch<T, KS, NT16, false>(L, st);
+    const bool res = L.k <= 4 * KS && L.n <= 16 * NT16;
+    if (L.x_rowmajor)
+        return res ? km_launch<T, KS, NT16, true, true>(L, st)
+                   : km_launch<T, KS, NT16, false, true>(L, st);
+    return res ? km_launch<T, KS, NT16, true, false>(L, st)
+               : km_launch<T, KS, NT16, false, false>(L, st);
 }
 
 template <typename T>

@@ -17,9 +17,9 @@ def assign(X: torch.Tensor, centroids: torch.Tensor, with_dist: bool = True,
            workspace: torch.Tensor | None = None):
     """Nearest centroid of every point.
 
-    X: m x k points (one per row; stored column-major, i.e. feature-major,
-    for the single pass; another layout is copied first).  centroids: n x k
-    (one per row).  F64 or F32.  Returns (labels, dist): int32 labels[i], the
+    X: m x k points (one per row), row-major (each point's coordinates
+    contiguous) or column-major (feature-major); another layout is copied
+    first.  centroids: n x k (one per row).  F64 or F32.  Returns (labels, dist): int32 labels[i], the
     smallest c with the smallest squared distance, and dist[i], that distance
     (None unless with_dist)."""
     _check_device(X, centroids)
@@ -29,13 +29,17 @@ def assign(X: torch.Tensor, centroids: torch.Tensor, with_dist: bool = True,
     n, k2 = centroids.shape
     if k2 != k:
         raise ValueError("centroids have %d coordinates, points %d" % (k2, k))
-    if not is_colmajor(X):
-        X = colmajor(X)
+    if X.stride(1) == 1 and X.stride(0) >= k:
+        rowmajor, ldx = 1, X.stride(0)
+    else:
+        if not is_colmajor(X):
+            X = colmajor(X)
+        rowmajor, ldx = 0, _ld(X)
     Mu = centroids.contiguous()              # n x k row-major = k x n column-major, ld k
     labels = torch.empty(m, dtype=torch.int32, device=X.device)
     dist = torch.empty(m, dtype=X.dtype, device=X.device) if with_dist else None
     ws, wsb = _ws(workspace)
-    _lib.call("tsm_kmeans_assign", m, k, n, X.data_ptr(), _ld(X), Mu.data_ptr(), k,
+    _lib.call("tsm_kmeans_assign", m, k, n, X.data_ptr(), ldx, rowmajor, Mu.data_ptr(), k,
               labels.data_ptr(), dist.data_ptr() if dist is not None else None, _DT[X.dtype],
               ws, wsb, _stream())
     return labels, dist

@@ -189,12 +189,15 @@ def test_tsm2r_plan_argument_checks(args, expect):
 def test_kmeans_argument_checks():
     L = _lib.lib()
     p = 4096                                    # never dereferenced: the checks come first
-    ok = [1000, 16, 8, p, 1000, p, 16, p, None, 0, None, 0, None]
-    for pos, bad in [(1, -1), (2, 0), (3, 0), (4, None), (5, 999), (6, None), (7, 15), (8, None),
-                     (10, 2)]:
+    ok = [1000, 16, 8, p, 1000, 0, p, 16, p, None, 0, None, 0, None]
+    for pos, bad in [(1, -1), (2, 0), (3, 0), (4, None), (5, 999), (6, 2), (7, None), (8, 15),
+                     (9, None), (11, 2)]:
         args = list(ok)
         args[pos - 1] = bad
         assert L.tsm_kmeans_assign(*args) == -pos, pos
+    rowm = list(ok)
+    rowm[5], rowm[4] = 1, 15                    # row-major: ldx >= k
+    assert L.tsm_kmeans_assign(*rowm) == -5
     empty = list(ok)
     empty[0] = 0
     assert L.tsm_kmeans_assign(*empty) == 0     # no points: nothing to do, no GPU call

@@ -39,6 +39,33 @@ def test_integer_points_bit_exact(dev, dtype, m, k, n):
     assert np.array_equal(dist.double().cpu().numpy(), rdist)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,k,n", SHAPES)
+@pytest.mark.parametrize("pad", [0, 3])
+def test_rowmajor_points_bit_exact(dev, dtype, m, k, n, pad):
+    """Row-major points (each point's k values contiguous, ld = k + pad): the
+    contiguous-stream path, staged through LDS."""
+    seed = 2450 + m % 997 + k + n
+    X, Mu, Xh, Muh = _data(seed, m, k, n, dtype, dev, dist="int", r=6)
+    store = torch.empty((m, k + pad), dtype=dtype, device=dev)
+    Xr = store[:, :k]
+    Xr.copy_(X)
+    assert Xr.stride() == (k + pad, 1)
+    lab, dist = kmeans.assign(Xr, Mu.t())
+    rlab, rdist = oracle.kmeans_assign(Xh, Muh)
+    assert np.array_equal(lab.cpu().numpy(), rlab)
+    assert np.array_equal(dist.double().cpu().numpy(), rdist)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("m,k,n", [(200003, 16, 16), (3001, 100, 40)])
+def test_rowmajor_random_points_within_rounding(dev, dtype, m, k, n):
+    seed = 2550 + m % 997 + k + n
+    X, Mu, Xh, Muh = _data(seed, m, k, n, dtype, dev)
+    lab, dist = kmeans.assign(X.contiguous(), Mu.t())
+    _check_valid(lab, dist, Xh, Muh, torch.finfo(dtype).eps / 2)
+
+
 def _check_valid(lab, dist, Xh, Muh, u):
     """Each label's oracle distance is within the rounding bound of the
     minimum, and the returned distance within that bound of the label's."""
@@ -101,8 +128,11 @@ def test_misaligned_and_rowmajor_points(dev, dtype):
     store = torch.empty((k, m + 3), dtype=dtype, device=dev)
     Xs = store[:, 1:m + 1].t()                 # column-major, base not 16-byte aligned
     Xs.copy_(X)
+    rstore = torch.empty((m, k + 1), dtype=dtype, device=dev)
+    Xrs = rstore[:, 1:]                        # row-major, base not 16-byte aligned
+    Xrs.copy_(X)
     rlab, rdist = oracle.kmeans_assign(Xh, Muh)
-    for Xv in (Xs, X.contiguous()):            # the second is row-major: copied first
+    for Xv in (Xs, X.contiguous(), Xrs):
         lab, dist = kmeans.assign(Xv, Mu.t())
         assert np.array_equal(lab.cpu().numpy(), rlab)
         assert np.array_equal(dist.double().cpu().numpy(), rdist)

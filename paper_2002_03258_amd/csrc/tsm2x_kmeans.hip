@@ -73,33 +73,58 @@ __device__ __forceinline__ void take_min(T v, int c, T& bv, int& bc) {
     }
 }
 
-// One step of the reduce-scatter over the lanes l and l ^ off: of the 2H
-// rows (v, c, x) each lane holds, the lane with `upper` set keeps rows
-// H .. 2H-1 and the other rows 0 .. H-1; each sends the half it gives up and
-// combines the half it keeps with its partner's.  Afterwards rows 0 .. H-1
-// of the arrays hold the kept half.
-template <typename T, int H>
-__device__ __forceinline__ void scatter_step(T (&v)[2 * H], int (&c)[2 * H], T (&x)[2 * H],
-                                             bool upper, int off) {
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        const T sv = upper ? v[i] : v[H + i], kv = upper ? v[H + i] : v[i];
-        const int sc = upper ? c[i] : c[H + i], kc = upper ? c[H + i] : c[i];
-        const T sx = upper ? x[i] : x[H + i], kx = upper ? x[H + i] : x[i];
-        const T ov = __shfl_xor(sv, off);
-        const int oc = __shfl_xor(sc, off);
-        const T ox = __shfl_xor(sx, off);
-        v[i] = kv;
-        c[i] = kc;
-        take_min(ov, oc, v[i], c[i]);
-        // both lanes add the two halves in the same order: lower lane's first
-        x[i] = upper ? ox + kx : kx + ox;
+// Exchange between partner lanes by the gfx950 lane-swap instructions.
+// S32: v_permlane32_swap, after which x = [x lanes 0-31, y lanes 0-31] and
+// y = [x lanes 32-63, y lanes 32-63] (partner l ^ 32).  Otherwise
+// v_permlane16_swap, which trades the odd 16-lane rows of x with the even
+// rows of y (partner l ^ 16).
+template <bool S32>
+__device__ __forceinline__ void swap_u32(uint32_t& x, uint32_t& y) {
+    if (S32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    }
+}
+template <bool S32, typename V>
+__device__ __forceinline__ void swap_lanes(V& x, V& y) {
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(V) == 4) {
+        uint32_t a = __builtin_bit_cast(uint32_t, x), b = __builtin_bit_cast(uint32_t, y);
+        swap_u32<S32>(a, b);
+        x = __builtin_bit_cast(V, a);
+        y = __builtin_bit_cast(V, b);
+    } else {
+        uint2 a = __builtin_bit_cast(uint2, x), b = __builtin_bit_cast(uint2, y);
+        swap_u32<S32>(a.x, b.x);
+        swap_u32<S32>(a.y, b.y);
+        x = __builtin_bit_cast(V, a);
+        y = __builtin_bit_cast(V, b);
     }
 }
 
-// RES: one chunk and one panel cover Mu (k <= 4*KS, n <= 16*NT16); Mu and
-// its norms then stay in registers for the whole walk, and the next tile's
-// rows of X are requested before the current tile is reduced.
+// One step of the reduce-scatter over partner lanes (l ^ 32 for S32, else
+// l ^ 16): of the 2H rows (v, c, x) each lane holds, the lower lane of a pair
+// keeps rows 0 .. H-1 and the upper lane rows H .. 2H-1.  After swapping
+// rows i and H + i, both values of the kept row are in each lane (the lower
+// lane's first); they are combined into row i, so rows 0 .. H-1 of the
+// arrays hold the kept half.
+template <typename T, int H, bool S32>
+__device__ __forceinline__ void scatter_step(T (&v)[2 * H], int (&c)[2 * H], T (&x)[2 * H]) {
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        swap_lanes<S32>(v[i], v[H + i]);
+        swap_lanes<S32>(c[i], c[H + i]);
+        swap_lanes<S32>(x[i], x[H + i]);
+        take_min(v[H + i], c[H + i], v[i], c[i]);
+        x[i] = x[i] + x[H + i];
+    }
+}
+
 template <typename T, int KS, int NT16, int RG, bool VEC, bool RES, bool ROWX>
 __global__ __launch_bounds__(256) void kmeans_assign_kernel(
     int64_t m, int k, int n, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Mu,
@@ -263,7 +288,7 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
     auto finish = [&](int64_t tile, T (&bv)[R], int (&bc)[R], T (&x2)[R]) {
         const int64_t row0 = tile * TR;
         const bool full = row0 + TR <= m;
-        scatter_step<T, R / 2>(bv, bc, x2, (kk >> 1) != 0, 32);
+        scatter_step<T, R / 2, true>(bv, bc, x2);
         T v2[R / 2], x22[R / 2];
         int c2[R / 2];
 #pragma unroll
@@ -272,7 +297,7 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
             c2[i] = bc[i];
             x22[i] = x2[i];
         }
-        scatter_step<T, R / 4>(v2, c2, x22, (kk & 1) != 0, 16);
+        scatter_step<T, R / 4, false>(v2, c2, x22);
         constexpr int NQ = R / 4;
         const int64_t r = row0 + 16 * RL * (kk >> 1) + RL * rl + (kk & 1) * NQ;
         int32_t lab[NQ];

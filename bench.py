@@ -260,8 +260,9 @@ def traffic_for(kernel: str, launches):
 
 
 def timed(fn, reps=5, warmup=1, flush=None):
-    """Mean seconds of fn() over `reps` runs, each bracketed by HIP events;
-    `flush` (untimed) runs before each rep to evict the 256 MB MALL."""
+    """Median seconds of fn() over `reps` runs, each bracketed by HIP events
+    (the median keeps one disturbed run from moving a row); `flush`
+    (untimed) runs before each rep to evict the 256 MB MALL."""
     for _ in range(warmup):
         fn()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -274,7 +275,8 @@ def timed(fn, reps=5, warmup=1, flush=None):
         fn()
         e1.record()
     torch.cuda.synchronize()
-    return sum(e0.elapsed_time(e1) for e0, e1 in evs) / reps / 1e3
+    ts = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    return ts[len(ts) // 2] / 1e3
 
 
 def rows_tsm2l(dev):

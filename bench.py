@@ -556,6 +556,10 @@ def main():
     ap.add_argument("--profile-kernel", default=None, metavar="DTYPE:M:N",
                     help="only launch TSM2R on one workload of the grid 5 times "
                          "(for rocprofv3 counters), e.g. f64:30720:16")
+    ap.add_argument("--profile-op", default=None, metavar="OP:DTYPE:M:K[:LAYOUT]",
+                    help="only launch one TSM2L (tsm2l, B k x k) or K-means assignment "
+                         "(kmeans, k = n, LAYOUT col or row) product 5 times, for rocprofv3 "
+                         "counters, e.g. tsm2l:f64:16777216:16 or kmeans:f32:16777216:16:row")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a 1 GiB device copy 5 times (counter calibration)")
     ap.add_argument("--tune", action="store_true",
@@ -577,6 +581,27 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print("copied 5 x %d bytes" % src.numel(), flush=True)
+        return
+    if args.profile_op:
+        f = args.profile_op.split(":")
+        op, dtype, m, k = f[0], torch.float64 if f[1] == "f64" else torch.float32, int(f[2]), int(f[3])
+        seed = si.config_seed(8)
+        X = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
+        B = si.matrix(seed, si.STREAM_B, k, k, dtype=dtype, device=dev)
+        if op == "tsm2l":
+            C = tsm.empty_colmajor(m, k, dtype, dev)
+            run = lambda: tsm.tsm2l(X, B, out=C)
+        elif op == "kmeans":
+            from paper_2002_03258_amd import kmeans
+            if len(f) > 4 and f[4] == "row":
+                X = X.contiguous()
+            run = lambda: kmeans.assign(X, B.t())
+        else:
+            raise SystemExit("--profile-op: tsm2l or kmeans")
+        for _ in range(5):
+            run()
+        torch.cuda.synchronize()
+        print("launched %s 5 times" % args.profile_op, flush=True)
         return
     if args.profile_kernel:
         dts, ms, ns = args.profile_kernel.split(":")

@@ -18,6 +18,9 @@ unblocked, sequential sums) with numpy marshalling:
   compute-bound regimes (Design of TSM2R, "Determine compute-bound or
   memory-bound"): t2 = PeakPerf / PeakBand * bytes_per_element.
 - :func:`normwise_error` -- ||C - C_ref||_F / ||C_ref||_F.
+- :func:`matmul_dot2` -- the same product with every sum taken by Dot2
+  (Ogita, Rump, Oishi 2005), as accurate as a sum in twice double precision:
+  it measures the rounding error of :func:`matmul` itself at full size.
 - :func:`kmeans_assign` -- the K-means assignment step named in the paper's
   Introduction: nearest centroid by squared Euclidean distance, from its
   definition.
@@ -80,6 +83,9 @@ def _load():
             lib.tsm_oracle_split.argtypes = [ctypes.c_void_p, i64, ctypes.c_int,
                                              ctypes.c_void_p, ctypes.c_void_p]
             lib.tsm_oracle_split.restype = None
+            lib.tsm_oracle_matmul_dot2.argtypes = [i64, i64, i64, dp, i64, i64,
+                                                   dp, i64, i64, dp, i64, i64]
+            lib.tsm_oracle_matmul_dot2.restype = None
             lib.tsm_oracle_kmeans_assign.argtypes = [i64, i64, i64, dp, i64, i64, dp, i64, i64,
                                                      ctypes.c_void_p, ctypes.c_void_p]
             lib.tsm_oracle_kmeans_assign.restype = None
@@ -121,6 +127,24 @@ def matmul(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     crs, ccs = _strides(C)
     lib.tsm_oracle_matmul(m, k, n, _dptr(A), ars, acs, _dptr(B), brs, bcs,
                           _dptr(C), crs, ccs)
+    return C
+
+
+def matmul_dot2(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """C = A*B with each entry's sum by Dot2 (error-free products and
+    additions, errors summed apart): accurate to about u|C| + (k u)^2 |A||B|."""
+    lib = _load()
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2, (A.shape, B.shape)
+    C = np.empty((m, n), dtype=np.float64, order="F")
+    ars, acs = _strides(A)
+    brs, bcs = _strides(B)
+    crs, ccs = _strides(C)
+    lib.tsm_oracle_matmul_dot2(m, k, n, _dptr(A), ars, acs, _dptr(B), brs, bcs,
+                               _dptr(C), crs, ccs)
     return C
 
 

@@ -25,6 +25,13 @@
  *  - tsm_oracle_split: the storage form of A used by the low-precision path:
  *    hi = round(a), lo = round(a - hi).  a - hi is formed in double, where it
  *    is exact.
+ *  - tsm_oracle_matmul_dot2: the same product with each sum taken by
+ *    Dot2 (Ogita, Rump, Oishi, "Accurate sum and dot product", SIAM J. Sci.
+ *    Comput. 26(6), 2005): every product is split exactly into its rounded
+ *    value and error (TwoProduct, by fma), every addition likewise (TwoSum),
+ *    and the errors are summed apart, so the result is as accurate as if the
+ *    sum were taken in twice double precision and then rounded.  It measures
+ *    the rounding error of the sequential sums at full size.
  *  - tsm_oracle_kmeans_assign: the assignment step of K-means, the
  *    application the paper's Introduction names as a tall-and-skinny GEMM
  *    user (many points, few centroids): each point goes to the centroid at
@@ -52,6 +59,41 @@ void tsm_oracle_matmul(int64_t m, int64_t k, int64_t n,
             for (int64_t j = 0; j < k; ++j)
                 s += A[i * a_rs + j * a_cs] * B[j * b_rs + p * b_cs];
             C[i * c_rs + p * c_cs] = s;
+        }
+    }
+}
+
+/* TwoSum (Knuth): s + e == a + b exactly, s = fl(a + b). */
+static void two_sum(double a, double b, double* s, double* e)
+{
+    const double x = a + b;
+    const double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+/* C = A*B with each C[i,p] by Dot2: sum of the TwoProduct/TwoSum errors
+ * carried beside the running sum, added once at the end. */
+void tsm_oracle_matmul_dot2(int64_t m, int64_t k, int64_t n,
+                            const double* A, int64_t a_rs, int64_t a_cs,
+                            const double* B, int64_t b_rs, int64_t b_cs,
+                            double* C, int64_t c_rs, int64_t c_cs)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < m; ++i) {
+        for (int64_t p = 0; p < n; ++p) {
+            double s = 0.0, c = 0.0;
+            for (int64_t j = 0; j < k; ++j) {
+                const double x = A[i * a_rs + j * a_cs], y = B[j * b_rs + p * b_cs];
+                const double h = x * y;
+                const double r = fma(x, y, -h);         /* x*y == h + r exactly */
+                double t, q;
+                two_sum(s, h, &t, &q);
+                s = t;
+                c += q + r;
+            }
+            C[i * c_rs + p * c_cs] = s + c;
         }
     }
 }

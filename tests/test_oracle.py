@@ -359,3 +359,58 @@ def test_kmeans_oracle_nan_handling():
     lab, dist = oracle.kmeans_assign(X, Mu)
     assert lab.tolist() == [1, 0, 2]                   # row 1: every distance NaN -> label 0
     assert dist[0] == 2.0 and np.isnan(dist[1]) and dist[2] == 2.0
+
+
+# ------------------------------------------------------------ Dot2 oracle
+def _exact_dot(x, y):
+    from fractions import Fraction
+    return sum((Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y)), Fraction(0))
+
+
+def _illcond_vectors(n, rng):
+    """Dot products with heavy cancellation: large terms that cancel in pairs
+    around a small true value (exponents spread over 2^0 .. 2^60)."""
+    x = rng.standard_normal(n) * 2.0 ** rng.integers(0, 60, n)
+    y = rng.standard_normal(n)
+    half = n // 2
+    x[half:2 * half] = -x[:half]
+    y[half:2 * half] = y[:half] * (1 + 2.0 ** -40 * rng.standard_normal(half))
+    return x, y
+
+
+@pytest.mark.parametrize("n,seed", [(10, 1), (64, 2), (200, 3), (501, 4)])
+def test_dot2_within_its_error_bound_on_cancelling_sums(n, seed):
+    rng = np.random.default_rng(seed)
+    x, y = _illcond_vectors(n, rng)
+    exact = float(_exact_dot(x, y))
+    got = oracle.matmul_dot2(x[None, :], y[:, None])[0, 0]
+    plain = oracle.matmul(x[None, :], y[:, None])[0, 0]
+    u = 2.0 ** -53
+    gam = n * u / (1 - n * u)
+    bound = u * abs(exact) + gam ** 2 * float(np.sum(np.abs(x * y)))
+    assert abs(got - exact) <= bound
+    # the sequential sum is far off on these: the check has teeth
+    if n >= 64:
+        assert abs(plain - exact) > 1e3 * max(abs(got - exact), bound)
+
+
+def test_dot2_equals_plain_on_exact_sums():
+    rng = np.random.default_rng(5)
+    A = rng.integers(-8, 9, (37, 300)).astype(np.float64)
+    B = rng.integers(-8, 9, (300, 5)).astype(np.float64)
+    assert np.array_equal(oracle.matmul_dot2(A, B), oracle.matmul(A, B))
+    assert np.array_equal(oracle.matmul_dot2(A, B), A @ B)
+
+
+def test_plain_oracle_error_at_full_size_is_far_below_the_fp64_bar():
+    # rows of the largest TSM2R product (k = 30720, uniform[-1, 1)): the
+    # sequential oracle differs from Dot2 by about 6e-15 normwise (u sqrt(k/2)
+    # is 1.4e-14), well below the FP64 tolerance of the parity tests
+    import seeded_inputs as si
+    m = k = 30720
+    rows = [0, 12345, m - 1]
+    Ar = si.matrix_rows(7, si.STREAM_A, m, k, rows, dtype=torch.float64).numpy()
+    B = si.matrix(8, si.STREAM_B, k, 16, dtype=torch.float64).numpy()
+    plain = oracle.matmul(Ar, B)
+    dd = oracle.matmul_dot2(Ar, B)
+    assert oracle.normwise_error(plain, dd) < 1e-14

@@ -87,3 +87,23 @@ def test_kmeans_beyond_2_31_points(dev, big):
     res = torch.arange(M, device=dev, dtype=torch.int64) % 7
     assert torch.equal(lab, torch.tensor(lut_l, dtype=torch.int32, device=dev)[res])
     assert torch.equal(dist, torch.tensor(lut_d, dtype=torch.float32, device=dev)[res])
+
+
+def test_lowp_beyond_2_31_rows(dev, big):
+    """The bf16 storage form (small integers are exact in bf16; lo = 0):
+    split, TSM2L on the planes, and dB over all M rows."""
+    k, n = 2, 3
+    A = tsm.empty_colmajor(M, k, torch.float32, dev)
+    for j in range(k):
+        A[:, j] = _col(j, dev)
+    S = tsm.split(A, "bf16", lo=True)
+    B = torch.tensor([[1.0, 2.0, -1.0], [3.0, -1.0, 2.0]], device=dev)
+    C = tsm.tsm2l(S, B)
+    for p in range(n):
+        assert torch.equal(C[:, p], A[:, 0] * B[0, p] + A[:, 1] * B[1, p]), p
+    del C
+    dC = torch.ones((n, M), device=dev).t()
+    dB = tsm.grad_b(S, dC)
+    for j in range(k):
+        assert dB[j].tolist() == [float(_sum_col(j))] * n
+    del A, S, dC, dB

@@ -261,12 +261,14 @@ def traffic_for(kernel: str, launches):
     return tot / len(launches) if launches else None
 
 
-def timed(fn, reps=5, warmup=1, flush=None):
+def timed(fn, reps=5, warmup=1, flush=None, warm_seconds=0.05):
     """Median seconds of fn() over `reps` runs, each bracketed by HIP events
     (the median keeps one disturbed run from moving a row); `flush`
-    (untimed) runs before each rep to evict the 256 MB MALL."""
-    for _ in range(warmup):
-        fn()
+    (untimed) runs before each rep to evict the 256 MB MALL.  The warm-up is
+    at least `warmup` calls and `warm_seconds` of GPU time: the GPU takes
+    some tens of milliseconds of sustained load to reach steady clocks."""
+    from paper_2002_03258_amd.tune import _warm
+    _warm(fn, warm_seconds, max(1, warmup))
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(reps)]
     torch.cuda.synchronize()

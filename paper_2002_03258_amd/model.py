@@ -45,12 +45,12 @@ class Device:
     stream_gbs: float = 7090.0         # measured: 16-byte streaming read of one large buffer
     # fitted by `fit` to the measured rates of every candidate plan of the 24
     # square TSM2R products (m = k in {10240, 20480, 30720}, n in {2, 4, 8, 16},
-    # FP64 and FP32; 789 plans):
-    latency_us: float = 1.52           # loaded memory latency
-    eta: float = 0.952                 # fraction of the streaming rate reached at full concurrency
+    # FP64 and FP32; 788 plans, timed after a warm-up in interleaved rounds):
+    latency_us: float = 1.53           # loaded memory latency
+    eta: float = 0.954                 # fraction of the streaming rate reached at full concurrency
     balance_exp: float = 0.41          # weight of the per-CU balance term
-    t0_us: float = 16.5                # fixed cost per product (launches, ramp-up, drain)
-    round_us: float = 7.8              # cost of each round of resident workgroups
+    t0_us: float = 17.4                # fixed cost per product (launches, ramp-up, drain)
+    round_us: float = 7.5              # cost of each round of resident workgroups
 
 
 MI355X = Device()

@@ -11,7 +11,10 @@ by measurement on the caller's own operands:
    both tile heights), asking the library what each would launch;
 2. rank them with the performance model (`model.predict_tsm2r`);
 3. time the best few, and the planner's own choice, with HIP events on the
-   current stream;
+   current stream: after a warm-up of sustained calls (the GPU takes some
+   tens of milliseconds of load to reach its steady clocks, and whatever is
+   timed first otherwise looks slow), in interleaved rounds, taking each
+   plan's median;
 4. pin the fastest for that shape (`pin_tsm2r`), so later calls use it.
 
 Every candidate computes the same product (up to the order of the k sums), so
@@ -56,6 +59,22 @@ def candidates(m: int, k: int, n: int, dtype: int, max_rounds: int = 3,
     return out
 
 
+def _warm(fn, seconds: float = 0.1, min_calls: int = 3) -> None:
+    """Run fn() until `seconds` of GPU time have passed (and min_calls)."""
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    calls = 0
+    while True:
+        fn()
+        calls += 1
+        e1 = torch.cuda.Event(enable_timing=True)
+        e1.record(st)
+        e1.synchronize()
+        if calls >= min_calls and e0.elapsed_time(e1) >= seconds * 1e3:
+            return
+
+
 def _time(fn, reps: int) -> float:
     """Median seconds of `reps` runs of fn() on the current stream."""
     st = torch.cuda.current_stream()
@@ -71,8 +90,8 @@ def _time(fn, reps: int) -> float:
     return ts[len(ts) // 2]
 
 
-def autotune_tsm2r(A: torch.Tensor, B: torch.Tensor, top: int = 6, reps: int = 5,
-                   warmup: int = 1, pin: bool = True) -> dict:
+def autotune_tsm2r(A: torch.Tensor, B: torch.Tensor, top: int = 6, reps: int = 3,
+                   rounds: int = 3, warm_seconds: float = 0.1, pin: bool = True) -> dict:
     """Tune the TSM2R plan of C = A*B (A column-major F64/F32 m x k on the
     GPU, B k x n, n <= 32) on these operands.
 
@@ -100,18 +119,24 @@ def autotune_tsm2r(A: torch.Tensor, B: torch.Tensor, top: int = 6, reps: int = 5
                            if p["tall"] == default["tall"] and p["slices"] == default["slices"]))
     C = empty_colmajor(m, n, A.dtype, A.device)
     alg = model.algorithmic_bytes(m, k, n, es)
+    unpin_tsm2r(m, k, n, dt)
+    _warm(lambda: tsm2r(A, B, out=C), warm_seconds)
+    times = [[] for _ in chosen]
+    for _ in range(rounds):
+        for i, p in enumerate(chosen):
+            pin_tsm2r(m, k, n, dt, p["slices"], p["tall"])
+            tsm2r(A, B, out=C)                   # first call of this plan untimed
+            times[i].append(_time(lambda: tsm2r(A, B, out=C), reps))
     report = []
     for p in ranked:
         entry = {key: p[key] for key in ("tall", "slices", "tiles", "tile_rows", "occupancy",
                                           "workgroups", "kernel")}
         entry["pred_gbs"] = p["pred"].gbs
-        if any(p is c for c in chosen):
-            pin_tsm2r(m, k, n, dt, p["slices"], p["tall"])
-            for _ in range(warmup):
-                tsm2r(A, B, out=C)
-            t = _time(lambda: tsm2r(A, B, out=C), reps)
-            entry["seconds"] = t
-            entry["gbs"] = alg / t / 1e9
+        for i, c in enumerate(chosen):
+            if p is c:
+                ts = sorted(times[i])
+                entry["seconds"] = ts[len(ts) // 2]
+                entry["gbs"] = alg / entry["seconds"] / 1e9
         report.append(entry)
     timed = [e for e in report if "gbs" in e]
     best = max(timed, key=lambda e: e["gbs"])

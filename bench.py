@@ -573,8 +573,9 @@ def main():
                          "performance model's prediction, and print the table")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
-              "(the kernels run on one device's share of the work)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: --gpus %d is not supported (the kernels run on one "
+              "device's share of the work; how the path shards is described with the design)"
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
 

@@ -194,3 +194,42 @@ def test_tsmttsm_shape_check(dev):
     A = torch.zeros(10, 3, dtype=torch.float64, device=dev)
     with pytest.raises(ValueError):
         tsm.tsmttsm(A, torch.zeros(11, 2, dtype=torch.float64, device=dev))
+
+
+def test_workspace_errors_leave_outputs_untouched(dev):
+    """A caller workspace that is too small or not 256-byte aligned is refused
+    (TSM_ERR_WORKSPACE = 3) before anything is launched."""
+    from paper_2002_03258_amd import _lib
+    L = _lib.lib()
+    m, k, n = 2000, 8000, 16
+    A = dev_matrix(81, si.STREAM_A, m, k, torch.float64, dev)
+    B = dev_matrix(81, si.STREAM_B, k, n, torch.float64, dev)
+    # the query covers a transposed B too; the split partials alone are
+    # megabytes here (S > 1), so 256 bytes is too small for any form
+    assert tsm.tsm2r_plan(m, k, n, tsm.F64)["slices"] > 1
+    need = tsm.workspace_size(tsm.OP_TSM2R, m, k, n, tsm.F64)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    for ptr, nbytes in ((ws.data_ptr(), 256), (ws.data_ptr() + 16, need)):
+        C = torch.full((n, m), float("nan"), dtype=torch.float64, device=dev).t()
+        rc = L.tsm2r_ex(0, 0, m, k, n, A.data_ptr(), m, B.data_ptr(), k, 0.0, C.data_ptr(), m,
+                        tsm.F64, ptr, nbytes, stream)
+        assert rc == 3
+        torch.cuda.synchronize()
+        assert torch.isnan(C).all()
+    # dB and the K-means assignment likewise
+    dC = dev_matrix(82, si.STREAM_DC, 100000, 8, torch.float64, dev)
+    Ag = dev_matrix(82, si.STREAM_A, 100000, 3000, torch.float64, dev)
+    gneed = tsm.workspace_size(tsm.OP_GRAD_B, 100000, 3000, 8, tsm.F64)
+    dB = torch.full((8, 3000), float("nan"), dtype=torch.float64, device=dev).t()
+    if gneed > 0:
+        rc = L.tsm_grad_b(100000, 3000, 8, Ag.data_ptr(), 100000, dC.data_ptr(), 100000,
+                          dB.data_ptr(), 3000, tsm.F64, ws.data_ptr() + 16, gneed, stream)
+        assert rc == 3
+    X = dev_matrix(83, si.STREAM_A, 1000, 16, torch.float64, dev)
+    lab = torch.full((1000,), -7, dtype=torch.int32, device=dev)
+    rc = L.tsm_kmeans_assign(1000, 16, 16, X.data_ptr(), 1000, 0, B.data_ptr(), k,
+                             lab.data_ptr(), None, tsm.F64, ws.data_ptr() + 16, 4096, stream)
+    assert rc == 3
+    torch.cuda.synchronize()
+    assert torch.isnan(dB).all() and (lab == -7).all()

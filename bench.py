@@ -113,6 +113,20 @@ def run_step(calls, evs=None):
             evs[i][1].record()
 
 
+def gpu_clocks():
+    """The GPU's current clocks as rocm-smi reports them (clocks are not
+    pinned for the measurement), or None where rocm-smi is unavailable."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=20)
+        cards = json.loads(r.stdout)
+        card = cards[sorted(cards)[0]]
+        return {key: val for key, val in card.items() if "clk" in key.lower()}
+    except Exception:
+        return None
+
+
 def _plan_prediction(c):
     p = tsm.tsm2r_plan(c["m"], c["k"], c["n"], tsm.F64 if c["dtype"] == torch.float64 else tsm.F32)
     return perf_model.predict_tsm2r(c["m"], c["k"], c["n"], es(c["dtype"]), p["slices"],
@@ -690,6 +704,7 @@ def main():
         "roofline": roofline,
     }
     line["model"] = model_summary(calls, evs, step_bytes, value)
+    line["config"]["gpu_clocks_after_timing"] = gpu_clocks()
     if tuned is not None:
         line["config"]["tuned_plans"] = tuned
     if not args.no_check:

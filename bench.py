@@ -89,12 +89,17 @@ def src_hash() -> str:
 
 
 def make_r_inputs(dev):
+    """The 24 products of the TSM2R grid.  Consecutive products never share
+    A (the order is n, then m, per type), so no product finds part of its A
+    left in the 256 MB MALL by the one before."""
     seed = si.config_seed(1)
+    mats = {(dtype, m): si.matrix(seed, si.STREAM_A, m, m, dtype=dtype, device=dev)
+            for dtype in R_DTYPES for m in R_SIZES}
     calls = []
     for dtype in R_DTYPES:
-        for m in R_SIZES:
-            A = si.matrix(seed, si.STREAM_A, m, m, dtype=dtype, device=dev)
-            for n in R_NS:
+        for n in R_NS:
+            for m in R_SIZES:
+                A = mats[(dtype, m)]
                 B = si.matrix(seed + n, si.STREAM_B, m, n, dtype=dtype, device=dev)
                 C = tsm.empty_colmajor(m, n, dtype, dev)
                 calls.append(dict(dtype=dtype, m=m, k=m, n=n, A=A, B=B, C=C, seed=seed,

@@ -163,7 +163,7 @@ def model_report(calls):
                                                  "pred GB/s", "meas GB/s", "pred/meas"))
     samples = []
     for c in calls:
-        r = tune.autotune_tsm2r(c["A"], c["B"], top=1000, reps=3, pin=False)
+        r = tune.autotune_tsm2r(c["A"], c["B"], top=1000, pin=False)
         d = r["default"]
         for e in sorted(r["report"], key=lambda e: (e["tall"], e["slices"])):
             pr = perf_model.predict_tsm2r(c["m"], c["k"], c["n"], es(c["dtype"]), e["slices"],
@@ -653,7 +653,7 @@ def main():
     if args.tune:
         tuned = {}
         for c in calls:
-            r = tune.autotune_tsm2r(c["A"], c["B"], top=4, reps=3)
+            r = tune.autotune_tsm2r(c["A"], c["B"], top=4)
             tuned[c["workload"]] = {"slices": r["best"]["slices"], "tall": r["best"]["tall"],
                                     "gain": r["best"]["gbs"] / r["default"]["gbs"]}
             c["kernel"] = r["best"]["kernel"]

@@ -45,12 +45,12 @@ class Device:
     stream_gbs: float = 7090.0         # measured: 16-byte streaming read of one large buffer
     # fitted by `fit` to the measured rates of every candidate plan of the 24
     # square TSM2R products (m = k in {10240, 20480, 30720}, n in {2, 4, 8, 16},
-    # FP64 and FP32; 788 plans, timed after a warm-up in interleaved rounds):
+    # FP64 and FP32; 788 plans, timed after a warm-up in shuffled rounds):
     latency_us: float = 1.53           # loaded memory latency
-    eta: float = 0.954                 # fraction of the streaming rate reached at full concurrency
-    balance_exp: float = 0.41          # weight of the per-CU balance term
-    t0_us: float = 17.4                # fixed cost per product (launches, ramp-up, drain)
-    round_us: float = 7.5              # cost of each round of resident workgroups
+    eta: float = 0.955                 # fraction of the streaming rate reached at full concurrency
+    balance_exp: float = 0.43          # weight of the per-CU balance term
+    t0_us: float = 7.7                 # fixed cost per product (launches, ramp-up, drain)
+    round_us: float = 8.2              # cost of each round of resident workgroups
 
 
 MI355X = Device()

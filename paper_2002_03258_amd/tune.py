@@ -11,16 +11,21 @@ by measurement on the caller's own operands:
    both tile heights), asking the library what each would launch;
 2. rank them with the performance model (`model.predict_tsm2r`);
 3. time the best few, and the planner's own choice, with HIP events on the
-   current stream: after a warm-up of sustained calls (the GPU takes some
-   tens of milliseconds of load to reach its steady clocks, and whatever is
-   timed first otherwise looks slow), in interleaved rounds, taking each
-   plan's median;
+   current stream.  Every candidate runs once first (so the library's
+   grow-only workspace reaches its final size), then the GPU is warmed up
+   (it takes some tens of milliseconds of load to reach its steady clocks,
+   and whatever is timed first otherwise looks slow); the candidates are
+   then timed in rounds, each in its own (seeded) random order so that no
+   plan always follows the same one, each sample a block of back-to-back
+   calls, and each plan's median is kept;
 4. pin the fastest for that shape (`pin_tsm2r`), so later calls use it.
 
 Every candidate computes the same product (up to the order of the k sums), so
 tuning never changes results beyond rounding.
 """
 from __future__ import annotations
+
+import random
 
 import torch
 
@@ -75,6 +80,19 @@ def _warm(fn, seconds: float = 0.1, min_calls: int = 3) -> None:
             return
 
 
+def _time_block(fn, reps: int) -> float:
+    """Seconds per call of `reps` back-to-back runs of fn() on the current
+    stream, timed as one block."""
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
 def _time(fn, reps: int) -> float:
     """Median seconds of `reps` runs of fn() on the current stream."""
     st = torch.cuda.current_stream()
@@ -90,8 +108,8 @@ def _time(fn, reps: int) -> float:
     return ts[len(ts) // 2]
 
 
-def autotune_tsm2r(A: torch.Tensor, B: torch.Tensor, top: int = 6, reps: int = 3,
-                   rounds: int = 3, warm_seconds: float = 0.1, pin: bool = True) -> dict:
+def autotune_tsm2r(A: torch.Tensor, B: torch.Tensor, top: int = 6, reps: int = 4,
+                   rounds: int = 5, warm_seconds: float = 0.2, pin: bool = True) -> dict:
     """Tune the TSM2R plan of C = A*B (A column-major F64/F32 m x k on the
     GPU, B k x n, n <= 32) on these operands.
 
@@ -119,14 +137,21 @@ def autotune_tsm2r(A: torch.Tensor, B: torch.Tensor, top: int = 6, reps: int = 3
                            if p["tall"] == default["tall"] and p["slices"] == default["slices"]))
     C = empty_colmajor(m, n, A.dtype, A.device)
     alg = model.algorithmic_bytes(m, k, n, es)
+    for p in chosen:                             # workspace at its final size
+        pin_tsm2r(m, k, n, dt, p["slices"], p["tall"])
+        tsm2r(A, B, out=C)
     unpin_tsm2r(m, k, n, dt)
     _warm(lambda: tsm2r(A, B, out=C), warm_seconds)
     times = [[] for _ in chosen]
+    order = list(range(len(chosen)))
+    rng = random.Random(1234)
     for _ in range(rounds):
-        for i, p in enumerate(chosen):
+        rng.shuffle(order)
+        for i in order:
+            p = chosen[i]
             pin_tsm2r(m, k, n, dt, p["slices"], p["tall"])
             tsm2r(A, B, out=C)                   # first call of this plan untimed
-            times[i].append(_time(lambda: tsm2r(A, B, out=C), reps))
+            times[i].append(_time_block(lambda: tsm2r(A, B, out=C), reps))
     report = []
     for p in ranked:
         entry = {key: p[key] for key in ("tall", "slices", "tiles", "tile_rows", "occupancy",

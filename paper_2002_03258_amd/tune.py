@@ -93,21 +93,6 @@ def _time_block(fn, reps: int) -> float:
     return e0.elapsed_time(e1) * 1e-3 / reps
 
 
-def _time(fn, reps: int) -> float:
-    """Median seconds of `reps` runs of fn() on the current stream."""
-    st = torch.cuda.current_stream()
-    ts = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        fn()
-        e1.record(st)
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1) * 1e-3)
-    ts.sort()
-    return ts[len(ts) // 2]
-
-
 def autotune_tsm2r(A: torch.Tensor, B: torch.Tensor, top: int = 6, reps: int = 4,
                    rounds: int = 5, warm_seconds: float = 0.2, pin: bool = True) -> dict:
     """Tune the TSM2R plan of C = A*B (A column-major F64/F32 m x k on the

@@ -389,7 +389,10 @@ static int rowtile_dispatch(const LaunchRT& L, hipStream_t st) {
     const bool wide = L.nout > 16;   // two 16-column tiles per pass
     switch (L.kp) {
         case 8: return wide ? rowtile_launch<T, 2, 2, 2>(L, vec, st) : rowtile_launch<T, 2, 1, 2>(L, vec, st);
-        case 16: return wide ? rowtile_launch<T, 4, 2, 2>(L, vec, st) : rowtile_launch<T, 4, 1, 2>(L, vec, st);
+        // k = 16, n <= 16: one row group per lane (four waves per SIMD instead
+        // of three) measured up to 16 % faster for float and the same for
+        // double; for k = 8 it was slower at most sizes
+        case 16: return wide ? rowtile_launch<T, 4, 2, 2>(L, vec, st) : rowtile_launch<T, 4, 1, 1>(L, vec, st);
         case 32: return wide ? rowtile_launch<T, 8, 2, 1>(L, vec, st) : rowtile_launch<T, 8, 1, 2>(L, vec, st);
     }
     return 1;

@@ -389,11 +389,12 @@ static int rowtile_dispatch(const LaunchRT& L, hipStream_t st) {
     const bool wide = L.nout > 16;   // two 16-column tiles per pass
     switch (L.kp) {
         case 8: return wide ? rowtile_launch<T, 2, 2, 2>(L, vec, st) : rowtile_launch<T, 2, 1, 2>(L, vec, st);
-        // k = 16, n <= 16: one row group per lane (four waves per SIMD instead
-        // of three) measured up to 16 % faster for float and the same for
-        // double; for k = 8 it was slower at most sizes
+        // k = 16 and 32 with n <= 16: one row group per lane (more waves per
+        // SIMD) measured up to 16 % faster for float (k = 16) and 2.7 % on
+        // average at k = 32, double the same or faster; for k = 8 and for the
+        // wide instances with two groups it was slower
         case 16: return wide ? rowtile_launch<T, 4, 2, 2>(L, vec, st) : rowtile_launch<T, 4, 1, 1>(L, vec, st);
-        case 32: return wide ? rowtile_launch<T, 8, 2, 1>(L, vec, st) : rowtile_launch<T, 8, 1, 2>(L, vec, st);
+        case 32: return wide ? rowtile_launch<T, 8, 2, 1>(L, vec, st) : rowtile_launch<T, 8, 1, 1>(L, vec, st);
     }
     return 1;
 }

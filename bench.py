@@ -1,26 +1,43 @@
-"""Throughput benchmark of the TSM2R / TSM2L kernels on one MI355X.
+"""Throughput benchmark of the TSM2R / TSM2L path on one MI355X.
 
-A step is one pass over the TSM2R workload grid of square A (m = k in
-{10240, 20480, 30720}) times B (k x n, n in {2, 4, 8, 16}) in FP64 and FP32:
-24 products C = A*B, inputs resident in HBM, iid uniform[-1, 1] from the
-seeded counter-based generator.  ``value`` is the achieved HBM throughput:
-algorithmic bytes (A read once, B read once, C written once) per second over
-the K timed steps.
+A step is one forward and backward pass of C = A*B through the library's
+autograd Function, as training runs it (C = matmul(A, B), then dA = dC*B^T
+and dB = A^T*dC), on the two differentiation workloads:
+  TSM2L shape  A 8388608 x 16, B 16 x 16;
+  TSM2R shape  A 16384 x 16384, B 16384 x 8;
+each in FP64 and in the bf16-split precision form (A kept in HBM as its
+bfloat16 hi + lo planes, B, C, dA and dB float32), with the upstream gradient
+dC ~ N(0, 1): four forward + backward passes per step, inputs resident in HBM,
+iid uniform[-1, 1] from the seeded counter-based generator.  ``value`` is the
+achieved HBM throughput: algorithmic bytes (every operand read once, every
+result written once) per second over the K timed steps.
 
-Besides the headline line the JSON carries:
-  roofline      the dominant kernel (largest total time in the step), its
-                algorithmic bytes per launch over its average launch duration
-                (HIP events on the stream it runs on) against 8 TB/s, and the
-                HBM traffic rocprofv3 counted for it (profiles/), or null;
-  cpu_baseline  the FP64 oracle timed on this host's cores on a row sample of
-                the largest workload;
-  rows          the other hot-path rows measured on their own workloads
-                (TSM2L grid, backward of C = A*B), each with GB/s, fraction of
-                8 TB/s and the normwise error of sampled outputs vs the oracle;
-  check         normwise errors of sampled rows of every product of the step.
+Besides the headline the JSON line carries:
+  config.cases  each pass's GB/s, time and bytes, and the bf16-split speedup
+                over FP64 per shape;
+  err           each pass's C, dA and dB against the FP64 oracle on sampled
+                rows (all of dB for the TSM2L shape): normwise and
+                componentwise error, for bf16-split against both the stored
+                values (hi + lo) and the float values of A;
+  roofline      the dominant kernel of the step (largest total launch time,
+                timed per launch by the library with HIP events on the stream
+                it runs on), its algorithmic bytes per launch over its average
+                launch time against 8 TB/s, and the HBM traffic rocprofv3
+                counted for it (profiles/), or null;
+  ceilings      the measured HBM ceilings of this device: linear 16-byte
+                streams (read, copy, write) and the TSM2L tile pattern without
+                its arithmetic;
+  cpu_baseline  the FP64 oracle timed on this host's cores on row samples of
+                the same two workloads, forward and backward;
+  rows          the other hot-path workloads: the TSM2R grid (square A,
+                m = k in {10240, 20480, 30720}, n in {2..16}, FP64 and FP32),
+                the TSM2L grid, the precision form of TSM2R, FP32 autograd and
+                bf16-split autograd with the split of A inside every pass,
+                general shapes and the K-means assignment.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       [--no-cpu-baseline] [--no-rows] [--profile-kernel | --profile-copy]
+       [--no-cpu-baseline] [--no-rows] [--no-check]
+       [--profile-kernel DT:M:N | --profile-op SPEC | --profile-copy | --ceiling]
 """
 from __future__ import annotations
 
@@ -44,33 +61,34 @@ from paper_2002_03258_amd import tune  # noqa: E402
 import seeded_inputs as si  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
-# streaming-read ceiling measured on MI355X with a 16-byte non-temporal
-# linear-read probe (reported beside the datasheet peak)
-READ_CEILING_GBS = 7090.0
-# read + write ceiling measured the same way: a 1 GiB copy with 16-byte
-# non-temporal loads and stores
-COPY_CEILING_GBS = 6385.0
+METRIC = "achieved HBM GB/s (% peak), TSM2R/TSM2L fp64 vs bf16-split fwd+bwd at tol"
 
-
-def attach_ceilings(rows):
-    """Each row's fraction of the measured ceiling of its traffic mix: the
-    copy ceiling for products that write about as much as they read (TSM2L,
-    the backward passes), the streaming-read ceiling otherwise."""
-    for r in rows:
-        rw = r["row"].startswith("TSM2L forward") or r["row"].startswith("autograd")
-        r["measured_ceiling_GBps"] = COPY_CEILING_GBS if rw else READ_CEILING_GBS
-        r["frac_of_measured_ceiling"] = r["GBps"] / r["measured_ceiling_GBps"]
-    return rows
 R_SIZES = (10240, 20480, 30720)
 R_NS = (2, 4, 8, 16)
 R_DTYPES = (torch.float64, torch.float32)
 L_MS = (1 << 20, 1 << 22, 1 << 24)
 L_KS = (8, 16, 32)
 TOL = {torch.float64: 1e-13, torch.float32: 1e-5}
-# the TSM2R kernel's sources: counter summaries taken from another version of
-# them are not used
-KERNEL_SRC = [os.path.join(ROOT, "paper_2002_03258_amd", "csrc", f)
-              for f in ("tsm2x_tsm2r.hip", "tsm2x_device.h")]
+# the differentiation workloads: (shape, kind, m, k, n)
+AG_SHAPES = (("TSM2L", "L", 8388608, 16, 16), ("TSM2R", "R", 16384, 16384, 8))
+AG_MODES = ("f64", "bf16_split")
+# normwise tolerances per mode (and per view of the precision form)
+AG_TOL = {"f64": 1e-13, "f32": 1e-5, "bf16_split": {"stored": 1e-5, "value": 2e-5}}
+# kernels that are overhead, not a step of the product (split partial sums,
+# zero fills, the transposed-B copy, the split of A)
+OVERHEAD_KERNELS = ("split_reduce_kernel", "fill_scale_kernel", "transpose_kernel",
+                    "split_kernel")
+
+
+def attach_ceilings(rows, ceilings):
+    """Each row's fraction of the measured ceiling of its traffic mix: the
+    copy ceiling for products that write about as much as they read (TSM2L,
+    the backward passes), the streaming-read ceiling otherwise."""
+    for r in rows:
+        rw = r["row"].startswith("TSM2L forward") or r["row"].startswith("autograd")
+        r["measured_ceiling_GBps"] = ceilings["copy_GBps"] if rw else ceilings["read_GBps"]
+        r["frac_of_measured_ceiling"] = r["GBps"] / r["measured_ceiling_GBps"]
+    return rows
 
 
 def es(dtype) -> int:
@@ -79,13 +97,6 @@ def es(dtype) -> int:
 
 def nn_kernel_name(dtype, m, n) -> str:
     return tsm.kernel_name(tsm.OP_TSM2R, m, m, n, tsm.F64 if dtype == torch.float64 else tsm.F32)
-
-
-def src_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SRC:
-        h.update(open(f, "rb").read())
-    return h.hexdigest()[:16]
 
 
 def make_r_inputs(dev):
@@ -213,73 +224,6 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline():
-    """The FP64 oracle on a row sample of the largest TSM2R workload, on all
-    of the host's cores and on one (each sample sized for about 10 s)."""
-    import oracle
-    m = k = R_SIZES[-1]
-    n = 16
-    seed = si.config_seed(1)
-    B = si.matrix(seed + n, si.STREAM_B, k, n).numpy()
-    cores = oracle.threads()
-
-    def probe_rows(target_s):
-        # rows of A the oracle gets through in about target_s seconds
-        Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(64))).numpy()
-        t0 = time.perf_counter()
-        oracle.matmul(Ar, B)
-        return int(min(m, max(64, 64 * target_s / max(time.perf_counter() - t0, 1e-3))))
-
-    rows_all = probe_rows(10.0)
-    oracle.set_threads(1)
-    rows_one = min(rows_all, probe_rows(6.0))
-    oracle.set_threads(cores)
-    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(rows_all))).numpy()
-
-    def rate(rows):
-        t0 = time.perf_counter()
-        oracle.matmul(Ar[:rows], B)
-        dt = time.perf_counter() - t0
-        return (rows * k + k * n + rows * n) * 8 / dt / 1e9, dt
-
-    v_all, dt = rate(rows_all)
-    oracle.set_threads(1)
-    v_one, dt1 = rate(rows_one)
-    oracle.set_threads(cores)
-    return {"value": v_all, "unit": "GB/s", "cores": cores, "kind": "oracle", "seconds": dt,
-            "single_thread_value": v_one, "single_thread_seconds": dt1, "cpu_model": _cpu_model(),
-            "sample": "FP64 TSM2R C = A*B on the first %d (all cores) and %d (one core) of %d "
-                      "rows of A (k = %d, n = %d); algorithmic bytes of the sample over the "
-                      "oracle's time" % (rows_all, rows_one, m, k, n)}
-
-
-def traffic_for(kernel: str, launches):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summaries (profiles/*_counters.txt), averaged like the launches of the
-    timed step; None when a workload is missing or the summary was taken
-    from another kernel source."""
-    import glob
-    found = {}
-    for path in glob.glob(os.path.join(ROOT, "profiles", "*_counters.txt")):
-        info = {}
-        for line in open(path):
-            if "=" in line and not line.startswith("#"):
-                key, val = line.split("=", 1)
-                info[key.strip()] = val.strip()
-        if info.get("kernel") != kernel or info.get("kernel_source_sha256_16") != src_hash():
-            continue
-        try:
-            found[info["workload"]] = float(info["hbm_bytes_per_launch"])
-        except (KeyError, ValueError):
-            continue
-    tot = 0.0
-    for wl in launches:
-        if wl not in found:
-            return None
-        tot += found[wl]
-    return tot / len(launches) if launches else None
-
-
 def timed(fn, reps=5, warmup=1, flush=None, warm_seconds=0.05):
     """Median seconds of fn() over `reps` runs, each bracketed by HIP events
     (the median keeps one disturbed run from moving a row); `flush`
@@ -307,7 +251,7 @@ def rows_tsm2l(dev):
     out = []
     seed = si.config_seed(2)
     for dtype in R_DTYPES:
-        tot_b, tot_t, worst = 0.0, 0.0, 0.0
+        tot_b, tot_t, worst, worst_cw = 0.0, 0.0, 0.0, 0.0
         for m in L_MS:
             for k in L_KS:
                 A = si.matrix(seed + k, si.STREAM_A, m, k, dtype=dtype, device=dev)
@@ -319,17 +263,19 @@ def rows_tsm2l(dev):
                 tot_b += nb
                 tot_t += t
                 rows = [0, m // 3, m - 1]
-                ref = oracle.matmul(si.matrix_rows(seed + k, si.STREAM_A, m, k, rows,
-                                                   dtype=dtype).double().numpy(),
-                                    si.matrix(seed + k, si.STREAM_B, k, k, dtype=dtype)
-                                    .double().numpy())
-                worst = max(worst, oracle.normwise_error(C[rows].double().cpu().numpy(), ref))
+                Ar = si.matrix_rows(seed + k, si.STREAM_A, m, k, rows, dtype=dtype).double().numpy()
+                Bh = si.matrix(seed + k, si.STREAM_B, k, k, dtype=dtype).double().numpy()
+                ref = oracle.matmul(Ar, Bh)
+                Cs = C[rows].double().cpu().numpy()
+                worst = max(worst, oracle.normwise_error(Cs, ref))
+                worst_cw = max(worst_cw, oracle.componentwise_error(Cs, ref, Ar, Bh))
                 del A, B, C, flush
         torch.cuda.empty_cache()
         out.append({"row": "TSM2L forward (C = A*B, m in 2^20..2^24, k = n in 8..32)",
                     "dtype": str(dtype).replace("torch.", ""), "GBps": tot_b / tot_t / 1e9,
                     "frac_of_8TBps": tot_b / tot_t / 1e9 / PEAK_HBM_GBS,
-                    "max_normwise_err": worst, "tol": TOL[dtype]})
+                    "max_normwise_err": worst, "max_componentwise_err": worst_cw,
+                    "tol": TOL[dtype]})
     return out
 
 
@@ -459,7 +405,11 @@ def rows_lowp(dev):
                        "fp32_GBps": b32 / t32 / 1e9, "speedup_vs_fp32": t32 / t,
                        "bytes_ratio_fp32_over_form": b32 / nb,
                        "err_vs_stored": oracle.normwise_error(Cs, oracle.matmul(stored, Bh)),
-                       "err_vs_fp32_values": oracle.normwise_error(Cs, oracle.matmul(Ar, Bh))}
+                       "err_vs_fp32_values": oracle.normwise_error(Cs, oracle.matmul(Ar, Bh)),
+                       "componentwise_err_vs_stored": oracle.componentwise_error(
+                           Cs, oracle.matmul(stored, Bh), stored, Bh),
+                       "componentwise_err_vs_fp32_values": oracle.componentwise_error(
+                           Cs, oracle.matmul(Ar, Bh), Ar, Bh)}
                 if t_split is not None:
                     row["split_GBps"] = (m * k * 4 + S.nbytes()) / t_split / 1e9
                 out.append(row)
@@ -470,102 +420,469 @@ def rows_lowp(dev):
     return out
 
 
-def rows_autograd(dev):
-    """Forward + backward of C = A*B on the two autograd shapes."""
-    import oracle
-    out = []
-    seed = si.config_seed(4)
-    for shape, (m, k, n) in (("TSM2L", (8388608, 16, 16)), ("TSM2R", (16384, 16384, 8))):
-        for dtype in R_DTYPES:
-            A = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
-            B = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype, device=dev)
-            dC = si.matrix(seed, si.STREAM_DC, m, n, dtype=dtype, device=dev, dist="normal")
-            C = tsm.empty_colmajor(m, n, dtype, dev)
-            dA = tsm.empty_colmajor(m, k, dtype, dev)
-            dB = tsm.empty_colmajor(k, n, dtype, dev)
-            fwd = (lambda: tsm.tsm2l(A, B, out=C)) if shape == "TSM2L" else \
-                (lambda: tsm.tsm2r(A, B, out=C))
-            s = es(dtype)
-            t_f = timed(fwd)
-            b_f = (m * k + k * n + m * n) * s
-            if shape == "TSM2L":
-                # the autograd Function's backward: one fused pass over A and dC
-                res = {}
+def ag_bytes(kind: str, mode: str, m: int, k: int, n: int) -> dict:
+    """Algorithmic bytes of each library call of one forward + backward of
+    C = A*B: every operand read once, every result written once.  A counts as
+    its stored form (8 or 4 bytes per element, or the two 2-byte planes of the
+    split form); B, C, dC, dA, dB as float64 (f64) or float32."""
+    s = 8 if mode == "f64" else 4
+    sa = 4 if mode in ("bf16_split", "f16_split") else (2 if mode in ("bf16", "f16") else s)
+    fwd = sa * m * k + s * (k * n + m * n)
+    if kind == "L":
+        # fused backward: reads A, dC and B, writes dA and dB
+        return {"fwd": fwd, "bwd": sa * m * k + s * (m * n + k * n) + s * (m * k + k * n)}
+    return {"fwd": fwd, "grad_a": s * (m * n + k * n + m * k), "grad_b": sa * m * k + s * (m * n + k * n)}
 
-                def bwd():
-                    res["g"] = tsm.tsm2l_backward(A, B, dC)
-                t_bw = timed(bwd)
-                dA, dB = res["g"]
-                t_a, t_b = t_bw, 0.0
-                b_a = (m * k + m * n + k * n + m * k + k * n) * s
-                b_b = 0
-            else:
-                t_a = timed(lambda: tsm.grad_a(dC, B, out=dA))
-                t_b = timed(lambda: tsm.grad_b(A, dC, out=dB))
-                b_a = (m * n + k * n + m * k) * s
-                b_b = (m * k + m * n + k * n) * s
-            rows = [0, m // 2, m - 1]
-            Ar = si.matrix_rows(seed, si.STREAM_A, m, k, rows, dtype=dtype).double().numpy()
-            Bh = si.matrix(seed, si.STREAM_B, k, n, dtype=dtype).double().numpy()
-            dCr = si.matrix_rows(seed, si.STREAM_DC, m, n, rows, dtype=dtype,
-                                 dist="normal").double().numpy()
-            e_f = oracle.normwise_error(C[rows].double().cpu().numpy(), oracle.matmul(Ar, Bh))
-            e_a = oracle.normwise_error(dA[rows].double().cpu().numpy(), oracle.matmul(dCr, Bh.T))
-            cols = [0, k // 2, k - 1]
-            if m * n <= (1 << 22):
-                Ac = si.matrix_cols(seed, si.STREAM_A, m, k, cols, dtype=dtype).double().numpy()
-                dCh = si.matrix(seed, si.STREAM_DC, m, n, dtype=dtype,
-                                dist="normal").double().numpy()
-                e_b = oracle.normwise_error(dB[cols].double().cpu().numpy(),
-                                            oracle.matmul(Ac.T, dCh))
-            else:
-                e_b = None
-            out.append({"row": "autograd fwd+bwd %s shape m=%d k=%d n=%d" % (shape, m, k, n),
-                        "dtype": str(dtype).replace("torch.", ""),
-                        "GBps": (b_f + b_a + b_b) / (t_f + t_a + t_b) / 1e9,
-                        "frac_of_8TBps": (b_f + b_a + b_b) / (t_f + t_a + t_b) / 1e9 / PEAK_HBM_GBS,
-                        "fwd_GBps": b_f / t_f / 1e9,
-                        ("fused_bwd_GBps" if shape == "TSM2L" else "grad_a_GBps"): b_a / t_a / 1e9,
-                        "grad_b_GBps": b_b / t_b / 1e9 if t_b > 0 else None,
-                        "err": {"C": e_f, "dA": e_a, "dB": e_b}, "tol": TOL[dtype]})
-            del A, B, dC, C, dA, dB
-            torch.cuda.empty_cache()
-    # bf16-split: forward on the planes (split once, reported apart), dA in
-    # float, dB on the planes
-    for shape, (m, k, n) in (("TSM2L", (8388608, 16, 16)), ("TSM2R", (16384, 16384, 8))):
-        A = si.matrix(seed, si.STREAM_A, m, k, dtype=torch.float32, device=dev)
-        B = si.matrix(seed, si.STREAM_B, k, n, dtype=torch.float32, device=dev)
-        dC = si.matrix(seed, si.STREAM_DC, m, n, dtype=torch.float32, device=dev, dist="normal")
-        S = tsm.split(A, "bf16", lo=True)
-        C = tsm.empty_colmajor(m, n, torch.float32, dev)
-        dA = tsm.empty_colmajor(m, k, torch.float32, dev)
-        dB = tsm.empty_colmajor(k, n, torch.float32, dev)
-        fwd = (lambda: tsm.tsm2l(S, B, out=C)) if shape == "TSM2L" else (lambda: tsm.tsm2r(S, B, out=C))
-        t_f = timed(fwd)
-        b_f = S.nbytes() + (k * n + m * n) * 4
-        row = {"row": "autograd fwd+bwd %s shape m=%d k=%d n=%d" % (shape, m, k, n),
-               "dtype": "bf16_split", "fwd_GBps": b_f / t_f / 1e9}
-        if shape == "TSM2L":
-            # the autograd Function's backward: one fused pass over the planes and dC
-            t_a = timed(lambda: tsm.tsm2l_backward(S, B, dC))
-            t_b = 0.0
-            b_a = S.nbytes() + (m * n + k * n + m * k + k * n) * 4
-            b_b = 0
-            row["fused_bwd_GBps"] = b_a / t_a / 1e9
-        else:
-            t_a = timed(lambda: tsm.grad_a(dC, B, out=dA))
-            t_b = timed(lambda: tsm.grad_b(S, dC, out=dB))
-            b_a = (m * n + k * n + m * k) * 4
-            b_b = S.nbytes() + (m * n + k * n) * 4
-            row["grad_a_GBps"] = b_a / t_a / 1e9
-            row["grad_b_GBps"] = b_b / t_b / 1e9
-        row["GBps"] = (b_f + b_a + b_b) / (t_f + t_a + t_b) / 1e9
-        row["frac_of_8TBps"] = row["GBps"] / PEAK_HBM_GBS
-        row["ms_fwd_bwd"] = (t_f + t_a + t_b) * 1e3
-        out.append(row)
-        del A, B, dC, S, C, dA, dB
-        torch.cuda.empty_cache()
+
+class AGCase:
+    """One forward + backward of C = A*B through tsm.matmul and
+    torch.autograd.grad, on resident seeded inputs.  For the precision modes
+    A is split once here (its storage form, kept across steps) unless
+    `split_inside`, where every forward splits it again."""
+
+    def __init__(self, dev, shape, kind, m, k, n, mode, seed, index, split_inside=False):
+        self.shape, self.kind, self.m, self.k, self.n, self.mode = shape, kind, m, k, n, mode
+        self.seed, self.split_inside = seed, split_inside
+        self.dtype = torch.float64 if mode == "f64" else torch.float32
+        self.A = si.matrix(seed, si.STREAM_A, m, k, dtype=self.dtype, device=dev).requires_grad_()
+        self.B = si.matrix(seed, si.STREAM_B, k, n, dtype=self.dtype, device=dev).requires_grad_()
+        self.dC = si.matrix(seed, si.STREAM_DC, m, n, dtype=self.dtype, device=dev, dist="normal")
+        lowp = mode not in ("f64", "f32")
+        self.Aop = tsm.split(self.A, mode.split("_")[0], lo=mode.endswith("split")) \
+            if lowp and not split_inside else self.A
+        self.tag_fwd, self.tag_bwd = 2 * index + 1, 2 * index + 2
+        self.bytes = ag_bytes(kind, mode, m, k, n)
+        self.total_bytes = sum(self.bytes.values())
+        self.name = "%s %s" % (shape, mode)
+
+    def run(self):
+        tsm.timing_tag(self.tag_fwd)
+        C = tsm.matmul(self.Aop, self.B, self.mode, self.kind)
+        tsm.timing_tag(self.tag_bwd)
+        dA, dB = torch.autograd.grad(C, (self.A, self.B), self.dC)
+        tsm.timing_tag(0)
+        return C, dA, dB
+
+    def role(self, tag: int, kernel: str):
+        """Which call of the pass a kernel launched under `tag` belongs to
+        (a key of self.bytes), or None for overhead kernels."""
+        fam = kernel.split("<")[0]
+        if fam in OVERHEAD_KERNELS:
+            return None
+        if tag == self.tag_fwd:
+            return "fwd"
+        if tag != self.tag_bwd:
+            return None
+        if self.kind == "L":
+            return "bwd" if fam == "tsm2l_bwd_kernel" else None
+        if fam == "rowtile_kernel":
+            return "grad_a"
+        if fam in ("tn_kernel", "tn_lp_kernel"):
+            return "grad_b"
+        return None
+
+
+def make_ag_cases(dev, modes=AG_MODES, split_inside=False, first_index=0):
+    seed = si.config_seed(4)
+    cases = []
+    for shape, kind, m, k, n in AG_SHAPES:
+        for mode in modes:
+            cases.append(AGCase(dev, shape, kind, m, k, n, mode, seed,
+                                first_index + len(cases), split_inside))
+    return cases
+
+
+def _stored(A: np.ndarray, fmt: int, lo: bool) -> np.ndarray:
+    """The values the precision form stores for float32 values A: hi (+ lo),
+    split by the oracle."""
+    hi, lo_ = oracle_mod().split(np.asfortranarray(A.astype(np.float32)), fmt, with_lo=lo)
+    v = oracle_mod().decode_plane(hi, fmt)
+    return v + oracle_mod().decode_plane(lo_, fmt) if lo else v
+
+
+def oracle_mod():
+    import oracle
+    return oracle
+
+
+def _errs(got: np.ndarray, ref: np.ndarray, X: np.ndarray, Y: np.ndarray) -> dict:
+    o = oracle_mod()
+    return {"normwise": o.normwise_error(got, ref), "componentwise": o.componentwise_error(got, ref, X, Y)}
+
+
+def case_errors(c: AGCase, C, dA, dB) -> dict:
+    """C, dA and dB of one pass against the FP64 oracle: sampled rows of C and
+    dA; sampled rows of dB (every row for the TSM2L shape, where dB is 16 x 16
+    and needs all of A and dC).  The precision form is compared with the
+    products of the stored values (hi + lo, split by the oracle) and of the
+    float values of A; dA = dC*B^T involves no stored value."""
+    o = oracle_mod()
+    m, k, n, dt, seed = c.m, c.k, c.n, c.dtype, c.seed
+    rng = np.random.default_rng(m + k + n)
+    rows = sorted(set([0, 1, m // 3, m // 2 + 7, m - 1] + rng.integers(0, m, 11).tolist()))
+    Ar = si.matrix_rows(seed, si.STREAM_A, m, k, rows, dtype=dt).double().numpy()
+    Bh = si.matrix(seed, si.STREAM_B, k, n, dtype=dt).double().numpy()
+    dCr = si.matrix_rows(seed, si.STREAM_DC, m, n, rows, dtype=dt, dist="normal").double().numpy()
+    lowp = c.mode not in ("f64", "f32")
+    fmt = o.BF16 if c.mode.startswith("bf16") else o.F16
+    lo = c.mode.endswith("split")
+
+    def views(X):
+        return {"stored": _stored(X, fmt, lo), "value": X} if lowp else {"value": X}
+
+    def tol(view):
+        t = AG_TOL[c.mode]
+        return t[view] if isinstance(t, dict) else t
+
+    out = {}
+    Cs = C.detach()[rows].double().cpu().numpy()
+    out["C"] = {v: dict(_errs(Cs, o.matmul(X, Bh), X, Bh), tol=tol(v))
+                for v, X in views(Ar).items()}
+    dAs = dA[rows].double().cpu().numpy()
+    out["dA"] = {"value": dict(_errs(dAs, o.matmul(dCr, Bh.T), dCr, Bh.T), tol=tol("value"))}
+    if c.kind == "L":
+        cols = list(range(k))
+        Acols = c.A.detach().double().cpu().numpy()     # every row: dB = A^T dC needs all of A
+        # row-major dC: the oracle's loop over m then reads each row of dC once
+        dCh = np.ascontiguousarray(c.dC.double().cpu().numpy())
+        # the device inputs are the seeded generator's values (checked on the sample)
+        assert np.array_equal(Acols[rows], Ar) and np.array_equal(dCh[rows], dCr)
+    else:
+        cols = sorted(set([0, 1, k // 2, k - 1] + rng.integers(0, k, 12).tolist()))
+        Acols = si.matrix_cols(seed, si.STREAM_A, m, k, cols, dtype=dt).double().numpy()
+        dCh = si.matrix(seed, si.STREAM_DC, m, n, dtype=dt, dist="normal").double().numpy()
+    dBs = dB[cols].double().cpu().numpy()
+    out["dB"] = {v: dict(_errs(dBs, o.matmul(np.ascontiguousarray(X.T), dCh), X.T, dCh),
+                         tol=tol(v)) for v, X in views(Acols).items()}
+    out["sample"] = "C, dA: %d rows; dB: %d of %d rows" % (len(rows), len(cols), k)
+    ok = all(e["normwise"] <= e["tol"] for key in ("C", "dA", "dB") for e in out[key].values())
+    out["ok"] = ok
     return out
+
+
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summaries (profiles/*_counters.txt), or None when none
+    matches or the summary was taken from other sources than the current ones
+    (each summary names its source files and their SHA-256)."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.txt"))):
+        info = {}
+        for line in open(path):
+            if "=" in line and not line.startswith("#"):
+                key, val = line.split("=", 1)
+                info[key.strip()] = val.strip()
+        if info.get("kernel") != kernel or info.get("workload") != workload:
+            continue
+        sha = info.get("kernel_source_sha256_16", "")
+        files = sha[sha.find("(") + 1:sha.find(")")].split(",") if "(" in sha else []
+        if not files or sha.split()[0] != sources_hash(files):
+            continue
+        try:
+            return float(info["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
+
+
+def sources_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2002_03258_amd", "csrc", f.strip()), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def roofline_of(cases, timing):
+    """The dominant kernel of the timed steps: the (kernel, tag) row of the
+    library's launch timing with the largest total time, its algorithmic
+    bytes per launch (the bytes of the call it serves) over its average
+    launch time."""
+    by_tag = {}
+    for c in cases:
+        by_tag[c.tag_fwd] = c
+        by_tag[c.tag_bwd] = c
+    best = None
+    for r in timing:
+        c = by_tag.get(r["tag"])
+        if c is None or c.role(r["tag"], r["kernel"]) is None:
+            continue
+        if best is None or r["total_ms"] > best[0]["total_ms"]:
+            best = (r, c)
+    if best is None:
+        return None
+    r, c = best
+    role = c.role(r["tag"], r["kernel"])
+    per_launch = c.bytes[role]
+    avg_s = r["total_ms"] / 1e3 / r["launches"]
+    achieved = per_launch / avg_s / 1e9
+    workload = "autograd:%s:%s:%s" % (c.mode, c.kind, role)
+    traffic = traffic_from_profiles(r["kernel"], workload)
+    return {"bound": "hbm", "kernel": r["kernel"], "call": "%s, %s" % (c.name, role),
+            "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": avg_s * 1e6,
+            "launches": r["launches"], "algorithmic_bytes_per_launch": per_launch,
+            "workload": workload, "traffic": traffic,
+            "traffic_over_algorithmic": (traffic / per_launch) if traffic else None}
+
+
+def headline(dev, steps, warmup, check=True):
+    """The timed step: the four forward + backward passes."""
+    cases = make_ag_cases(dev)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        for c in cases:
+            c.run()
+    torch.cuda.synchronize()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in cases] for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    last = [None] * len(cases)
+    torch.cuda.synchronize()
+    tsm.timing_start()
+    e0.record()
+    for s in range(steps):
+        for i, c in enumerate(cases):
+            evs[s][i][0].record()
+            last[i] = c.run()
+            evs[s][i][1].record()
+    e1.record()
+    torch.cuda.synchronize()
+    tsm.timing_stop()
+    timing = tsm.timing_collect()
+    total_ms = e0.elapsed_time(e1)
+    step_bytes = sum(c.total_bytes for c in cases)
+    value = step_bytes * steps / (total_ms / 1e3) / 1e9
+    per_case = []
+    for i, c in enumerate(cases):
+        t = float(np.median([evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(steps)])) / 1e3
+        calls = {}
+        for r in timing:
+            role = c.role(r["tag"], r["kernel"]) if r["tag"] in (c.tag_fwd, c.tag_bwd) else None
+            if role is not None:
+                d = calls.setdefault(role, {"kernels": [], "ms_per_launch": 0.0})
+                d["kernels"].append(r["kernel"])
+                d["ms_per_launch"] += r["total_ms"] / r["launches"]
+        for role, d in calls.items():
+            d["GBps"] = c.bytes[role] / (d["ms_per_launch"] / 1e3) / 1e9
+            d["bytes"] = c.bytes[role]
+        per_case.append({"case": c.name, "shape": (c.m, c.k, c.n), "mode": c.mode,
+                         "bytes": c.total_bytes, "ms_median": t * 1e3,
+                         "GBps": c.total_bytes / t / 1e9,
+                         "frac_of_8TBps": c.total_bytes / t / 1e9 / PEAK_HBM_GBS,
+                         "calls": calls})
+    modes = {}
+    for mode in AG_MODES:
+        sel = [p for p in per_case if p["mode"] == mode]
+        b = sum(p["bytes"] for p in sel)
+        t = sum(p["ms_median"] for p in sel) / 1e3
+        modes[mode] = {"GBps": b / t / 1e9, "ms": t * 1e3, "frac_of_8TBps": b / t / 1e9 / PEAK_HBM_GBS}
+    speedup = {}
+    for shape, *_ in AG_SHAPES:
+        t64 = [p["ms_median"] for p in per_case if p["case"] == "%s f64" % shape][0]
+        tsp = [p["ms_median"] for p in per_case if p["case"] == "%s bf16_split" % shape][0]
+        speedup[shape] = t64 / tsp
+    res = {"value": value, "ms_per_step": total_ms / steps, "bytes_per_step": step_bytes,
+           "cases": per_case, "modes": modes, "bf16_split_speedup_over_f64": speedup,
+           "roofline": roofline_of(cases, timing),
+           "kernel_timing": [dict(r, case=next((c.name for c in cases
+                                                if r["tag"] in (c.tag_fwd, c.tag_bwd)), None))
+                             for r in timing]}
+    if check:
+        res["err"] = {}
+        for i, c in enumerate(cases):
+            res["err"][c.name] = case_errors(c, *last[i])
+            print("checked %s against the oracle" % c.name, file=sys.stderr, flush=True)
+    del last, cases
+    torch.cuda.empty_cache()
+    return res
+
+
+def measure_ceilings(dev):
+    """HBM ceilings of this device with 16-byte non-temporal accesses: a
+    4 GiB linear read, a 2 GiB copy, a 4 GiB write, and the TSM2L tile pattern
+    without arithmetic on the 2^24 x 16 FP64 and 2^23 x 16 FP32 shapes (A read
+    once, C = a column permutation of A written once).  Each the median of 5
+    runs after a warm-up; GB/s counts the bytes moved."""
+    out = {}
+    big = torch.empty(1 << 32, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
+    half = 1 << 31
+    t = timed(lambda: tsm.probe_stream("read", dst, big))
+    out["read_GBps"] = big.numel() / t / 1e9
+    t = timed(lambda: tsm.probe_stream("copy", dst, big, nbytes=half))
+    out["copy_GBps"] = 2 * half / t / 1e9
+    t = timed(lambda: tsm.probe_stream("write", dst))
+    out["write_GBps"] = dst.numel() / t / 1e9
+    del big, dst
+    for dt, m in ((torch.float64, 1 << 24), (torch.float32, 1 << 23)):
+        X = si.matrix(si.config_seed(9), si.STREAM_A, m, 16, dtype=dt, device=dev)
+        O = tsm.empty_colmajor(m, 16, dt, dev)
+        t = timed(lambda: tsm.probe_tiles(X, O))
+        out["tsm2l_pattern_%s_m%d_k16_GBps" % (str(dt).replace("torch.", ""), m)] = \
+            2 * X.numel() * X.element_size() / t / 1e9
+        del X, O
+    torch.cuda.empty_cache()
+    out["note"] = ("16-byte non-temporal loads/stores; read 4 GiB, copy 2 GiB -> 2 GiB (bytes "
+                   "read + written), write 4 GiB; TSM2L pattern = the rowtile kernel's loads and "
+                   "stores without the matrix-core work")
+    return out
+
+
+def cpu_baseline():
+    """The FP64 oracle on row samples of the headline workload, forward and
+    backward (C, dA and dB's share of the sampled rows), on all of the host's
+    cores and on one; each sample sized for a few seconds."""
+    o = oracle_mod()
+    seed = si.config_seed(4)
+    cores = o.threads()
+
+    def one(shape, kind, m, k, n, rows):
+        A = si.matrix_rows(seed, si.STREAM_A, m, k, list(range(rows))).numpy()
+        B = si.matrix(seed, si.STREAM_B, k, n).numpy()
+        dC = si.matrix_rows(seed, si.STREAM_DC, m, n, list(range(rows)), dist="normal").numpy()
+        t0 = time.perf_counter()
+        o.matmul(A, B)
+        o.matmul(dC, B.T)
+        o.matmul(np.ascontiguousarray(A.T), dC)
+        dt = time.perf_counter() - t0
+        return sum(ag_bytes(kind, "f64", rows, k, n).values()), dt
+
+    def run(target_s):
+        tot_b, tot_t, desc = 0.0, 0.0, []
+        for shape, kind, m, k, n in AG_SHAPES:
+            probe = max(64, min(m, 4096 if kind == "R" else 1 << 16) // 64)
+            b, t = one(shape, kind, m, k, n, probe)
+            rows = int(min(m, max(probe, probe * target_s / max(t, 1e-4))))
+            b, t = one(shape, kind, m, k, n, rows)
+            tot_b += b
+            tot_t += t
+            desc.append("%d of %d rows of the %s shape" % (rows, m, shape))
+        return tot_b / tot_t / 1e9, tot_t, desc
+
+    v_all, t_all, d_all = run(5.0)
+    o.set_threads(1)
+    v_one, t_one, d_one = run(3.0)
+    o.set_threads(cores)
+    return {"value": v_all, "unit": "GB/s", "cores": cores, "kind": "oracle", "seconds": t_all,
+            "single_thread_value": v_one, "single_thread_seconds": t_one,
+            "cpu_model": _cpu_model(),
+            "sample": "FP64 forward + backward (C = A*B, dA = dC*B^T, dB = A^T*dC) of the autograd "
+                      "workloads on row samples, all cores: %s; one core: %s; algorithmic bytes of "
+                      "the samples over the oracle's time" % ("; ".join(d_all), "; ".join(d_one))}
+
+
+def rows_autograd_more(dev):
+    """Forward + backward of the same workloads in FP32 (the precision form's
+    baseline: same 4 bytes per element of A as the split form), and in
+    bf16-split with the split of A inside every pass (a float32 A that
+    changes every step).  GB/s counts the algorithmic bytes of the pass; the
+    split's own traffic is not counted (its time is)."""
+    out = []
+    cases = make_ag_cases(dev, modes=("f32",)) + \
+        make_ag_cases(dev, modes=("bf16_split",), split_inside=True, first_index=2)
+    for c in cases:
+        res = {}
+
+        def run():
+            res["r"] = c.run()
+        t = timed(run)
+        err = case_errors(c, *res["r"])
+        out.append({"row": "autograd fwd+bwd %s shape m=%d k=%d n=%d%s" % (
+            c.shape, c.m, c.k, c.n, ", A split inside every pass" if c.split_inside else ""),
+            "dtype": c.mode, "GBps": c.total_bytes / t / 1e9,
+            "frac_of_8TBps": c.total_bytes / t / 1e9 / PEAK_HBM_GBS, "ms": t * 1e3, "err": err})
+        del res
+    del cases
+    torch.cuda.empty_cache()
+    return out
+
+
+def rows_tsm2r_grid(dev, steps=5, check=True, tune_plans=False):
+    """The TSM2R grid: 24 products C = A*B, square A (m = k in {10240, 20480,
+    30720}), n in {2, 4, 8, 16}, FP64 and FP32, as one timed sequence
+    (`tune_plans`: each product's plan autotuned first)."""
+    calls = make_r_inputs(dev)
+    tuned = None
+    if tune_plans:
+        tuned = {}
+        for c in calls:
+            r = tune.autotune_tsm2r(c["A"], c["B"], top=4)
+            tuned[c["workload"]] = {"slices": r["best"]["slices"], "tall": r["best"]["tall"],
+                                    "gain": r["best"]["gbs"] / r["default"]["gbs"]}
+    for _ in range(2):
+        run_step(calls)
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in calls] for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for s in range(steps):
+        run_step(calls, evs[s])
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    step_bytes = sum(c["bytes"] for c in calls)
+    v = step_bytes * steps / (total_ms / 1e3) / 1e9
+    row = {"row": "TSM2R grid (C = A*B, m = k in 10240..30720, n in 2..16, 24 products)",
+           "dtype": "f64+f32", "GBps": v, "frac_of_8TBps": v / PEAK_HBM_GBS,
+           "ms_per_pass": total_ms / steps,
+           "model": model_summary(calls, evs, step_bytes, v)}
+    if tuned is not None:
+        row["tuned_plans"] = tuned
+    if check:
+        row["check"] = check_calls(calls)
+    del calls
+    torch.cuda.empty_cache()
+    return [row]
+
+
+def profile_op(dev, spec):
+    """Launch one workload 5 times and nothing else (for rocprofv3 counters):
+    tsm2l:DT:M:K (B k x k), kmeans:DT:M:K[:row], or autograd:MODE:KIND (one
+    forward + backward of the autograd workload of that shape, KIND L or R)."""
+    f = spec.split(":")
+    if f[0] == "autograd":
+        mode, kind = f[1], f[2]
+        shape = [s for s in AG_SHAPES if s[1] == kind][0]
+        c = AGCase(dev, shape[0], kind, shape[2], shape[3], shape[4], mode, si.config_seed(4), 0)
+        run = c.run
+    elif f[0] == "lowp":
+        # lowp:FORM:M:N, FORM bf16 / bf16_split / f16 / f16_split: the split of
+        # a square float A, then the precision-form TSM2R product 5 times
+        form, m, n = f[1], int(f[2]), int(f[3])
+        A = si.matrix(si.config_seed(3), si.STREAM_A, m, m, dtype=torch.float32, device=dev)
+        B = si.matrix(si.config_seed(3) + n, si.STREAM_B, m, n, dtype=torch.float32, device=dev)
+        S = tsm.split(A, form.split("_")[0], lo=form.endswith("split"))
+        del A
+        C = tsm.empty_colmajor(m, n, torch.float32, dev)
+        run = lambda: tsm.tsm2r(S, B, out=C)
+    elif f[0] == "grid":
+        # grid:DT:M:N, one TSM2R product of the square grid
+        dtype, m, n = torch.float64 if f[1] == "f64" else torch.float32, int(f[2]), int(f[3])
+        seed = si.config_seed(1)
+        A = si.matrix(seed, si.STREAM_A, m, m, dtype=dtype, device=dev)
+        B = si.matrix(seed + n, si.STREAM_B, m, n, dtype=dtype, device=dev)
+        C = tsm.empty_colmajor(m, n, dtype, dev)
+        run = lambda: tsm.tsm2r(A, B, out=C)
+    else:
+        op, dtype, m, k = f[0], torch.float64 if f[1] == "f64" else torch.float32, int(f[2]), int(f[3])
+        seed = si.config_seed(8)
+        X = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
+        B = si.matrix(seed, si.STREAM_B, k, k, dtype=dtype, device=dev)
+        if op == "tsm2l":
+            C = tsm.empty_colmajor(m, k, dtype, dev)
+            run = lambda: tsm.tsm2l(X, B, out=C)
+        elif op == "kmeans":
+            from paper_2002_03258_amd import kmeans
+            if len(f) > 4 and f[4] == "row":
+                X = X.contiguous()
+            run = lambda: kmeans.assign(X, B.t())
+        else:
+            raise SystemExit("--profile-op: tsm2l, kmeans, autograd, lowp or grid")
+    for _ in range(5):
+        run()
+    torch.cuda.synchronize()
+    print("launched %s 5 times" % spec, flush=True)
 
 
 def main():
@@ -579,14 +896,18 @@ def main():
     ap.add_argument("--profile-kernel", default=None, metavar="DTYPE:M:N",
                     help="only launch TSM2R on one workload of the grid 5 times "
                          "(for rocprofv3 counters), e.g. f64:30720:16")
-    ap.add_argument("--profile-op", default=None, metavar="OP:DTYPE:M:K[:LAYOUT]",
-                    help="only launch one TSM2L (tsm2l, B k x k) or K-means assignment "
-                         "(kmeans, k = n, LAYOUT col or row) product 5 times, for rocprofv3 "
-                         "counters, e.g. tsm2l:f64:16777216:16 or kmeans:f32:16777216:16:row")
+    ap.add_argument("--profile-op", default=None, metavar="SPEC",
+                    help="only launch one workload 5 times, for rocprofv3 counters: "
+                         "tsm2l:DT:M:K, kmeans:DT:M:K[:row], autograd:MODE:KIND, "
+                         "lowp:FORM:M:N or grid:DT:M:N, e.g. tsm2l:f64:16777216:16, "
+                         "autograd:f64:L or lowp:bf16_split:32768:8")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a 1 GiB device copy 5 times (counter calibration)")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="only measure the HBM ceilings (stream and TSM2L-pattern probes) and "
+                         "print them")
     ap.add_argument("--tune", action="store_true",
-                    help="autotune the plan of each TSM2R workload before the warmup steps")
+                    help="autotune the plan of each TSM2R grid workload before it is timed")
     ap.add_argument("--model-report", action="store_true",
                     help="only time every candidate plan of each TSM2R workload beside the "
                          "performance model's prediction, and print the table")
@@ -606,26 +927,11 @@ def main():
         torch.cuda.synchronize()
         print("copied 5 x %d bytes" % src.numel(), flush=True)
         return
+    if args.ceiling:
+        print(json.dumps({"ceilings": measure_ceilings(dev)}), flush=True)
+        return
     if args.profile_op:
-        f = args.profile_op.split(":")
-        op, dtype, m, k = f[0], torch.float64 if f[1] == "f64" else torch.float32, int(f[2]), int(f[3])
-        seed = si.config_seed(8)
-        X = si.matrix(seed, si.STREAM_A, m, k, dtype=dtype, device=dev)
-        B = si.matrix(seed, si.STREAM_B, k, k, dtype=dtype, device=dev)
-        if op == "tsm2l":
-            C = tsm.empty_colmajor(m, k, dtype, dev)
-            run = lambda: tsm.tsm2l(X, B, out=C)
-        elif op == "kmeans":
-            from paper_2002_03258_amd import kmeans
-            if len(f) > 4 and f[4] == "row":
-                X = X.contiguous()
-            run = lambda: kmeans.assign(X, B.t())
-        else:
-            raise SystemExit("--profile-op: tsm2l or kmeans")
-        for _ in range(5):
-            run()
-        torch.cuda.synchronize()
-        print("launched %s 5 times" % args.profile_op, flush=True)
+        profile_op(dev, args.profile_op)
         return
     if args.profile_kernel:
         dts, ms, ns = args.profile_kernel.split(":")
@@ -641,84 +947,45 @@ def main():
         print("launched %s 5 times on m = k = %d, n = %d" % (nn_kernel_name(dtype, m, n), m, n),
               flush=True)
         return
+    if args.model_report:
+        model_report(make_r_inputs(dev))
+        return
 
     t_setup = time.perf_counter()
-    calls = make_r_inputs(dev)
-    torch.cuda.synchronize()
-    print("inputs ready in %.1f s" % (time.perf_counter() - t_setup), file=sys.stderr, flush=True)
-    if args.model_report:
-        model_report(calls)
-        return
-    tuned = None
-    if args.tune:
-        tuned = {}
-        for c in calls:
-            r = tune.autotune_tsm2r(c["A"], c["B"], top=4)
-            tuned[c["workload"]] = {"slices": r["best"]["slices"], "tall": r["best"]["tall"],
-                                    "gain": r["best"]["gbs"] / r["default"]["gbs"]}
-            c["kernel"] = r["best"]["kernel"]
-        print("tuned %d workloads" % len(calls), file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        run_step(calls)
-    torch.cuda.synchronize()
-    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-            for _ in calls] for _ in range(args.steps)]
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for s in range(args.steps):
-        run_step(calls, evs[s])
-    e1.record()
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    step_bytes = sum(c["bytes"] for c in calls)
-    step_flops = sum(2.0 * c["m"] * c["k"] * c["n"] for c in calls)
-    value = step_bytes * args.steps / (total_ms / 1e3) / 1e9
-
-    per_kernel = {}
-    for s in range(args.steps):
-        for i, c in enumerate(calls):
-            d = per_kernel.setdefault(c["kernel"], {"t": 0.0, "b": 0.0, "n": 0, "wl": []})
-            d["t"] += evs[s][i][0].elapsed_time(evs[s][i][1]) / 1e3
-            d["b"] += c["bytes"]
-            d["n"] += 1
-            if s == 0:
-                d["wl"].append(c["workload"])
-    dom = max(per_kernel, key=lambda k: per_kernel[k]["t"])
-    d = per_kernel[dom]
-    achieved = d["b"] / d["t"] / 1e9
-    per_launch = d["b"] / d["n"]
-    traffic = traffic_for(dom, d["wl"])
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                "avg_launch_us": d["t"] / d["n"] * 1e6, "launches": d["n"],
-                "algorithmic_bytes_per_launch": per_launch,
-                "workloads": d["wl"], "traffic": traffic,
-                "traffic_over_algorithmic": (traffic / per_launch) if traffic else None}
+    h = headline(dev, args.steps, args.warmup, check=not args.no_check)
+    print("headline timed (setup + timing %.1f s)" % (time.perf_counter() - t_setup),
+          file=sys.stderr, flush=True)
+    clocks = gpu_clocks()
+    shapes = "; ".join("%s A %dx%d, B %dx%d" % (s, m, k, k, n) for s, _, m, k, n in AG_SHAPES)
     line = {
-        "metric": "achieved HBM GB/s (% peak), TSM2R/TSM2L fp64 vs bf16-split fwd+bwd at tol",
-        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
-        "data": "synthetic (seeded counter-based uniform[-1,1])",
-        "config": {"workload": "TSM2R plain FP64 and FP32: square A m=k in {10240,20480,30720}, "
-                               "B k x n with n in {2,4,8,16}, column-major (24 products per step)",
-                   "bytes_per_step": step_bytes, "frac_of_8TBps": value / PEAK_HBM_GBS,
-                   "frac_of_measured_read_ceiling": value / READ_CEILING_GBS,
-                   "gflop_per_s": step_flops * args.steps / (total_ms / 1e3) / 1e9},
-        "roofline": roofline,
+        "metric": METRIC, "value": h["value"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 vs bf16_split",
+        "data": "synthetic (seeded counter-based uniform[-1,1] A, B; N(0,1)-like dC)",
+        "config": {"workload": "autograd forward + backward of C = A*B (dA = dC*B^T, "
+                               "dB = A^T*dC), FP64 and bf16-split (A stored as bf16 hi + lo "
+                               "planes; B, C, dA, dB float32), " + shapes,
+                   "bytes_per_step": h["bytes_per_step"],
+                   "frac_of_8TBps": h["value"] / PEAK_HBM_GBS,
+                   "modes": h["modes"],
+                   "bf16_split_speedup_over_f64": h["bf16_split_speedup_over_f64"],
+                   "cases": h["cases"], "gpu_clocks_after_timing": clocks},
+        "roofline": h["roofline"],
+        "kernel_timing": h["kernel_timing"],
     }
-    line["model"] = model_summary(calls, evs, step_bytes, value)
-    line["config"]["gpu_clocks_after_timing"] = gpu_clocks()
-    if tuned is not None:
-        line["config"]["tuned_plans"] = tuned
-    if not args.no_check:
-        line["check"] = check_calls(calls)
-    del calls
-    torch.cuda.empty_cache()
+    if "err" in h:
+        line["err"] = h["err"]
+    ceil = measure_ceilings(dev)
+    line["ceilings"] = ceil
+    line["config"]["frac_of_measured_copy_ceiling"] = h["value"] / ceil["copy_GBps"]
+    print("ceilings measured", file=sys.stderr, flush=True)
     if not args.no_rows:
-        line["rows"] = attach_ceilings(rows_tsm2l(dev) + rows_lowp(dev) + rows_autograd(dev) +
-                                       rows_general(dev) + rows_kmeans(dev))
+        rows = []
+        for fn in (rows_tsm2r_grid, rows_tsm2l, rows_lowp, rows_autograd_more, rows_general,
+                   rows_kmeans):
+            rows += fn(dev, tune_plans=True) if (fn is rows_tsm2r_grid and args.tune) else fn(dev)
+            print("rows: %s done" % fn.__name__, file=sys.stderr, flush=True)
+        line["rows"] = attach_ceilings(rows, ceil)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

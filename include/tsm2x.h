@@ -275,6 +275,64 @@ int tsm2x_tsm2r_plan(int64_t m, int64_t k, int64_t n, int dtype, int* slices, in
  * -1..1. */
 int tsm2x_tsm2r_pin(int64_t m, int64_t k, int64_t n, int dtype, int slices, int tall);
 
+/* Per-launch kernel timing, for measuring each kernel of a sequence of
+ * calls while it runs (the paper times its kernels with GPU events, in its
+ * Experimental Evaluation; this is the same measurement, per kernel launch).
+ * Off until tsm2x_timing_start.  While on, every kernel launch of the library
+ * is bracketed by a HIP event pair recorded on the stream the kernel is
+ * launched on, and attributed to the kernel instance and to the tag last set
+ * by tsm2x_timing_tag (an arbitrary caller label, e.g. which step of a
+ * sequence is running; process-wide, so it also labels launches made from
+ * other host threads).  The recording adds one event record before and after
+ * each launch; with timing off a launch pays one atomic load.
+ *   tsm2x_timing_start    drop earlier records and rows, start recording;
+ *   tsm2x_timing_stop     stop recording (records kept);
+ *   tsm2x_timing_tag      set the tag of later launches;
+ *   tsm2x_timing_collect  wait for every recorded launch to finish, add it to
+ *                         one row per (kernel, tag), and return the number of
+ *                         rows.  Call it when no recorded work is being
+ *                         enqueued by another thread;
+ *   tsm2x_timing_row      row i: the kernel's name as rocprofv3 prints it
+ *                         (static storage, valid until the next start), its
+ *                         tag, launch count and summed launch time in
+ *                         milliseconds.  Returns -1 for i out of range.
+ * All return 0 unless stated. */
+int tsm2x_timing_start(void);
+int tsm2x_timing_stop(void);
+int tsm2x_timing_tag(int tag);
+int tsm2x_timing_collect(void);
+int tsm2x_timing_row(int i, const char** kernel, int* tag, int64_t* launches,
+                     double* total_ms);
+
+/* Bandwidth probes (measurement support, not part of any product): the HBM
+ * ceilings the products are compared with, measured with the products' own
+ * 16-byte non-temporal load and store forms.  The paper compares achieved
+ * bandwidth with the device's peak (Performance Metrics Estimation, and the
+ * bandwidth utilisation of its Experimental Evaluation); these give the
+ * ceiling a real access pattern reaches on this device.
+ *
+ * tsm2x_probe_stream: kind 0 reads `bytes` of src (dst: at least 16 bytes,
+ * normally left untouched), kind 1 copies `bytes` from src to dst, kind 2
+ * writes `bytes` of a pattern to dst (src unused).  Each wavefront moves one
+ * 4 KB piece per iteration of a grid-stride loop; `blocks` 256-thread
+ * workgroups (0: 65536), never more than the pieces need.  Pointers 16-byte
+ * aligned, bytes a multiple of 16.  Arguments: 1 kind, 2 src, 3 dst,
+ * 4 bytes, 5 blocks, 6 stream.
+ *
+ * tsm2x_probe_tiles: the access pattern of the TSM2L kernel without its
+ * arithmetic.  X is column-major m-by-kin, O column-major m-by-nout (F64 or
+ * F32; 1 <= kin, nout <= 32); a persistent grid of `blocks` workgroups
+ * (0: as many as are resident at once) walks the row tiles the TSM2L kernel
+ * walks for (kin, nout), loading every element of X once and storing every
+ * element of O once.  O receives X's columns in a fixed mapping (output
+ * column 16t + j of a tile takes one input column of the same rows); only
+ * the bytes moved matter.  Arguments: 1 m, 2 kin, 3 nout, 4 X, 5 ldx, 6 O,
+ * 7 ldo, 8 dtype, 9 blocks, 10 stream. */
+int tsm2x_probe_stream(int kind, const void* src, void* dst, int64_t bytes, int64_t blocks,
+                       void* stream);
+int tsm2x_probe_tiles(int64_t m, int kin, int nout, const void* X, int64_t ldx, void* O,
+                      int64_t ldo, int dtype, int64_t blocks, void* stream);
+
 /* Static description of an error code (never NULL). */
 const char* tsm2x_error_string(int code);
 

@@ -17,7 +17,8 @@ unblocked, sequential sums) with numpy marshalling:
 - :func:`t2_threshold` -- the paper's boundary between the memory-bound and
   compute-bound regimes (Design of TSM2R, "Determine compute-bound or
   memory-bound"): t2 = PeakPerf / PeakBand * bytes_per_element.
-- :func:`normwise_error` -- ||C - C_ref||_F / ||C_ref||_F.
+- :func:`normwise_error` -- ||C - C_ref||_F / ||C_ref||_F, and
+  :func:`componentwise_error` -- max |C - C_ref| / (|A||B|), elementwise.
 - :func:`matmul_dot2` -- the same product with every sum taken by Dot2
   (Ogita, Rump, Oishi 2005), as accurate as a sum in twice double precision:
   it measures the rounding error of :func:`matmul` itself at full size.
@@ -247,6 +248,23 @@ def t2_threshold(peak_perf_gflops: float, peak_bw_gbs: float,
     per pass, A-streaming is memory-bound (Design of TSM2R, "Determine
     compute-bound or memory-bound", the equation for t2^threshold)."""
     return peak_perf_gflops / peak_bw_gbs * bytes_per_elem
+
+
+def componentwise_error(C, C_ref, A, B) -> float:
+    """max_ij |C - C_ref|_ij / (|A| |B|)_ij for C_ref ~ A*B: the error in the
+    units of the standard bound |fl(A*B) - A*B| <= gamma_k |A| |B| (Higham,
+    Accuracy and Stability of Numerical Algorithms, eq. 3.13).  An entry with
+    (|A||B|)_ij = 0 counts 0 if it is exact and infinity otherwise."""
+    C = np.asarray(C, dtype=np.float64)
+    C_ref = np.asarray(C_ref, dtype=np.float64)
+    den = matmul(np.abs(np.asarray(A, dtype=np.float64)), np.abs(np.asarray(B, dtype=np.float64)))
+    diff = np.abs(C - C_ref)
+    if diff.size == 0:
+        return 0.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(den > 0, diff / np.where(den > 0, den, 1.0),
+                     np.where(diff > 0, np.inf, 0.0))
+    return float(np.max(r))
 
 
 def normwise_error(C, C_ref) -> float:

@@ -19,7 +19,8 @@ __all__ = ["tsm2r", "tsm2l", "gemm", "tsmttsm", "grad_a", "grad_b", "tsm2l_backw
            "empty_colmajor", "workspace_size", "kernel_name", "tsm2r_plan", "pin_tsm2r",
            "unpin_tsm2r", "matmul", "TSMMatmul", "TSMError", "F64", "F32", "BF16", "F16",
            "BF16_SPLIT", "F16_SPLIT", "OP_TSM2R", "OP_TSM2L", "OP_GRAD_A", "OP_GRAD_B",
-           "OP_TSM2R_ROWMAJOR"]
+           "OP_TSM2R_ROWMAJOR", "timing_start", "timing_stop", "timing_tag", "timing_collect",
+           "probe_stream", "probe_tiles"]
 
 _DT = {torch.float64: F64, torch.float32: F32}
 
@@ -60,9 +61,24 @@ class SplitA:
     ``planes`` is one device buffer of shape (nplanes, k, ld); plane p holds
     the column-major m x k matrix ``planes[p].t()[:m]``."""
 
-    def __init__(self, planes: torch.Tensor, m: int, k: int, fmt: str, has_lo: bool):
+    def __init__(self, planes: torch.Tensor, m: int, k: int, fmt: str, has_lo: bool,
+                 source: torch.Tensor | None = None):
         self.planes, self.m, self.k, self.fmt, self.has_lo = planes, m, k, fmt, has_lo
         self.ld = planes.shape[2]
+        # the float matrix the planes were split from (not copied), and its
+        # version counter then: `matmul` differentiates with respect to it
+        self.source = source
+        self.source_version = source._version if source is not None else None
+
+    def check_source(self) -> torch.Tensor:
+        """The float matrix these planes were split from; raises if it was
+        modified in place since (the planes would no longer hold its values)."""
+        if self.source is None:
+            raise ValueError("this SplitA was made without its source matrix")
+        if self.source._version != self.source_version:
+            raise ValueError("the source of this SplitA was modified after the split; "
+                             "split it again")
+        return self.source
 
     @property
     def hi(self) -> torch.Tensor:
@@ -96,6 +112,11 @@ def split(A: torch.Tensor, fmt: str = "bf16", lo: bool = True) -> SplitA:
     _check_device(A)
     if A.dtype != torch.float32:
         raise ValueError("split expects a float32 matrix")
+    if A.dim() != 2:
+        raise ValueError("split expects a matrix")
+    if fmt not in ("bf16", "f16"):
+        raise ValueError("fmt must be 'bf16' or 'f16'")
+    src = A
     A = colmajor(A)
     m, k = A.shape
     ld = max(8, (m + 7) // 8 * 8)
@@ -104,7 +125,7 @@ def split(A: torch.Tensor, fmt: str = "bf16", lo: bool = True) -> SplitA:
     lo_ptr = planes[1].data_ptr() if lo else None
     _lib.call("tsm2x_split", m, k, A.data_ptr(), _ld(A), planes[0].data_ptr(), lo_ptr, ld,
               0 if fmt == "bf16" else 1, _stream())
-    return SplitA(planes, m, k, fmt, lo)
+    return SplitA(planes, m, k, fmt, lo, source=src)
 
 
 def _layout(x: torch.Tensor):
@@ -128,6 +149,26 @@ def _operand(x: torch.Tensor):
     return x, lay[0], lay[1]
 
 
+def _check_matrix(name: str, x: torch.Tensor, rows: int, cols: int, dtype) -> None:
+    if x.dim() != 2 or tuple(x.shape) != (rows, cols):
+        raise ValueError("%s must be %d x %d, got %s" % (name, rows, cols, tuple(x.shape)))
+    if x.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, x.dtype))
+
+
+def _check_out(out: torch.Tensor, rows: int, cols: int, dtype, device) -> None:
+    if not is_colmajor(out) or tuple(out.shape) != (rows, cols) or out.dtype != dtype:
+        raise ValueError("out must be a column-major %d x %d %s tensor" % (rows, cols, dtype))
+    if out.device != device:
+        raise ValueError("out must be on %s" % (device,))
+
+
+def _plain_dtype(x: torch.Tensor) -> int:
+    if x.dtype not in _DT:
+        raise ValueError("expected a float64 or float32 tensor, got %s" % (x.dtype,))
+    return _DT[x.dtype]
+
+
 def _ws(workspace):
     return (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
         if workspace is not None else (None, 0)
@@ -145,7 +186,9 @@ def _product(fn: str, A, B: torch.Tensor, out, beta: float, workspace) -> torch.
         _check_device(A, B)
         if B.dtype != A.dtype:
             raise ValueError("A and B must have the same dtype")
-        code, cdt, dev = _DT[A.dtype], A.dtype, A.device
+        if A.dim() != 2 or B.dim() != 2:
+            raise ValueError("A and B must be matrices")
+        code, cdt, dev = _plain_dtype(A), A.dtype, A.device
         m, k = A.shape
         A, ta, lda = _operand(A)
         a_ptr = A.data_ptr()
@@ -157,8 +200,8 @@ def _product(fn: str, A, B: torch.Tensor, out, beta: float, workspace) -> torch.
         if beta != 0:
             raise ValueError("beta != 0 accumulates into `out`, which must be given")
         out = empty_colmajor(m, n, cdt, dev)
-    elif not is_colmajor(out) or tuple(out.shape) != (m, n) or out.dtype != cdt:
-        raise ValueError("out must be a column-major %d x %d %s tensor" % (m, n, cdt))
+    else:
+        _check_out(out, m, n, cdt, dev)
     ws, wsb = _ws(workspace)
     _lib.call(fn, ta, tb, m, k, n, a_ptr, lda, B.data_ptr(), ldb, float(beta), out.data_ptr(),
               _ld(out), code, ws, wsb, _stream())
@@ -198,13 +241,18 @@ def tsmttsm(A: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,
 
 
 def grad_a(dC: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """dA = dC*B^T (dC m x n, B k x n, n <= 32)."""
+    """dA = dC*B^T (dC m x n, B k x n, n <= 32, same dtype)."""
     _check_device(dC, B)
-    dt = _DT[dC.dtype]
-    dC = colmajor(dC)
-    B = colmajor(B)
+    dt = _plain_dtype(dC)
+    if dC.dim() != 2 or B.dim() != 2:
+        raise ValueError("dC and B must be matrices")
     m, n = dC.shape
     k = B.shape[0]
+    _check_matrix("B", B, k, n, dC.dtype)
+    if out is not None:
+        _check_out(out, m, k, dC.dtype, dC.device)
+    dC = colmajor(dC)
+    B = colmajor(B)
     dA = out if out is not None else empty_colmajor(m, k, dC.dtype, dC.device)
     _lib.call("tsm_grad_a", m, k, n, dC.data_ptr(), _ld(dC), B.data_ptr(), _ld(B),
               dA.data_ptr(), _ld(dA), dt, _stream())
@@ -213,12 +261,18 @@ def grad_a(dC: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None) -
 
 def grad_b(A, dC: torch.Tensor, out: torch.Tensor | None = None,
            workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """dB = A^T*dC (A m x k or a SplitA, dC m x n, n <= 32)."""
+    """dB = A^T*dC (A m x k or a SplitA, dC m x n, n <= 32; dC float32 for a
+    SplitA, else of A's dtype)."""
     if isinstance(A, SplitA):
         _check_device(A.planes, dC)
         m, k = A.shape
-        dC = colmajor(dC)
+        if dC.dim() != 2:
+            raise ValueError("dC must be a matrix")
+        _check_matrix("dC", dC, m, dC.shape[1], torch.float32)
         n = dC.shape[1]
+        if out is not None:
+            _check_out(out, k, n, torch.float32, dC.device)
+        dC = colmajor(dC)
         dB = out if out is not None else empty_colmajor(k, n, torch.float32, dC.device)
         ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
             if workspace is not None else (None, 0)
@@ -226,11 +280,16 @@ def grad_b(A, dC: torch.Tensor, out: torch.Tensor | None = None,
                   dB.data_ptr(), _ld(dB), A.dtype_code, ws, wsb, _stream())
         return dB
     _check_device(A, dC)
-    dt = _DT[A.dtype]
-    A = colmajor(A)
-    dC = colmajor(dC)
+    dt = _plain_dtype(A)
+    if A.dim() != 2 or dC.dim() != 2:
+        raise ValueError("A and dC must be matrices")
     m, k = A.shape
     n = dC.shape[1]
+    _check_matrix("dC", dC, m, n, A.dtype)
+    if out is not None:
+        _check_out(out, k, n, A.dtype, A.device)
+    A = colmajor(A)
+    dC = colmajor(dC)
     dB = out if out is not None else empty_colmajor(k, n, A.dtype, A.device)
     ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) \
         if workspace is not None else (None, 0)
@@ -252,12 +311,18 @@ def tsm2l_backward(A, B: torch.Tensor, dC: torch.Tensor):
         m, k = A.shape
     else:
         _check_device(A, B, dC)
-        code, odt, dev = _DT[A.dtype], A.dtype, A.device
+        code, odt, dev = _plain_dtype(A), A.dtype, A.device
+        if A.dim() != 2:
+            raise ValueError("A must be a matrix")
         A = colmajor(A)
         m, k = A.shape
         a_ptr, lda = A.data_ptr(), _ld(A)
-    B, dC = colmajor(B), colmajor(dC)
+    if B.dim() != 2 or dC.dim() != 2:
+        raise ValueError("B and dC must be matrices")
     n = B.shape[1]
+    _check_matrix("B", B, k, n, odt)
+    _check_matrix("dC", dC, m, n, odt)
+    B, dC = colmajor(B), colmajor(dC)
     dA = empty_colmajor(m, k, odt, dev)
     dB = empty_colmajor(k, n, odt, dev)
     _lib.call("tsm2l_backward", m, k, n, a_ptr, lda, B.data_ptr(), _ld(B),
@@ -300,6 +365,74 @@ def pin_tsm2r(m: int, k: int, n: int, dtype: int, slices: int = 0, tall: int = -
 def unpin_tsm2r(m: int, k: int, n: int, dtype: int) -> None:
     """Remove a pinned TSM2R plan."""
     pin_tsm2r(m, k, n, dtype, 0, -1)
+
+
+def timing_start() -> None:
+    """Start timing every kernel launch of the library (HIP events on each
+    launch's stream); earlier records are dropped."""
+    _lib.call("tsm2x_timing_start")
+
+
+def timing_stop() -> None:
+    """Stop recording launches (the records are kept for timing_collect)."""
+    _lib.call("tsm2x_timing_stop")
+
+
+def timing_tag(tag: int) -> None:
+    """Label later launches with ``tag`` (process-wide, all host threads)."""
+    _lib.call("tsm2x_timing_tag", int(tag))
+
+
+def timing_collect() -> list:
+    """Wait for the recorded launches and return one dict per (kernel, tag):
+    ``kernel`` (as rocprofv3 names it), ``tag``, ``launches``, ``total_ms``."""
+    import ctypes
+    L = _lib.lib()
+    nrows = L.tsm2x_timing_collect()
+    out = []
+    for i in range(nrows):
+        name, tag = ctypes.c_char_p(), ctypes.c_int()
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        if L.tsm2x_timing_row(i, ctypes.byref(name), ctypes.byref(tag), ctypes.byref(n),
+                              ctypes.byref(ms)) == 0:
+            out.append({"kernel": name.value.decode(), "tag": tag.value,
+                        "launches": n.value, "total_ms": ms.value})
+    return out
+
+
+def probe_stream(kind: str, dst: torch.Tensor, src: torch.Tensor | None = None,
+                 nbytes: int | None = None, blocks: int = 0) -> None:
+    """Bandwidth probe (measurement support): "read" nbytes of src, "copy"
+    src to dst, or "write" dst, with 16-byte non-temporal accesses."""
+    kinds = {"read": 0, "copy": 1, "write": 2}
+    if kind not in kinds:
+        raise ValueError("kind must be read, copy or write")
+    _check_device(dst)
+    if src is not None:
+        _check_device(src)
+    if nbytes is None:
+        nbytes = (src if kind == "read" else dst).numel() * \
+            (src if kind == "read" else dst).element_size()
+    if kind != "read" and nbytes > dst.numel() * dst.element_size():
+        raise ValueError("dst is smaller than nbytes")
+    if kind != "write" and (src is None or nbytes > src.numel() * src.element_size()):
+        raise ValueError("src is missing or smaller than nbytes")
+    if kind == "read" and dst.numel() * dst.element_size() < 16:
+        raise ValueError("dst must hold at least 16 bytes")
+    _lib.call("tsm2x_probe_stream", kinds[kind], src.data_ptr() if src is not None else None,
+              dst.data_ptr(), int(nbytes), int(blocks), _stream())
+
+
+def probe_tiles(X: torch.Tensor, O: torch.Tensor, blocks: int = 0) -> None:
+    """Bandwidth probe (measurement support): the TSM2L kernel's access
+    pattern without its arithmetic, X (m x kin) read once and O (m x nout)
+    written once, both column-major float64 or float32."""
+    _check_device(X, O)
+    if not (is_colmajor(X) and is_colmajor(O)) or X.shape[0] != O.shape[0] or \
+            X.dtype != O.dtype:
+        raise ValueError("X and O must be column-major with the same rows and dtype")
+    _lib.call("tsm2x_probe_tiles", X.shape[0], X.shape[1], O.shape[1], X.data_ptr(), _ld(X),
+              O.data_ptr(), _ld(O), _plain_dtype(X), int(blocks), _stream())
 
 
 from .autograd import TSMMatmul, matmul  # noqa: E402,F401

@@ -71,6 +71,17 @@ def lib():
             L.tsm2x_version.argtypes = []
             L.tsm2x_finalize.argtypes = []
             L.tsm2x_finalize.restype = None
+            for f in ("tsm2x_timing_start", "tsm2x_timing_stop", "tsm2x_timing_tag",
+                      "tsm2x_timing_collect"):
+                getattr(L, f).argtypes = [i32] if f == "tsm2x_timing_tag" else []
+                getattr(L, f).restype = i32
+            L.tsm2x_timing_row.argtypes = [i32, ctypes.POINTER(ctypes.c_char_p), pi, p64,
+                                           ctypes.POINTER(ctypes.c_double)]
+            L.tsm2x_timing_row.restype = i32
+            L.tsm2x_probe_stream.argtypes = [i32, vp, vp, i64, i64, vp]
+            L.tsm2x_probe_stream.restype = i32
+            L.tsm2x_probe_tiles.argtypes = [i64, i32, i32, vp, i64, vp, i64, i32, i64, vp]
+            L.tsm2x_probe_tiles.restype = i32
             for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a",
                       "tsm_grad_b",
                       "tsm2l_backward", "tsm2x_split", "tsm2x_version", "tsm2x_tsm2r_plan",
@@ -92,5 +103,7 @@ EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a",
            "tsm2l_backward", "tsm_kmeans_assign",
            "tsm2x_split",
            "tsm2x_workspace_size", "tsm2x_kernel_name", "tsm2x_tsm2r_plan", "tsm2x_tsm2r_pin",
+           "tsm2x_timing_start", "tsm2x_timing_stop", "tsm2x_timing_tag", "tsm2x_timing_collect",
+           "tsm2x_timing_row", "tsm2x_probe_stream", "tsm2x_probe_tiles",
            "tsm2x_error_string", "tsm2x_last_hip_error",
            "tsm2x_version", "tsm2x_finalize")

@@ -118,7 +118,8 @@ RTPlan plan_rowtile(int64_t m, int64_t kin, int64_t nout, int dt, int cus) {
     const int es = esize(dt);
     const int RL = 16 / es;
     P.kp = kin <= 8 ? 8 : (kin <= 16 ? 16 : 32);
-    const int RG = (P.kp == 32 && nout > 16) ? 1 : 2;
+    // row groups per lane of the instance rowtile_dispatch launches
+    const int RG = P.kp == 8 ? 2 : (P.kp == 16 && nout > 16 ? 2 : 1);
     const int64_t TR = 16 * RL * RG;
     const int64_t ntiles = cdiv(m, TR);
     const int64_t wblocks = cdiv(ntiles, 4);
@@ -166,7 +167,7 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     TNPlan P{};
     // output tiles per workgroup: two share each staged Y tile when there
     // are several column groups (Y is then re-read by every group)
-    P.ct = (plain_dtype(dt) && ncols > 16) ? (int)env_int("TSM2X_TN_CT", 2) : 1;
+    P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", 2) : 1;
     if (P.ct != 1 && P.ct != 2) P.ct = 1;
     // rows per wavefront loop iteration: G stages of 16*RL rows for the
     // float kernels (one stage with two output tiles), 128 for the 16-bit form
@@ -266,23 +267,36 @@ int check_ex(int transA, int transB, int64_t m, int64_t k, int64_t n, const void
 // a multiple of 16 bytes so the kernels' 16-byte B loads apply.
 int64_t bt_ld(int64_t k, int ce) { return cdiv(k, 16 / ce) * (16 / ce); }
 
-// Workspace of a TSM2R-kernel product of at most 32 columns: the split
-// partials of its plan, then room for B when it is given transposed.
-size_t tsm2r_ws(int transA, int64_t m, int64_t k, int64_t n, int dtype, bool transB) {
+// Bytes of split partials of a TSM2R-kernel product of at most 32 columns,
+// for the kernel instance the call launches (`vec`: 16-byte loads of A).
+size_t tsm2r_part(int transA, int64_t m, int64_t k, int64_t n, int dtype, bool vec) {
     const int cus = cu_count();
-    const int ce = plain_dtype(dtype) ? esize(dtype) : 4;
-    size_t part = 0;
     if (!plain_dtype(dtype)) {
         NNPlan P{};
-        plan_tsm2r_lp(m, k, n, dtype, cus, true, &P);
-        part = P.ws;
-    } else if (transA) {
-        part = plan_tn(k, m, n, dtype, cus).ws;
-    } else {
-        NNPlan P{};
-        if (!plan_nn(m, k, n, dtype, cus, true, &P)) part = P.ws;
+        plan_tsm2r_lp(m, k, n, dtype, cus, vec, &P);
+        return P.ws;
     }
-    return align256(part) + (transB ? (size_t)bt_ld(k, ce) * n * ce : 0);
+    if (transA) return plan_tn(k, m, n, dtype, cus).ws;
+    NNPlan P{};
+    return plan_nn(m, k, n, dtype, cus, vec, &P) ? 0 : P.ws;
+}
+
+// Workspace of a TSM2R-kernel product of at most 32 columns: the split
+// partials, then room for B when it is given transposed (plain types) or for
+// B's packed 16-bit terms (precision form, B read in either order).
+size_t tsm2r_ws(int transA, int64_t m, int64_t k, int64_t n, int dtype, bool transB, bool vec) {
+    const size_t part = align256(tsm2r_part(transA, m, k, n, dtype, vec));
+    if (!plain_dtype(dtype)) return part + lp_bterms_bytes(k, n);
+    const int ce = esize(dtype);
+    return part + (transB ? (size_t)bt_ld(k, ce) * n * ce : 0);
+}
+
+// The most any plan of the call can need (the query does not know A's
+// alignment, which picks the kernel instance).
+size_t tsm2r_ws_max(int transA, int64_t m, int64_t k, int64_t n, int dtype, bool transB) {
+    const size_t a = tsm2r_ws(transA, m, k, n, dtype, transB, true);
+    const size_t b = tsm2r_ws(transA, m, k, n, dtype, transB, false);
+    return a > b ? a : b;
 }
 
 // C := beta*C + op(A)*op(B) on validated arguments.  `lform` asks for the TSM2L
@@ -328,32 +342,38 @@ int product(bool lform, int transA, int transB, int64_t m, int64_t k, int64_t n,
         if (launch_rowtile(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("rowtile_kernel");
     }
-    // TSM2R kernels; workspace = [split partials][B copied column-major]
+    // TSM2R kernels; workspace = [split partials][B copied column-major, or
+    // B's packed 16-bit terms for the precision form]
+    const bool avec = vec_ok(A, lda, plain_dtype(dtype) ? esize(dtype) : 2);
     void* w = nullptr;
-    int rc = get_ws(tsm2r_ws(transA, m, k, n, dtype, transB), ws, ws_bytes, &w);
+    int rc = get_ws(tsm2r_ws(transA, m, k, n, dtype, transB, avec), ws, ws_bytes, &w);
     if (rc) return rc;
-    const void* Bk = B;
-    int64_t ldbk = ldb;
-    if (transB) {
-        void* bc = (char*)w + (tsm2r_ws(transA, m, k, n, dtype, false));
-        launch_transpose(k, n, B, ldb, bc, bt_ld(k, ce), cdt, st);
-        rc = check_launch("transpose_kernel");
-        if (rc) return rc;
-        Bk = bc;
-        ldbk = bt_ld(k, ce);
-    }
     if (!plain_dtype(dtype)) {
         // A: 16-bit hi plane (and lo plane lda*k elements after it); B, C float
         NNPlan P{};
-        plan_tsm2r_lp(m, k, n, dtype, cus, vec_ok(A, lda, 2), &P);
+        plan_tsm2r_lp(m, k, n, dtype, cus, avec, &P);
+        void* bt = (char*)w + align256(P.ws);
+        launch_split_b(k, n, (const float*)B, transB ? ldb : 1, transB ? 1 : ldb, dtype, bt, st);
+        rc = check_launch("split_b_kernel");
+        if (rc) return rc;
         LaunchNN L{};
         L.fn = P.fn;
-        L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = Bk; L.ldb = ldbk; L.C = C;
+        L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = bt; L.ldb = 0; L.C = C;
         L.ldc = ldc; L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S;
         L.kslice = P.kslice; L.beta = beta;
         if (P.S > 1) L.part = (double*)w;
         launch_tsm2r_lp(L, dtype, st);
         return check_launch("tsm2r_lp_kernel");
+    }
+    const void* Bk = B;
+    int64_t ldbk = ldb;
+    if (transB) {
+        void* bc = (char*)w + align256(tsm2r_part(transA, m, k, n, dtype, avec));
+        launch_transpose(k, n, B, ldb, bc, bt_ld(k, ce), cdt, st);
+        rc = check_launch("transpose_kernel");
+        if (rc) return rc;
+        Bk = bc;
+        ldbk = bt_ld(k, ce);
     }
     if (transA) {
         // A given transposed is the column-major k x m matrix X = A^T (ld lda):
@@ -496,9 +516,14 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     return check_launch("tn_kernel");
 }
 
-int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
-                   int64_t ldb, const void* dC, int64_t lddc, void* dA, int64_t ldda, void* dB,
-                   int64_t lddb, int dtype, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks of tsm2l_backward (positions 1..14).
+int check_bwd(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
+              int64_t ldb, const void* dC, int64_t lddc, const void* dA, int64_t ldda,
+              const void* dB, int64_t lddb, int dtype) {
     if (m < 0) return -1;
     if (k < 0) return -2;
     if (n < 0) return -3;
@@ -514,8 +539,17 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, 
     if (lddb < (k > 1 ? k : 1)) return -13;
     if (!valid_dtype(dtype)) return -14;
     if (k > 32 || n > 32) return TSM_ERR_UNSUPPORTED;
+    return TSM_SUCCESS;
+}
+
+// The fused backward on checked arguments; `part` supplies the dB partials
+// (one k x n double block per workgroup): part(need) returns the buffer for
+// `need` bytes, or null with *rc set.
+template <typename PartFn>
+int run_bwd(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
+            int64_t ldb, const void* dC, int64_t lddc, void* dA, int64_t ldda, void* dB,
+            int64_t lddb, int dtype, hipStream_t st, PartFn part) {
     if (k == 0) return TSM_SUCCESS;
-    hipStream_t st = (hipStream_t)stream;
     const int odt = plain_dtype(dtype) ? dtype : TSM_F32;      // B, dC, dA, dB
     if (m == 0 || n == 0) {
         // dA (m x k) is zero when n == 0; dB (k x n) is zero when m == 0
@@ -529,12 +563,28 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, 
     int64_t blocks = 0;
     launch_tsm2l_bwd(L, dtype, &blocks, st, true);
     const size_t need = (size_t)blocks * (k <= 16 ? 16 : 32) * (n <= 16 ? 16 : 32) * 8;
-    void* w = nullptr;
-    int rc = get_ws(need, ws, ws_bytes, &w);
+    int rc = TSM_SUCCESS;
+    L.part = (double*)part(need, &rc);
     if (rc) return rc;
-    L.part = (double*)w;
     launch_tsm2l_bwd(L, dtype, &blocks, st, false);
     return check_launch("tsm2l_bwd_kernel");
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, const void* dC, int64_t lddc, void* dA, int64_t ldda, void* dB,
+                   int64_t lddb, int dtype, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_bwd(m, k, n, A, lda, B, ldb, dC, lddc, dA, ldda, dB, lddb, dtype);
+    if (rc) return rc;
+    return run_bwd(m, k, n, A, lda, B, ldb, dC, lddc, dA, ldda, dB, lddb, dtype,
+                   (hipStream_t)stream, [&](size_t need, int* prc) -> void* {
+                       void* w = nullptr;
+                       *prc = get_ws(need, ws, ws_bytes, &w);
+                       return w;
+                   });
 }
 
 int tsm2x_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
@@ -586,9 +636,9 @@ size_t tsm2x_workspace_size(int op, int64_t m, int64_t k, int64_t n, int dtype) 
     const int64_t np = n < 32 ? n : 32;      // panels of 32 columns reuse one workspace
     // products: enough for a B given transposed as well
     switch (op) {
-        case TSM_OP_TSM2R: return tsm2r_ws(0, m, k, np, dtype, true);
-        case TSM_OP_TSM2R_ROWMAJOR: return plain_dtype(dtype) ? tsm2r_ws(1, m, k, np, dtype, true) : 0;
-        case TSM_OP_TSM2L: return k <= 32 ? 0 : tsm2r_ws(0, m, k, np, dtype, true);
+        case TSM_OP_TSM2R: return tsm2r_ws_max(0, m, k, np, dtype, true);
+        case TSM_OP_TSM2R_ROWMAJOR: return plain_dtype(dtype) ? tsm2r_ws_max(1, m, k, np, dtype, true) : 0;
+        case TSM_OP_TSM2L: return k <= 32 ? 0 : tsm2r_ws_max(0, m, k, np, dtype, true);
         case TSM_OP_GRAD_B: return n <= 32 ? plan_tn(m, k, n, dtype, cu_count()).ws : 0;
         default: return 0;
     }

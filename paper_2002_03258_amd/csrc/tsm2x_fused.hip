@@ -301,11 +301,11 @@ static int bwd_launch(const LaunchBwd& L, int64_t* blocks_out, hipStream_t st, b
     const uint16_t* alo = ASPLIT ? (const uint16_t*)L.A + L.lda * L.k : nullptr;
     dim3 g((unsigned)bx), b(256);
     if (vec)
-        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, true, AF, ASPLIT>), g, b, 0, st,
+        TSM_LAUNCH((tsm2l_bwd_kernel<T, NTK, NTN, RG, true, AF, ASPLIT>), g, b, 0, st,
                            L.m, (int)L.k, (int)L.n, L.A, alo, L.lda, (const T*)L.B, L.ldb,
                            (const T*)L.dC, L.lddc, (T*)L.dA, L.ldda, L.part);
     else
-        hipLaunchKernelGGL((tsm2l_bwd_kernel<T, NTK, NTN, RG, false, AF, ASPLIT>), g, b, 0, st,
+        TSM_LAUNCH((tsm2l_bwd_kernel<T, NTK, NTN, RG, false, AF, ASPLIT>), g, b, 0, st,
                            L.m, (int)L.k, (int)L.n, L.A, alo, L.lda, (const T*)L.B, L.ldb,
                            (const T*)L.dC, L.lddc, (T*)L.dA, L.ldda, L.part);
     if (hipGetLastError() != hipSuccess) return 1;

@@ -5,6 +5,27 @@
 
 namespace tsm {
 
+// Per-launch timing, off unless the caller turned it on (tsm2x_timing_start):
+// a HIP event pair recorded on the launch's own stream around one kernel
+// launch, attributed to the kernel and to the caller's current tag.
+struct LaunchTimer {
+    LaunchTimer(const void* fn, hipStream_t st);
+    ~LaunchTimer();
+    int slot;                // -1 when timing is off
+    hipStream_t st;
+};
+
+}  // namespace tsm
+
+// hipLaunchKernelGGL with the launch timed when timing is on
+#define TSM_LAUNCH(KERNEL, GRID, BLOCK, LDS, ST, ...)                          \
+    do {                                                                       \
+        ::tsm::LaunchTimer tsm_launch_timer_((const void*)(KERNEL), (ST));     \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, ST, __VA_ARGS__);         \
+    } while (0)
+
+namespace tsm {
+
 enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3, DT_BF16_SPLIT = 4, DT_F16_SPLIT = 5 };
 
 // Output rows per wavefront of the tn kernel for NP padded output columns:
@@ -80,7 +101,13 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
 
 // Low-precision storage forms of A (bf16 / f16, single or split planes).
 int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P);
+// L.B: the packed terms of B written by launch_split_b (L.ldb unused)
 int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st);
+// B (k x n <= 32, B(j, p) = B[j*bsj + p*bsp]) split into three 16-bit terms
+// packed as the matrix-core operand of tsm2r_lp, lp_bterms_bytes(k, n) bytes
+size_t lp_bterms_bytes(int64_t k, int64_t n);
+int launch_split_b(int64_t k, int64_t n, const float* B, int64_t bsj, int64_t bsp, int dtype,
+                   void* out, hipStream_t st);
 int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, void* lo,
                  int64_t ldh, int fmt, hipStream_t st);
 // B(j, p) = B[j*bsj + p*bsp]

@@ -363,11 +363,11 @@ static int rowtile_launch_pf(const LaunchRT& L, bool vec, hipStream_t st) {
     if (bx < 1) bx = 1;
     dim3 grid((unsigned)bx, (unsigned)L.blocks_y), block(256);
     if (vec)
-        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, true, PF>), grid, block, 0, st, L.m,
+        TSM_LAUNCH((rowtile_kernel<T, KS, NT16, RG, true, PF>), grid, block, 0, st, L.m,
                            L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
                            (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
     else
-        hipLaunchKernelGGL((rowtile_kernel<T, KS, NT16, RG, false, PF>), grid, block, 0, st, L.m,
+        TSM_LAUNCH((rowtile_kernel<T, KS, NT16, RG, false, PF>), grid, block, 0, st, L.m,
                            L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in,
                            L.ys_out, (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
     return 0;
@@ -413,15 +413,15 @@ static int tn_launch(const LaunchTN& L, bool vec, hipStream_t st) {
     const int64_t gx = L.groups / CT;
     dim3 grid((unsigned)gx, (unsigned)L.S), block(256);
     if (vec && gx > 1)
-        hipLaunchKernelGGL((tn_kernel<T, NT16, G, CT, true, true>), grid, block, 0, st, L.R,
+        TSM_LAUNCH((tn_kernel<T, NT16, G, CT, true, true>), grid, block, 0, st, L.R,
                            L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
                            L.ldo, L.rslice, L.part, L.beta);
     else if (vec)
-        hipLaunchKernelGGL((tn_kernel<T, NT16, G, CT, true, false>), grid, block, 0, st, L.R,
+        TSM_LAUNCH((tn_kernel<T, NT16, G, CT, true, false>), grid, block, 0, st, L.R,
                            L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
                            L.ldo, L.rslice, L.part, L.beta);
     else
-        hipLaunchKernelGGL((tn_kernel<T, NT16, G, CT, false, false>), grid, block, 0, st, L.R,
+        TSM_LAUNCH((tn_kernel<T, NT16, G, CT, false, false>), grid, block, 0, st, L.R,
                            L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
                            L.ldo, L.rslice, L.part, L.beta);
     return 0;
@@ -468,17 +468,17 @@ int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t
     const dim3 g((unsigned)blocks), b(256);
     if (dtype == DT_F64) {
         if (wide)
-            hipLaunchKernelGGL((split_reduce_kernel<double, true>), g, b, 0, st, groups, S, NP, W,
+            TSM_LAUNCH((split_reduce_kernel<double, true>), g, b, 0, st, groups, S, NP, W,
                                rows, n, part, (double*)O, ldo, beta);
         else
-            hipLaunchKernelGGL((split_reduce_kernel<double, false>), g, b, 0, st, groups, S, NP,
+            TSM_LAUNCH((split_reduce_kernel<double, false>), g, b, 0, st, groups, S, NP,
                                W, rows, n, part, (double*)O, ldo, beta);
     } else {
         if (wide)
-            hipLaunchKernelGGL((split_reduce_kernel<float, true>), g, b, 0, st, groups, S, NP, W,
+            TSM_LAUNCH((split_reduce_kernel<float, true>), g, b, 0, st, groups, S, NP, W,
                                rows, n, part, (float*)O, ldo, beta);
         else
-            hipLaunchKernelGGL((split_reduce_kernel<float, false>), g, b, 0, st, groups, S, NP, W,
+            TSM_LAUNCH((split_reduce_kernel<float, false>), g, b, 0, st, groups, S, NP, W,
                                rows, n, part, (float*)O, ldo, beta);
     }
     return hipGetLastError() == hipSuccess ? 0 : 1;
@@ -495,10 +495,10 @@ int launch_fill_scale(int64_t m, int64_t n, void* C, int64_t ldc, double beta, i
                       hipStream_t st) {
     const dim3 g = flat_grid(m * n);
     if (dtype == DT_F64)
-        hipLaunchKernelGGL(fill_scale_kernel<double>, g, dim3(256), 0, st, m, n, (double*)C, ldc,
+        TSM_LAUNCH(fill_scale_kernel<double>, g, dim3(256), 0, st, m, n, (double*)C, ldc,
                            beta);
     else
-        hipLaunchKernelGGL(fill_scale_kernel<float>, g, dim3(256), 0, st, m, n, (float*)C, ldc,
+        TSM_LAUNCH(fill_scale_kernel<float>, g, dim3(256), 0, st, m, n, (float*)C, ldc,
                            (float)beta);
     return 0;
 }
@@ -507,10 +507,10 @@ int launch_transpose(int64_t k, int64_t n, const void* Bt, int64_t ldb, void* O,
                      int dtype, hipStream_t st) {
     const dim3 g = flat_grid(k * n);
     if (dtype == DT_F64)
-        hipLaunchKernelGGL(transpose_kernel<double>, g, dim3(256), 0, st, k, n, (const double*)Bt,
+        TSM_LAUNCH(transpose_kernel<double>, g, dim3(256), 0, st, k, n, (const double*)Bt,
                            ldb, (double*)O, ldo);
     else
-        hipLaunchKernelGGL(transpose_kernel<float>, g, dim3(256), 0, st, k, n, (const float*)Bt,
+        TSM_LAUNCH(transpose_kernel<float>, g, dim3(256), 0, st, k, n, (const float*)Bt,
                            ldb, (float*)O, ldo);
     return 0;
 }

@@ -411,7 +411,7 @@ static int km_launch(const LaunchKM& L, hipStream_t st) {
     if (bx > need) bx = need;
     if (bx < 1) bx = 1;
     const unsigned nb = (unsigned)((L.n + 255) / 256);
-    hipLaunchKernelGGL(kmeans_norms_kernel<T>, dim3(nb), dim3(256), 0, st, (int)L.k, (int)L.n,
+    TSM_LAUNCH(kmeans_norms_kernel<T>, dim3(nb), dim3(256), 0, st, (int)L.k, (int)L.n,
                        (const T*)L.Mu, L.ldm, (T*)L.mu2);
     if (hipGetLastError() != hipSuccess) return 1;
     // 16-byte runs of X (row-major: the last piece of a point whose k values
@@ -421,11 +421,11 @@ static int km_launch(const LaunchKM& L, hipStream_t st) {
                      ((uintptr_t)L.labels & 15u) == 0 && ((uintptr_t)L.dist & 15u) == 0;
     dim3 g((unsigned)bx), b(256);
     if (vec)
-        hipLaunchKernelGGL((kmeans_assign_kernel<T, KS, NT16, RG, true, RES, ROWX>), g, b, 0, st, L.m,
+        TSM_LAUNCH((kmeans_assign_kernel<T, KS, NT16, RG, true, RES, ROWX>), g, b, 0, st, L.m,
                            (int)L.k, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Mu, L.ldm,
                            (const T*)L.mu2, L.labels, (T*)L.dist);
     else
-        hipLaunchKernelGGL((kmeans_assign_kernel<T, KS, NT16, RG, false, RES, ROWX>), g, b, 0, st, L.m,
+        TSM_LAUNCH((kmeans_assign_kernel<T, KS, NT16, RG, false, RES, ROWX>), g, b, 0, st, L.m,
                            (int)L.k, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Mu, L.ldm,
                            (const T*)L.mu2, L.labels, (T*)L.dist);
     return hipGetLastError() != hipSuccess;

@@ -18,13 +18,20 @@
 // permute per output dword) so that MFMA instance q gets row 8*rl + q.
 // Every element of A is still loaded exactly once with 16-byte loads.
 //
-// B is float; it is split in the kernel into bf16/f16 terms B1 + B2 + B3
+// B is float; once per call it is split into bf16/f16 terms B1 + B2 + B3
 // (b1 = RNE(b), b2 = RNE(b - b1), b3 = RNE(b - b1 - b2), each difference
-// exact in float), which reproduce a float B.  Products kept:
-//   single:  hi*(B1 + B2)
+// exact in float) by split_b_kernel, which writes them to the workspace
+// already packed as the MFMA "S" operand: every row tile re-reads B, and the
+// terms are then one cached 16-byte load per lane and term instead of a split
+// in every chunk of every tile.  Three terms reproduce a float B (bf16:
+// |b - b1 - b2 - b3| <= 2^-24 |b|; binary16 keeps 11 bits per term).  Products
+// kept:
+//   single:  hi*(B1 + B2 + B3)
 //   split:   hi*(B1 + B2 + B3) + lo*(B1 + B2)
-// The dropped terms are below 2^-24 of |a||b| (bf16 storage) and the
-// arithmetic error is that of float accumulation.
+// The split form drops lo*B3 only: |lo| <= 2^-8 |a| and |B3| <= 2^-16 |b| for
+// bf16 (2^-11 and 2^-22 for binary16), so it is below 2^-24 |a||b|.  Against
+// the stored values hi (+ lo) the arithmetic error is then that of float
+// accumulation.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -127,17 +134,69 @@ __device__ __forceinline__ void load8h(const uint16_t* __restrict__ p, int64_t v
     }
 }
 
+// Bit patterns of the NBT terms of eight float values, packed two per dword
+// (value 2e in the low half of dword e): the MFMA operand layout.
+template <int FMT, int NBT>
+__device__ __forceinline__ void split_terms8(const float (&v)[8], u32x4 (&out)[NBT]) {
+    uint32_t h[NBT][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        float res = v[i];
+#pragma unroll
+        for (int c = 0; c < NBT; ++c) {
+            h[c][i] = rne16<FMT>(res);
+            res = res - val16<FMT>(h[c][i]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NBT; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[c][e] = h[c][2 * e] | (h[c][2 * e + 1] << 16);
+}
+
+// B (k x n, B(j, p) = B[j*bsj + p*bsp]) as the packed S operand of
+// tsm2r_lp: for 32-row chunk c of B, 16-column group t and term e, the u32x4
+// of lane (rl, kk) holds rows 32 c + 8 kk .. 32 c + 8 kk + 7 of column
+// 16 t + rl (zero beyond k or n), at Bt[((c * nt16 + t) * LP_BTERMS + e) * 64
+// + lane].  One thread per (c, t, lane).
+constexpr int LP_BTERMS = 3;
+
+template <int FMT>
+__global__ __launch_bounds__(256) void split_b_kernel(int64_t k, int n, const float* __restrict__ B,
+                                                      int64_t bsj, int64_t bsp, int nt16,
+                                                      u32x4* __restrict__ Bt) {
+    const int64_t chunks = (k + 31) / 32;
+    const int64_t total = chunks * nt16 * WAVE;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(e % WAVE);
+        const int64_t ct = e / WAVE;
+        const int t = (int)(ct % nt16);
+        const int64_t c = ct / nt16;
+        const int rl = lane & 15, kk = lane >> 4;
+        const int p = 16 * t + rl;
+        const int64_t jb = 32 * c + 8 * kk;
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (p < n && jb + i < k) ? B[(jb + i) * bsj + p * bsp] : 0.f;
+        u32x4 out[LP_BTERMS];
+        split_terms8<FMT, LP_BTERMS>(v, out);
+#pragma unroll
+        for (int q = 0; q < LP_BTERMS; ++q) Bt[(ct * LP_BTERMS + q) * WAVE + lane] = out[q];
+    }
+}
+
 template <int FMT, int NT16, bool SPLIT, int WK, bool VEC>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
-    const uint16_t* __restrict__ Al, int64_t lda, const float* __restrict__ B, int64_t ldb,
-    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part, int bvec,
+    const uint16_t* __restrict__ Al, int64_t lda, const u32x4* __restrict__ Bt,
+    float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part,
     double beta) {
     constexpr int TR = 128;              // 16 lanes x 8 rows
     constexpr int NP = 16 * NT16;
     constexpr int PG = 4;
     constexpr int NPL = SPLIT ? 2 : 1;   // planes
-    constexpr int NBT = SPLIT ? 3 : 2;   // B terms
+    constexpr int NBT = LP_BTERMS;       // B terms
     __shared__ __align__(16) unsigned char smem[WK * PG * TR * 8];
 
     const int lane = threadIdx.x & (WAVE - 1);
@@ -176,27 +235,14 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
             }
         }
     };
-    // a lane's 8 values of B in a chunk, B[j0 + 8 kk .. j0 + 8 kk + 7, p], are
-    // contiguous: two 16-byte (cached) loads when B is aligned
-    auto loadB = [&](int64_t j0, float (&bv)[NT16][8]) {
+    // the packed B terms of the chunk at j0 (a multiple of 32): cached loads,
+    // every row tile reads them
+    auto loadBt = [&](int64_t j0, u32x4 (&bt)[NT16][NBT]) {
+        const int64_t c = j0 / 32;
 #pragma unroll
-        for (int t = 0; t < NT16; ++t) {
-            const int p = 16 * t + rl;
-            const int64_t jb = j0 + 8 * kk;
-            const float* __restrict__ src = B + jb + (int64_t)p * ldb;
-            if (p < n && bvec && jb + 8 <= wk1) {
-                const f32x4 v0 = *reinterpret_cast<const f32x4*>(src);
-                const f32x4 v1 = *reinterpret_cast<const f32x4*>(src + 4);
+        for (int t = 0; t < NT16; ++t)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    bv[t][i] = v0[i];
-                    bv[t][4 + i] = v1[i];
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 8; ++i) bv[t][i] = (p < n && jb + i < wk1) ? src[i] : 0.f;
-            }
-        }
+            for (int e = 0; e < NBT; ++e) bt[t][e] = Bt[((c * NT16 + t) * NBT + e) * WAVE + lane];
     };
 
     // No register prefetch of the next chunk: its 32-64 VGPRs cost a
@@ -207,28 +253,9 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
         const int ng = (int)((wk1 - wk0 + 31) / 32);
         for (int g = 0; g < ng; ++g) {
             uint32_t raw[NPL][8][4];
-            float bv[NT16][8];
-            loadA(wk0 + 32 * g, raw);
-            loadB(wk0 + 32 * g, bv);
-            // B terms, packed as the S operand: dword e holds k = 2e, 2e + 1
             u32x4 bt[NT16][NBT];
-#pragma unroll
-            for (int t = 0; t < NT16; ++t) {
-                uint32_t h[NBT][8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    float res = bv[t][i];
-#pragma unroll
-                    for (int c = 0; c < NBT; ++c) {
-                        h[c][i] = rne16<FMT>(res);
-                        res = res - val16<FMT>(h[c][i]);
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < NBT; ++c)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) bt[t][c][e] = h[c][2 * e] | (h[c][2 * e + 1] << 16);
-            }
+            loadA(wk0 + 32 * g, raw);
+            loadBt(wk0 + 32 * g, bt);
             // 8 x 8 transpose of each plane: instance q gets row r + q
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -269,26 +296,6 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
             }
         }
     });
-}
-
-// Bit patterns of the NBT terms of eight float values, packed two per dword
-// (value 2e in the low half of dword e): the MFMA operand layout.
-template <int FMT, int NBT>
-__device__ __forceinline__ void split_terms8(const float (&v)[8], u32x4 (&out)[NBT]) {
-    uint32_t h[NBT][8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        float res = v[i];
-#pragma unroll
-        for (int c = 0; c < NBT; ++c) {
-            h[c][i] = rne16<FMT>(res);
-            res = res - val16<FMT>(h[c][i]);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < NBT; ++c)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) out[c][e] = h[c][2 * e] | (h[c][2 * e + 1] << 16);
 }
 
 // Value of row q (0..7) of a lane's 16-byte run of each plane: hi, or hi + lo.
@@ -434,7 +441,7 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // float 16x16x4 matrix cores.  Reduction across wavefronts and workgroups
 // as in tn_kernel.
 // --------------------------------------------------------------------------
-template <int FMT, int NT16, bool SPLIT, bool VEC, bool YC>
+template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC>
 __global__ __launch_bounds__(256) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
@@ -443,7 +450,9 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
     constexpr int WK = 4;
     constexpr int SR = 128;                    // rows per step
     constexpr int SROW = SR + 4;               // padded LDS column (16 more bytes)
-    constexpr int NC = 16 + 16 * NT16;         // staged columns: X tile, then Y tiles
+    constexpr int NX = 16 * CT;                // staged X columns (CT output tiles)
+    constexpr int NC = NX + 16 * NT16;         // then the Y columns
+    constexpr int XG = 4 * CT;                 // X column groups of 4
     constexpr int YG = 4 * NT16;               // Y column groups of 4
     constexpr int NPL = SPLIT ? 2 : 1;
     __shared__ __align__(16) float lds[WK][NC][SROW];
@@ -452,8 +461,7 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
     const int w = threadIdx.x / WAVE;
-    const int64_t ctile = blockIdx.x;
-    const int64_t c0 = ctile * 16;
+    const int64_t c0 = (int64_t)blockIdx.x * NX;
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t sb0 = (int64_t)s * rslice;
     const int64_t sb1 = (sb0 + rslice < R) ? sb0 + rslice : R;
@@ -462,17 +470,19 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
     const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
     float (*tile)[SROW] = lds[w];
 
-    f32x4 acc[NT16];
+    f32x4 acc[CT][NT16];
 #pragma unroll
-    for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) acc[ct][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    auto load = [&](int64_t rb, uint32_t (&xv)[4][NPL][4], float (&yv)[2][YG][4]) {
+    auto load = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4], float (&yv)[2][YG][4]) {
         {
             const int64_t r = rb + 8 * rl;
             const int64_t valid = wb1 - r;
             const bool full = valid >= 8;
 #pragma unroll
-            for (int cg = 0; cg < 4; ++cg) {
+            for (int cg = 0; cg < XG; ++cg) {
                 const int64_t c = c0 + 4 * cg + kk;
 #pragma unroll
                 for (int pl = 0; pl < NPL; ++pl) {
@@ -509,17 +519,17 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
 
     if (wb1 > wb0) {
         const int64_t nit = (wb1 - wb0 + SR - 1) / SR;
-        uint32_t xv[4][NPL][4];
+        uint32_t xv[XG][NPL][4];
         float yv[2][YG][4];
         load(wb0, xv, yv);
         for (int64_t it = 0; it < nit; ++it) {
-            uint32_t xn[4][NPL][4];
+            uint32_t xn[XG][NPL][4];
             float yn[2][YG][4];
             if (it + 1 < nit) load(wb0 + (it + 1) * SR, xn, yn);
             // stage: X column 4 cg + kk rows 8 rl .. 8 rl + 7 (widened),
-            //        Y column 4 cg + kk rows 64 h + 4 rl .. 64 h + 4 rl + 3
+            //        Y column NX + 4 cg + kk rows 64 h + 4 rl .. 64 h + 4 rl + 3
 #pragma unroll
-            for (int cg = 0; cg < 4; ++cg) {
+            for (int cg = 0; cg < XG; ++cg) {
                 f32x4 x0, x1;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -536,22 +546,27 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
                     f32x4 y;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) y[q] = yv[h][cg][q];
-                    *reinterpret_cast<f32x4*>(&tile[16 + 4 * cg + kk][64 * h + 4 * rl]) = y;
+                    *reinterpret_cast<f32x4*>(&tile[NX + 4 * cg + kk][64 * h + 4 * rl]) = y;
                 }
-            // read back 16-row blocks: rows 16 hb + 4 kk + q
+            // read back 16-row blocks: rows 16 hb + 4 kk + q; each staged Y
+            // block serves the CT output tiles
 #pragma unroll
             for (int hb = 0; hb < SR / 16; ++hb) {
-                const f32x4 xs = *reinterpret_cast<const f32x4*>(&tile[rl][16 * hb + 4 * kk]);
+                f32x4 ys[NT16];
 #pragma unroll
-                for (int t = 0; t < NT16; ++t) {
-                    const f32x4 ys =
-                        *reinterpret_cast<const f32x4*>(&tile[16 + 16 * t + rl][16 * hb + 4 * kk]);
+                for (int t = 0; t < NT16; ++t)
+                    ys[t] = *reinterpret_cast<const f32x4*>(&tile[NX + 16 * t + rl][16 * hb + 4 * kk]);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[t] = M::op(xs[q], ys[q], acc[t]);
+                for (int ct = 0; ct < CT; ++ct) {
+                    const f32x4 xs = *reinterpret_cast<const f32x4*>(&tile[16 * ct + rl][16 * hb + 4 * kk]);
+#pragma unroll
+                    for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[ct][t] = M::op(xs[q], ys[t][q], acc[ct][t]);
                 }
             }
 #pragma unroll
-            for (int cg = 0; cg < 4; ++cg)
+            for (int cg = 0; cg < XG; ++cg)
 #pragma unroll
                 for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
@@ -565,8 +580,14 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
         }
     }
 
-    tn_finish<float, NT16, WK>(ncols, n, O, ldo, 0.0, ctile, s, nsl, part, red, acc,
-                               [](int kq, int r) { return Mfma<float>::mrow(kq, r); });
+    // one 16-column output tile at a time (global tile index blockIdx.x*CT + ct)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        if (ct > 0) __syncthreads();           // red is reused
+        tn_finish<float, NT16, WK>(ncols, n, O, ldo, 0.0, (int64_t)blockIdx.x * CT + ct, s, nsl,
+                                   part, red, acc[ct],
+                                   [](int kq, int r) { return Mfma<float>::mrow(kq, r); });
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -637,19 +658,41 @@ int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st) {
     const uint16_t* ah = (const uint16_t*)L.A;
     const uint16_t* al = split ? ah + L.lda * L.k : nullptr;
     int n32 = (int)L.n;
-    // 16-byte loads of B's column runs need an aligned B with ldb % 4 == 0
-    int bvec = ((uintptr_t)L.B & 15u) == 0 && (L.ldb % 4) == 0;
     double beta = L.beta;
-    void* args[] = {(void*)&L.m,   (void*)&L.k,   (void*)&n32,      (void*)&ah,
-                    (void*)&al,    (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,
-                    (void*)&L.C,   (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part,
-                    (void*)&bvec,  (void*)&beta};
-    hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
-                                   0, st);
+    // L.B: B's terms packed by launch_split_b
+    void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&n32,    (void*)&ah,
+                    (void*)&al,    (void*)&L.lda,    (void*)&L.B,    (void*)&L.C,
+                    (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&beta};
+    hipError_t e;
+    {
+        LaunchTimer timer(L.fn, st);
+        e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args, 0, st);
+    }
     if (e != hipSuccess) return 1;
     if (L.S > 1)
         return launch_split_reduce(DT_F32, L.tiles, L.S, L.np, 128, L.m, (int)L.n, L.part, L.C,
                                    L.ldc, L.beta, st);
+    return 0;
+}
+
+size_t lp_bterms_bytes(int64_t k, int64_t n) {
+    return (size_t)((k + 31) / 32) * (n <= 16 ? 1 : 2) * LP_BTERMS * WAVE * sizeof(u32x4);
+}
+
+int launch_split_b(int64_t k, int64_t n, const float* B, int64_t bsj, int64_t bsp, int dtype,
+                   void* out, hipStream_t st) {
+    const int nt16 = n <= 16 ? 1 : 2;
+    const int64_t total = (k + 31) / 32 * nt16 * WAVE;
+    int64_t blocks = cdiv_lp(total, 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    const bool bf = dtype == DT_BF16 || dtype == DT_BF16_SPLIT;
+    if (bf)
+        TSM_LAUNCH(split_b_kernel<FMT_BF16>, dim3((unsigned)blocks), dim3(256), 0, st, k, (int)n, B,
+                   bsj, bsp, nt16, (u32x4*)out);
+    else
+        TSM_LAUNCH(split_b_kernel<FMT_F16>, dim3((unsigned)blocks), dim3(256), 0, st, k, (int)n, B,
+                   bsj, bsp, nt16, (u32x4*)out);
     return 0;
 }
 
@@ -671,10 +714,10 @@ static void tsm2l_lp_go(int64_t m, int k, int n, const uint16_t* ah, const uint1
     if (blocks < 1) blocks = 1;
     dim3 g((unsigned)blocks), b(256);
     if (vec)
-        hipLaunchKernelGGL((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, true>), g, b, 0, st, m, k, n, ah,
+        TSM_LAUNCH((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, true>), g, b, 0, st, m, k, n, ah,
                            al, lda, B, bsj, bsp, beta, C, ldc);
     else
-        hipLaunchKernelGGL((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, false>), g, b, 0, st, m, k, n,
+        TSM_LAUNCH((tsm2l_lp_kernel<FMT, KS, NT16, SPLIT, false>), g, b, 0, st, m, k, n,
                            ah, al, lda, B, bsj, bsp, beta, C, ldc);
 }
 
@@ -724,33 +767,42 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
                      ((uintptr_t)L.Y & 15u) == 0 && (L.ldy % 4) == 0;
     const uint16_t* xh = (const uint16_t*)L.X;
     const uint16_t* xl = split ? xh + L.ldx * L.ncols : nullptr;
-    dim3 g((unsigned)L.groups, (unsigned)L.S), b(256);
+    // L.groups 16-column tiles, a multiple of L.ct: L.ct of them per workgroup
+    const int64_t gx = L.groups / L.ct;
+    dim3 g((unsigned)gx, (unsigned)L.S), b(256);
     const int ni = (int)L.n;
     // Y is re-read by every column group: cached loads when there are several
-    const bool yc = L.groups > 1;
-#define TSM_T(F, NT, SP)                                                                           \
-    {                                                                                              \
-        if (vec && yc)                                                                             \
-            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, true, true>), g, b, 0, st, L.R, L.ncols,   \
-                               ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,    \
-                               L.rslice, L.part);                                                  \
-        else if (vec)                                                                              \
-            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, true, false>), g, b, 0, st, L.R, L.ncols,  \
-                               ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,    \
-                               L.rslice, L.part);                                                  \
-        else                                                                                       \
-            hipLaunchKernelGGL((tn_lp_kernel<F, NT, SP, false, false>), g, b, 0, st, L.R, L.ncols, \
-                               ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,    \
-                               L.rslice, L.part);                                                  \
-        return 0;                                                                                  \
+    const bool yc = gx > 1;
+#define TSM_T(F, NT, CT, SP)                                                                    \
+    {                                                                                           \
+        if (vec && yc)                                                                          \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, true>), g, b, 0, st, L.R, L.ncols,    \
+                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,         \
+                       L.rslice, L.part);                                                       \
+        else if (vec)                                                                           \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, false>), g, b, 0, st, L.R, L.ncols,   \
+                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,         \
+                       L.rslice, L.part);                                                       \
+        else                                                                                    \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, false, false>), g, b, 0, st, L.R, L.ncols,  \
+                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,         \
+                       L.rslice, L.part);                                                       \
+        return 0;                                                                               \
+    }
+#define TSM_T2(F, SP)                                                   \
+    {                                                                   \
+        if (L.ct == 2) {                                                \
+            if (L.n <= 16) TSM_T(F, 1, 2, SP) else TSM_T(F, 2, 2, SP)   \
+        } else {                                                        \
+            if (L.n <= 16) TSM_T(F, 1, 1, SP) else TSM_T(F, 2, 1, SP)   \
+        }                                                               \
     }
     if (fmt == FMT_BF16) {
-        if (split) { if (L.n <= 16) TSM_T(FMT_BF16, 1, true) else TSM_T(FMT_BF16, 2, true) }
-        else { if (L.n <= 16) TSM_T(FMT_BF16, 1, false) else TSM_T(FMT_BF16, 2, false) }
+        if (split) TSM_T2(FMT_BF16, true) else TSM_T2(FMT_BF16, false)
     } else {
-        if (split) { if (L.n <= 16) TSM_T(FMT_F16, 1, true) else TSM_T(FMT_F16, 2, true) }
-        else { if (L.n <= 16) TSM_T(FMT_F16, 1, false) else TSM_T(FMT_F16, 2, false) }
+        if (split) TSM_T2(FMT_F16, true) else TSM_T2(FMT_F16, false)
     }
+#undef TSM_T2
 #undef TSM_T
     return 1;
 }
@@ -774,7 +826,7 @@ int launch_split(int64_t m, int64_t k, const float* A, int64_t lda, void* hi, vo
     uint16_t* h = (uint16_t*)hi;
     uint16_t* l = (uint16_t*)lo;
 #define TSM_SPLIT(F, LO, V) \
-    hipLaunchKernelGGL((split_kernel<F, LO, V>), g, b, 0, st, m, k, A, lda, h, l, ldh)
+    TSM_LAUNCH((split_kernel<F, LO, V>), g, b, 0, st, m, k, A, lda, h, l, ldh)
     if (fmt == FMT_BF16) {
         if (lo) { if (vec) TSM_SPLIT(FMT_BF16, true, true); else TSM_SPLIT(FMT_BF16, true, false); }
         else { if (vec) TSM_SPLIT(FMT_BF16, false, true); else TSM_SPLIT(FMT_BF16, false, false); }

@@ -306,8 +306,11 @@ int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
                     (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,
                     (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&bvec,
                     (void*)&beta};
-    hipError_t e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args,
-                                   0, st);
+    hipError_t e;
+    {
+        LaunchTimer timer(L.fn, st);
+        e = hipLaunchKernel(L.fn, dim3((unsigned)L.tiles, (unsigned)L.S), dim3(256), args, 0, st);
+    }
     if (e != hipSuccess) return 1;
     if (L.S > 1)
         return launch_split_reduce(dtype, L.tiles, L.S, L.np, L.tile_rows, L.m, (int)L.n, L.part,

@@ -206,3 +206,90 @@ def test_fused_backward_lowp(dev, fmt, code, with_lo, m, k, n):
     assert err(to_np(dB), oracle.matmul(_stored_value(Ah, code, with_lo).T, dCh)) <= TOL_STORED
     # the same as the two separate kernels
     assert err(to_np(dB), to_np(tsm.grad_b(S, dC))) <= TOL_STORED
+
+
+# ------------------------------------------------------------------------
+# Pins of the products the precision form keeps.  On random data a dropped
+# term below ~2^-16 hides inside the float accumulation error, so each term
+# is pinned by a case where it alone decides exact results: rows of A with one
+# nonzero entry, so that every output is a single product and float
+# accumulation adds only zeros.
+# ------------------------------------------------------------------------
+def _one_hot_rows(m, k, value, seed):
+    """m x k float32, row i holds +-value in column i % k, zero elsewhere."""
+    sign = np.where(si.values(seed, si.STREAM_V, torch.arange(m), dist="int", r=1).numpy() < 0,
+                    -1.0, 1.0)
+    A = np.zeros((m, k), dtype=np.float32)
+    A[np.arange(m), np.arange(m) % k] = (sign * value).astype(np.float32)
+    return A
+
+
+def _dev(x, dev):
+    return torch.from_numpy(np.asfortranarray(x)).to(dev).t().contiguous().t()
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("kind,m,k,n", [("R", 1000, 777, 16), ("R", 300, 4100, 32),
+                                        ("L", 5000, 16, 16), ("L", 4133, 32, 7)])
+def test_every_term_of_B_is_kept(dev, fmt, code, kind, m, k, n):
+    """A one-hot with entries +-1 (hi = +-1, lo = 0) and B in [1, 2) with full
+    24-bit significands, so that B needs all three 16-bit terms (bf16: 8 + 8
+    + 8 bits; binary16: 11 + 11 + 2): every output must be exactly +-B[j, p]
+    in both forms.  Dropping hi*B3 (or hi*B2) changes the last bits."""
+    A = _one_hot_rows(m, k, 1.0, 31 + m)
+    B = (1.0 + np.abs(si.matrix(37 + k, si.STREAM_B, k, n).numpy())).astype(np.float32)
+    assert np.any(B != B.astype(np.float64).round(4))          # not short significands
+    want = (A.astype(np.float64) @ B.astype(np.float64))
+    Ad, Bd = _dev(A, dev), _dev(B, dev)
+    for with_lo in (False, True):
+        S = tsm.split(Ad, fmt, lo=with_lo)
+        C = tsm.tsm2l(S, Bd) if kind == "L" else tsm.tsm2r(S, Bd)
+        assert np.array_equal(to_np(C), want), (fmt, with_lo)
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("kind,m,k,n", [("R", 1000, 777, 16), ("R", 300, 4100, 32),
+                                        ("L", 5000, 16, 16), ("L", 4133, 32, 7)])
+def test_lo_plane_terms_are_kept(dev, fmt, code, kind, m, k, n):
+    """A one-hot with entries +-a, a = 1 + 2^-8 (bf16) or 1 + 2^-11 (binary16):
+    hi = 1 and lo = 2^-8 (2^-11).  B = 1 + r*2^-15 (1 + r*2^-12), so that B
+    has two nonzero terms and a*b is exact in float.  The split form must give
+    exactly +-a*b (every one of hi*B1, hi*B2, lo*B1, lo*B2 kept), the single
+    form exactly +-b (its stored value is hi = 1)."""
+    a, step, rmax = (1 + 2.0 ** -8, 2.0 ** -15, 1 << 14) if fmt == "bf16" else \
+        (1 + 2.0 ** -11, 2.0 ** -12, 1 << 11)
+    A = _one_hot_rows(m, k, a, 41 + m)
+    r = si.values(43 + k, si.STREAM_B, torch.arange(k * n), dist="int", r=rmax).numpy()
+    B = (1.0 + np.abs(r).reshape(n, k).T % rmax * step).astype(np.float32)
+    hi, lo = oracle.split(np.asfortranarray(A), code)
+    assert np.all(oracle.decode_plane(lo, code)[A != 0] != 0)
+    Ad, Bd = _dev(A, dev), _dev(B, dev)
+    want_split = A.astype(np.float64) @ B.astype(np.float64)
+    assert np.array_equal(want_split.astype(np.float32).astype(np.float64), want_split)
+    want_single = np.sign(A).astype(np.float64) @ B.astype(np.float64)
+    for with_lo, want in ((True, want_split), (False, want_single)):
+        S = tsm.split(Ad, fmt, lo=with_lo)
+        C = tsm.tsm2l(S, Bd) if kind == "L" else tsm.tsm2r(S, Bd)
+        assert np.array_equal(to_np(C), want), (fmt, with_lo)
+
+
+@pytest.mark.parametrize("fmt,code", FMTS)
+@pytest.mark.parametrize("m,n", [(24, 8), (64, 8), (517, 16), (2000, 32)])
+def test_grad_b_keeps_the_lo_plane(dev, fmt, code, m, n):
+    """dB = A^T*dC on the planes with A = diag(+-a) (m = k): dB[j, p] =
+    +-a*dC[j, p] exactly for the split form, +-dC[j, p] for the single form;
+    the same through the fused backward."""
+    a, step, rmax = (1 + 2.0 ** -8, 2.0 ** -15, 1 << 14) if fmt == "bf16" else \
+        (1 + 2.0 ** -11, 2.0 ** -12, 1 << 11)
+    A = _one_hot_rows(m, m, a, 47 + m)
+    r = si.values(53 + m, si.STREAM_DC, torch.arange(m * n), dist="int", r=rmax).numpy()
+    dC = (1.0 + np.abs(r).reshape(n, m).T % rmax * step).astype(np.float32)
+    Ad, dCd = _dev(A, dev), _dev(dC, dev)
+    for with_lo in (True, False):
+        want = (A if with_lo else np.sign(A)).astype(np.float64).T @ dC.astype(np.float64)
+        S = tsm.split(Ad, fmt, lo=with_lo)
+        assert np.array_equal(to_np(tsm.grad_b(S, dCd)), want), (fmt, with_lo, "tn")
+        if m <= 32:
+            B = _dev(np.ones((m, n), dtype=np.float32), dev)
+            _, dB = tsm.tsm2l_backward(S, B, dCd)
+            assert np.array_equal(to_np(dB), want), (fmt, with_lo, "fused")

@@ -279,6 +279,45 @@ def test_normwise_error():
     assert abs(oracle.normwise_error([[1.1]], [[1.0]]) - 0.1) < 1e-12
 
 
+def test_componentwise_error_closed_forms():
+    # A = [1, -1], B = [1; 1]: C = 0 exactly and (|A||B|) = 2, so an error of
+    # 1e-3 in C is 5e-4 of the componentwise scale, however small C is
+    A = np.array([[1.0, -1.0], [2.0, 0.0]])
+    B = np.array([[1.0], [1.0]])
+    ref = oracle.matmul(A, B)
+    assert ref[0, 0] == 0.0 and ref[1, 0] == 2.0
+    assert oracle.componentwise_error(ref, ref, A, B) == 0.0
+    assert oracle.componentwise_error(ref + [[1e-3], [0.0]], ref, A, B) == pytest.approx(5e-4)
+    assert oracle.componentwise_error(ref + [[0.0], [1e-3]], ref, A, B) == pytest.approx(5e-4)
+    # a zero scale: exact entries count 0, anything else infinity
+    Z = np.zeros((1, 2))
+    assert oracle.componentwise_error([[0.0]], [[0.0]], Z, B) == 0.0
+    assert oracle.componentwise_error([[1e-300]], [[0.0]], Z, B) == math.inf
+    assert oracle.componentwise_error(np.zeros((0, 1)), np.zeros((0, 1)), np.zeros((0, 2)), B) == 0.0
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_componentwise_error_bounds_the_sequential_sum(seed):
+    """The oracle's own double sums, against exact rational sums, stay within
+    gamma_k = k u / (1 - k u) of |A||B| componentwise (Higham, eq. 3.13),
+    and a single perturbation larger than that is seen."""
+    rng = random.Random(seed)
+    m, k, n = 6, 40, 3
+    A = np.array([[rng.uniform(-1, 1) for _ in range(k)] for _ in range(m)])
+    B = np.array([[rng.uniform(-1, 1) for _ in range(n)] for _ in range(k)])
+    exact = np.array([[float(sum(Fraction(A[i, j]) * Fraction(B[j, p]) for j in range(k)))
+                       for p in range(n)] for i in range(m)])
+    u = 2.0 ** -53
+    gamma = k * u / (1 - k * u)
+    C = oracle.matmul(A, B)
+    e = oracle.componentwise_error(C, exact, A, B)
+    assert e <= gamma
+    scale = np.abs(A) @ np.abs(B)
+    bad = C.copy()
+    bad[2, 1] += 4 * gamma * scale[2, 1]
+    assert oracle.componentwise_error(bad, exact, A, B) > gamma
+
+
 # ------------------------------------------------------------ k-means assignment
 def _kmeans_brute(X, Mu):
     """Exact rational distances, first index among equal minima."""

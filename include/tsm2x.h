@@ -292,7 +292,9 @@ int tsm2x_tsm2r_pin(int64_t m, int64_t k, int64_t n, int dtype, int slices, int 
  *                         one row per (kernel, tag), and return the number of
  *                         rows.  Call it when no recorded work is being
  *                         enqueued by another thread;
- *   tsm2x_timing_row      row i: the kernel's name as rocprofv3 prints it
+ *   tsm2x_timing_row      row i: the kernel's demangled name without its
+ *                         namespace and parameter list, e.g.
+ *                         "rowtile_kernel<double, 4, 1, 1, true, false>"
  *                         (static storage, valid until the next start), its
  *                         tag, launch count and summed launch time in
  *                         milliseconds.  Returns -1 for i out of range.

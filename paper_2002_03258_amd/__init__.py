@@ -385,7 +385,8 @@ def timing_tag(tag: int) -> None:
 
 def timing_collect() -> list:
     """Wait for the recorded launches and return one dict per (kernel, tag):
-    ``kernel`` (as rocprofv3 names it), ``tag``, ``launches``, ``total_ms``."""
+    ``kernel`` (demangled, without namespace and parameters), ``tag``,
+    ``launches``, ``total_ms``."""
     import ctypes
     L = _lib.lib()
     nrows = L.tsm2x_timing_collect()

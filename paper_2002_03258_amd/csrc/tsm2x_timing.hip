@@ -56,7 +56,7 @@ hipEvent_t take_event() {
 }
 
 // "tsm2l_bwd_kernel<double, 1, 1, 2, true, -1, false>": the demangled name
-// without return type and parameter list, as rocprofv3 prints kernels
+// without return type, namespace and parameter list
 std::string kernel_name(const void* fn, hipStream_t st) {
     auto it = g_names.find(fn);
     if (it != g_names.end()) return it->second;
@@ -68,6 +68,8 @@ std::string kernel_name(const void* fn, hipStream_t st) {
         name = (status == 0 && dem) ? dem : raw;
         std::free(dem);
         if (name.compare(0, 5, "void ") == 0) name.erase(0, 5);
+        // the kernels' namespace is left out, as tsm2x_kernel_name reports them
+        if (name.compare(0, 5, "tsm::") == 0) name.erase(0, 5);
         int depth = 0;
         for (size_t i = 0; i < name.size(); ++i) {
             if (name[i] == '<') ++depth;

@@ -193,6 +193,26 @@ int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
                    void* dA, int64_t ldda, void* dB, int64_t lddb, int dtype,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* tsm2l_backward for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments without the workspace, the same kernels, the same grid and the
+ * same results bit for bit, with the dB partials in a static device array of
+ * the library (16 MiB per device, held until the process ends; room for one
+ * 32 x 32 double partial per workgroup of the persistent grid, at most 2048
+ * workgroups) instead of a workspace.  The array's address is looked up once
+ * per device, on the first call made with that device current.  No
+ * allocation of any kind is made on the device.  Every call on one device
+ * shares that device's array: calls that overlap on one device (two streams,
+ * two host threads) race and must be ordered by the caller.  Nothing needs
+ * clearing between calls (every partial is written before it is read).
+ * Returns as tsm2l_backward (arguments 1..14 checked the same way), plus
+ * TSM_ERR_WORKSPACE when the grid's partials would exceed the array (not on
+ * a device of at most 256 compute units) and TSM_ERR_HIP when the address
+ * lookup fails. */
+int tsm2l_backward_noalloc(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
+                           int64_t ldda, void* dB, int64_t lddb, int dtype, void* stream);
+
 /* K-means assignment step.  The paper's Introduction names K-means as a
  * tall-and-skinny GEMM application (far fewer centroids than points).  For
  * points X, m-by-k, either column-major (x_rowmajor 0: point i is row i,

@@ -55,6 +55,9 @@ def lib():
             L.tsm2x_split.argtypes = [i64, i64, vp, i64, vp, vp, i64, i32, vp]
             L.tsm2l_backward.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                                          i32, vp, sz, vp]
+            L.tsm2l_backward_noalloc.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp,
+                                                 i64, vp, i64, i32, vp]
+            L.tsm2l_backward_noalloc.restype = i32
             L.tsm_kmeans_assign.argtypes = [i64, i64, i64, vp, i64, i32, vp, i64, vp, vp, i32, vp,
                                             sz, vp]
             L.tsm2x_workspace_size.argtypes = [i32, i64, i64, i64, i32]
@@ -100,7 +103,7 @@ def call(fn: str, *args) -> None:
 
 
 EXPORTS = ("tsm2r", "tsm2r_ex", "tsm2l", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a", "tsm_grad_b",
-           "tsm2l_backward", "tsm_kmeans_assign",
+           "tsm2l_backward", "tsm2l_backward_noalloc", "tsm_kmeans_assign",
            "tsm2x_split",
            "tsm2x_workspace_size", "tsm2x_kernel_name", "tsm2x_tsm2r_plan", "tsm2x_tsm2r_pin",
            "tsm2x_timing_start", "tsm2x_timing_stop", "tsm2x_timing_tag", "tsm2x_timing_collect",

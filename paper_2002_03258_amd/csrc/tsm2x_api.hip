@@ -518,6 +518,15 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
 
 }  // extern "C"
 
+// Scratch of the allocation-free fused backward: room for the dB partials
+// of 2048 workgroups of the widest instance (32 x 32 doubles each), i.e. a
+// persistent grid of 8 resident workgroups on each of 256 compute units.
+// Every device holds its own copy for the life of the process.  Host code
+// never passes `scratch` itself (on the host the name is only a stand-in);
+// it uses the per-device address hipGetSymbolAddress returns.
+static constexpr size_t kBwdScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) double scratch[kBwdScratchBytes / sizeof(double)];
+
 namespace {
 
 // Argument checks of tsm2l_backward (positions 1..14).
@@ -570,9 +579,59 @@ int run_bwd(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const v
     return check_launch("tsm2l_bwd_kernel");
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// This device's scratch address (looked up once per device, with the device
+// current); null with *rc set on failure.
+void* scratch_ptr(int* rc) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *rc = hip_fail(e, "hipGetDevice");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        g_last_hip = "scratch: device index beyond the supported 64 devices";
+        *rc = TSM_ERR_UNSUPPORTED;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *rc = hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                           "hipGetSymbolAddress(scratch)");
+            return nullptr;
+        }
+        g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
+
 }  // namespace
 
 extern "C" {
+
+int tsm2l_backward_noalloc(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, const void* dC, int64_t lddc, void* dA,
+                           int64_t ldda, void* dB, int64_t lddb, int dtype, void* stream) {
+    int rc = check_bwd(m, k, n, A, lda, B, ldb, dC, lddc, dA, ldda, dB, lddb, dtype);
+    if (rc) return rc;
+    return run_bwd(m, k, n, A, lda, B, ldb, dC, lddc, dA, ldda, dB, lddb, dtype,
+                   (hipStream_t)stream, [](size_t need, int* prc) -> void* {
+                       if (need > kBwdScratchBytes) {
+                           g_last_hip = "tsm2l_backward_noalloc: the dB partials need " +
+                                        std::to_string(need) + " bytes, beyond the " +
+                                        std::to_string(kBwdScratchBytes) + "-byte scratch";
+                           *prc = TSM_ERR_WORKSPACE;
+                           return nullptr;
+                       }
+                       return scratch_ptr(prc);
+                   });
+}
 
 int tsm2l_backward(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, const void* B,
                    int64_t ldb, const void* dC, int64_t lddc, void* dA, int64_t ldda, void* dB,

@@ -166,8 +166,11 @@ struct TNPlan {
 TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     TNPlan P{};
     // output tiles per workgroup: two share each staged Y tile when there
-    // are several column groups (Y is then re-read by every group)
-    P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", 2) : 1;
+    // are several column groups (Y is then re-read by every group).  The
+    // 16-bit forms stage 128 rows per step, so two tiles need 101 KB of LDS
+    // per workgroup and one workgroup per CU: measured slower (bf16 split,
+    // 16384^2, n = 8: 3.97 TB/s against 4.88 with one tile), so one by default
+    P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", plain_dtype(dt) ? 2 : 1) : 1;
     if (P.ct != 1 && P.ct != 2) P.ct = 1;
     // rows per wavefront loop iteration: G stages of 16*RL rows for the
     // float kernels (one stage with two output tiles), 128 for the 16-bit form

@@ -44,7 +44,7 @@ namespace tsm {
 // O[row(rl, q), col0 + 16 t + mrow(kk, r)] in acc[g][q][t][r] with
 // row(rl, q) = row0 + 16*RL*g + RL*rl + q.
 // --------------------------------------------------------------------------
-template <typename T, int KS, int NT16, int RG, bool VEC, bool PF>
+template <typename T, int KS, int NT16, int RG, bool VEC, bool NTS>
 __global__ __launch_bounds__(256) void rowtile_kernel(
     int64_t m, int kin, int64_t nout, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ys_in, int64_t ys_out, T* __restrict__ O,
@@ -102,10 +102,7 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
     for (; tile < ntiles; tile += tstride) {
         const int64_t row0 = tile * TR;
         const bool full = (row0 + TR <= m);
-        // the next tile's rows are requested before this tile is multiplied
-        T xn[KS][RG][RL];
         const bool more = tile + tstride < ntiles;
-        if (PF && more) loadX(tile + tstride, xn);
         for (int64_t c0 = cb0; c0 < cb1; c0 += CW) {
             if (!one_pass) loadY(c0);
             Acc acc[RG][RL][NT16];
@@ -142,22 +139,13 @@ __global__ __launch_bounds__(256) void rowtile_kernel(
 #pragma unroll
                                 for (int q = 0; q < RL; ++q) v[q] = __builtin_fma(beta, o[q], v[q]);
                             }
-                            store_run<T, RL, VEC>(O + r + col * ldo, m - r, full, v);
+                            store_run<T, RL, VEC, NTS>(O + r + col * ldo, m - r, full, v);
                         }
                     }
             }
         }
         if (more) {
-            if (PF) {
-#pragma unroll
-                for (int st = 0; st < KS; ++st)
-#pragma unroll
-                    for (int g = 0; g < RG; ++g)
-#pragma unroll
-                        for (int q = 0; q < RL; ++q) xv[st][g][q] = xn[st][g][q];
-            } else {
-                loadX(tile + tstride, xv);
-            }
+            loadX(tile + tstride, xv);
         }
     }
 }
@@ -348,12 +336,12 @@ static int occupancy(K kernel, int threads) {
 
 static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-template <typename T, int KS, int NT16, int RG, bool PF>
-static int rowtile_launch_pf(const LaunchRT& L, bool vec, hipStream_t st) {
+template <typename T, int KS, int NT16, int RG, bool NTS>
+static int rowtile_launch_st(const LaunchRT& L, bool vec, hipStream_t st) {
     // persistent grid: as many workgroups as fit at once (queried occupancy),
     // but no more than there are groups of 4 row tiles
-    static const int occ_v = occupancy(rowtile_kernel<T, KS, NT16, RG, true, PF>, 256);
-    static const int occ_s = occupancy(rowtile_kernel<T, KS, NT16, RG, false, PF>, 256);
+    static const int occ_v = occupancy(rowtile_kernel<T, KS, NT16, RG, true, NTS>, 256);
+    static const int occ_s = occupancy(rowtile_kernel<T, KS, NT16, RG, false, NTS>, 256);
     constexpr int64_t TR = 16 * (16 / (int64_t)sizeof(T)) * RG;
     const int64_t ntiles = (L.m + TR - 1) / TR;
     int64_t bx = (int64_t)L.cus * (vec ? occ_v : occ_s) / (L.blocks_y > 0 ? L.blocks_y : 1);
@@ -363,22 +351,26 @@ static int rowtile_launch_pf(const LaunchRT& L, bool vec, hipStream_t st) {
     if (bx < 1) bx = 1;
     dim3 grid((unsigned)bx, (unsigned)L.blocks_y), block(256);
     if (vec)
-        TSM_LAUNCH((rowtile_kernel<T, KS, NT16, RG, true, PF>), grid, block, 0, st, L.m,
-                           L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
-                           (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
+        TSM_LAUNCH((rowtile_kernel<T, KS, NT16, RG, true, NTS>), grid, block, 0, st, L.m,
+                   L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
+                   (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
     else
-        TSM_LAUNCH((rowtile_kernel<T, KS, NT16, RG, false, PF>), grid, block, 0, st, L.m,
-                           L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in,
-                           L.ys_out, (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
+        TSM_LAUNCH((rowtile_kernel<T, KS, NT16, RG, false, NTS>), grid, block, 0, st, L.m,
+                   L.kin, L.nout, (const T*)L.X, L.ldx, (const T*)L.Y, L.ys_in, L.ys_out,
+                   (T*)L.O, L.ldo, (int64_t)L.cols_per_block, (T)L.beta);
     return 0;
 }
 
+// The stores of O are non-temporal (they fill whole cache lines: four columns
+// x 256 bytes per wavefront instruction); TSM2X_RT_NTS=0 selects ordinary
+// stores (measurement).  A next-tile register prefetch was measured and
+// dropped: the extra waves it costs hid the latency better.
 template <typename T, int KS, int NT16, int RG>
 static int rowtile_launch(const LaunchRT& L, bool vec, hipStream_t st) {
-    static const char* e = std::getenv("TSM2X_RT_PF");
-    const bool pf = e && *e == '1';   // measured: the extra waves beat the prefetch
-    return pf ? rowtile_launch_pf<T, KS, NT16, RG, true>(L, vec, st)
-              : rowtile_launch_pf<T, KS, NT16, RG, false>(L, vec, st);
+    const char* e = std::getenv("TSM2X_RT_NTS");
+    const bool nts = !(e && *e == '0');
+    return nts ? rowtile_launch_st<T, KS, NT16, RG, true>(L, vec, st)
+               : rowtile_launch_st<T, KS, NT16, RG, false>(L, vec, st);
 }
 
 template <typename T>

@@ -247,8 +247,8 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
 
     // No register prefetch of the next chunk: its 32-64 VGPRs cost a
     // wavefront of occupancy, and the resident wavefronts hide the latency
-    // better (measured: split form at n = 32 4.3 -> 6.0 TB/s, no instance
-    // slower).
+    // better (measured: split form at n = 32 4.3 -> 6.0 TB/s without it; with
+    // B's terms pre-split, the prefetch still lost 2-14 % on every instance).
     if (wk1 > wk0) {
         const int ng = (int)((wk1 - wk0 + 31) / 32);
         for (int g = 0; g < ng; ++g) {

@@ -233,3 +233,26 @@ def test_workspace_errors_leave_outputs_untouched(dev):
     assert rc == 3
     torch.cuda.synchronize()
     assert torch.isnan(dB).all() and (lab == -7).all()
+
+
+@pytest.mark.parametrize("lo", [False, True])
+@pytest.mark.parametrize("rowB", [False, True])
+def test_caller_workspace_precision_form(dev, lo, rowB):
+    """The precision form's workspace holds the split partials and B's packed
+    terms; tsm2x_workspace_size covers both, with B in either order, and a
+    smaller workspace is refused before any launch."""
+    m, k, n = 3000, 20000, 24
+    A = dev_matrix(23, si.STREAM_A, m, k, torch.float32, dev)
+    B = _rowmajor(23, si.STREAM_B, k, n, torch.float32, dev) if rowB else \
+        dev_matrix(23, si.STREAM_B, k, n, torch.float32, dev)
+    S = tsm.split(A, "bf16", lo=lo)
+    nb = tsm.workspace_size(tsm.OP_TSM2R, m, k, n, S.dtype_code)
+    assert nb > 0
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    C = tsm.tsm2r(S, B, workspace=ws)
+    assert torch.equal(C, tsm.tsm2r(S, B))
+    C2 = tsm.empty_colmajor(m, n, torch.float32, dev).fill_(7.0)
+    with pytest.raises(tsm.TSMError):
+        tsm.tsm2r(S, B, out=C2, workspace=ws[: nb - 256])
+    torch.cuda.synchronize()
+    assert bool((C2 == 7.0).all())

@@ -165,12 +165,13 @@ struct TNPlan {
 // R; the WK = 4 wavefronts split the slice.
 TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     TNPlan P{};
-    // output tiles per workgroup: two share each staged Y tile when there
-    // are several column groups (Y is then re-read by every group).  The
-    // 16-bit forms stage 128 rows per step, so two tiles need 101 KB of LDS
-    // per workgroup and one workgroup per CU: measured slower (bf16 split,
-    // 16384^2, n = 8: 3.97 TB/s against 4.88 with one tile), so one by default
-    P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", plain_dtype(dt) ? 2 : 1) : 1;
+    // output tiles per workgroup: two share each Y tile when there are
+    // several column groups (Y is then re-read by every group).  The 16-bit
+    // forms take Y straight from L2 then (staged in LDS too, two tiles needed
+    // one workgroup per CU); with n > 16 their registers allow one tile only
+    // (measured: n = 32, one tile 3.08 TB/s, two 2.95)
+    const int ct_dflt = plain_dtype(dt) ? 2 : (n <= 16 ? 2 : 1);
+    P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", ct_dflt) : 1;
     if (P.ct != 1 && P.ct != 2) P.ct = 1;
     // rows per wavefront loop iteration: G stages of 16*RL rows for the
     // float kernels (one stage with two output tiles), 128 for the 16-bit form

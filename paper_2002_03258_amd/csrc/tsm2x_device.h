@@ -9,6 +9,19 @@ namespace tsm {
 
 constexpr int WAVE = 64;
 
+// Orders this wavefront's LDS stores and loads around a hand-over of staged
+// data between its lanes.  The compiler sees one lane's accesses only: where
+// it can prove that a lane's own store and later load touch different
+// addresses (the lane reads what other lanes wrote), it may move the load
+// above the store, or reuse a load from an earlier tile, and the lane then
+// reads stale LDS.  The fence forbids that reordering; at wavefront scope it
+// emits no instruction (a wavefront's LDS operations complete in order).
+// Used before a tile is staged (its previous contents have been read) and
+// before the staged tile is read back.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
 template <typename T, int N>
 struct VecOf {
     typedef T type __attribute__((ext_vector_type(N)));

@@ -26,15 +26,6 @@
 
 namespace tsm {
 
-// Orders this wavefront's LDS stores and loads around a hand-over between its
-// lanes.  Each lane reads the staged tile at the same addresses for every
-// block; without the fence the compiler may reuse an earlier load in a lane
-// that stored nothing in between.  At wavefront scope no instruction is
-// needed (a wavefront's LDS operations complete in order).
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-}
-
 // AF < 0: A holds T.  AF = FMT_BF16 / FMT_F16 (T = float): A is the 16-bit hi
 // plane and, with ASPLIT, Alo the lo plane.  A only feeds dB, which is staged
 // through LDS, so a lane loads 8 rows of a column (one 16-byte run per plane)

@@ -250,6 +250,7 @@ __global__ __launch_bounds__(256) void tn_kernel(
 #pragma unroll
             for (int gs = 0; gs < G; ++gs) {
                 // stage: column 4 cg + kk, rows RL*rl .. RL*rl + RL - 1
+                wave_lds_fence();
 #pragma unroll
                 for (int cg = 0; cg < NC / 4; ++cg) {
                     typedef typename VecOf<T, RL>::type V;
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(256) void tn_kernel(
                 }
                 // read back in four blocks of 4*RL rows: X columns 16 ct + rl
                 // and Y columns NX + 16 t + rl, rows 4*RL*h + RL*kk + q
+                wave_lds_fence();
                 typedef typename VecOf<T, RL>::type V;
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {

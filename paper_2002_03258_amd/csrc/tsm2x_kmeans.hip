@@ -57,13 +57,6 @@ __global__ void kmeans_norms_kernel(int k, int n, const T* __restrict__ Mu, int6
     mu2[c] = s;
 }
 
-// Orders this wavefront's LDS stores and loads around a hand-over between its
-// lanes (the compiler may otherwise reuse an earlier load in a lane that
-// stored nothing in between); no instruction at wavefront scope.
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-}
-
 // (v, c) replaces (bv, bc) when smaller, or equal with a smaller index
 template <typename T>
 __device__ __forceinline__ void take_min(T v, int c, T& bv, int& bc) {

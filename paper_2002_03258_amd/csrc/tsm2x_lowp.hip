@@ -434,14 +434,18 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // tn_lp: O(ncols x n) = X^T * Y with X (R x ncols) in the low-precision form
 // and Y (R x n) float: the gradient dB = A^T * dC of the low-precision form.
 // As tn_kernel: per wavefront step of 128 rows, a lane loads 8 rows of one X
-// column per plane and 4 rows of one Y column twice (16 bytes each, four
-// columns per load instruction), widens X to float and stages both in a
-// wavefront-private LDS tile; it reads back X column rl and Y columns
-// 16 t + rl, 4 consecutive rows at a time, as the S and T operands of the
-// float 16x16x4 matrix cores.  Reduction across wavefronts and workgroups
-// as in tn_kernel.
+// column per plane (16 bytes, four columns per load instruction), widens X
+// to float and stages it in a wavefront-private LDS tile; it reads back X
+// column 16 ct + rl, 4 consecutive rows at a time, as the S operand of the
+// float 16x16x4 matrix cores.  The T operand, Y columns 16 t + rl at the
+// same rows, is either staged the same way (YD false: 4 rows of one column
+// twice per lane, when one column group streams Y from HBM once) or loaded
+// straight in operand order (YD: Y is small and every column group re-reads
+// it, so the loads hit L2 and need no LDS; CT output tiles per workgroup then
+// share each Y word).  Reduction across wavefronts and workgroups as in
+// tn_kernel.
 // --------------------------------------------------------------------------
-template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC>
+template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC, bool YD>
 __global__ __launch_bounds__(256) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
@@ -451,9 +455,10 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
     constexpr int SR = 128;                    // rows per step
     constexpr int SROW = SR + 4;               // padded LDS column (16 more bytes)
     constexpr int NX = 16 * CT;                // staged X columns (CT output tiles)
-    constexpr int NC = NX + 16 * NT16;         // then the Y columns
+    constexpr int NC = NX + (YD ? 0 : 16 * NT16);   // then the staged Y columns
     constexpr int XG = 4 * CT;                 // X column groups of 4
-    constexpr int YG = 4 * NT16;               // Y column groups of 4
+    constexpr int YG = 4 * NT16;               // Y column groups of 4 (staged Y)
+    constexpr int NB = SR / 16;                // 16-row blocks per step
     constexpr int NPL = SPLIT ? 2 : 1;
     __shared__ __align__(16) float lds[WK][NC][SROW];
     __shared__ double red[WK][WAVE][4 * NT16];
@@ -476,7 +481,34 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
 #pragma unroll
         for (int t = 0; t < NT16; ++t) acc[ct][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    auto load = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4], float (&yv)[2][YG][4]) {
+    // Y words a lane holds per step: staged (YD false), rows 64 h + 4 rl of
+    // column 4 cg + kk; direct (YD), the MFMA operand itself, rows
+    // 16 hb + 4 kk of column 16 t + rl (Y is small and re-read by every column
+    // group, so these loads hit L2; nothing of Y goes through LDS)
+    constexpr int YW = YD ? NB * NT16 : 2 * YG;
+    auto loadY = [&](int64_t rb, float (&yv)[YW][4]) {
+#pragma unroll
+        for (int yi = 0; yi < YW; ++yi) {
+            // staged: yi = h * YG + cg; direct: yi = hb * NT16 + t
+            const int64_t r = YD ? rb + 16 * (yi / NT16) + 4 * kk : rb + 64 * (yi / YG) + 4 * rl;
+            const int p = YD ? 16 * (yi % NT16) + rl : 4 * (yi % YG) + kk;
+            const int64_t valid = wb1 - r;
+            const bool full = valid >= 4;
+            if (YC && VEC && p < n && full) {
+                // Y re-read by every column group: through the cache
+                const f32x4 y = *reinterpret_cast<const f32x4*>(Y + r + (int64_t)p * ldy);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) yv[yi][q] = y[q];
+            } else if (p < n)
+                load_run<float, 4, VEC>(Y + r + (int64_t)p * ldy, valid, full, yv[yi]);
+            else
+#pragma unroll
+                for (int q = 0; q < 4; ++q) yv[yi][q] = 0.f;
+        }
+    };
+    // X (and staged Y) of a step are loaded one step ahead; direct Y is loaded
+    // at the start of its own step (its registers would cost a wavefront)
+    auto loadX = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4]) {
         {
             const int64_t r = rb + 8 * rl;
             const int64_t valid = wb1 - r;
@@ -495,39 +527,25 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
                 }
             }
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t r = rb + 64 * h + 4 * rl;
-            const int64_t valid = wb1 - r;
-            const bool full = valid >= 4;
-#pragma unroll
-            for (int cg = 0; cg < YG; ++cg) {
-                const int p = 4 * cg + kk;
-                if (YC && VEC && p < n && full) {
-                    // Y re-read by every column group: through the cache
-                    const f32x4 y = *reinterpret_cast<const f32x4*>(Y + r + (int64_t)p * ldy);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) yv[h][cg][q] = y[q];
-                } else if (p < n)
-                    load_run<float, 4, VEC>(Y + r + (int64_t)p * ldy, valid, full, yv[h][cg]);
-                else
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) yv[h][cg][q] = 0.f;
-            }
-        }
     };
 
     if (wb1 > wb0) {
         const int64_t nit = (wb1 - wb0 + SR - 1) / SR;
         uint32_t xv[XG][NPL][4];
-        float yv[2][YG][4];
-        load(wb0, xv, yv);
+        float yv[YW][4];
+        loadX(wb0, xv);
+        if (!YD) loadY(wb0, yv);
         for (int64_t it = 0; it < nit; ++it) {
             uint32_t xn[XG][NPL][4];
-            float yn[2][YG][4];
-            if (it + 1 < nit) load(wb0 + (it + 1) * SR, xn, yn);
+            float yn[YW][4];
+            if (YD) loadY(wb0 + it * SR, yv);
+            if (it + 1 < nit) {
+                loadX(wb0 + (it + 1) * SR, xn);
+                if (!YD) loadY(wb0 + (it + 1) * SR, yn);
+            }
             // stage: X column 4 cg + kk rows 8 rl .. 8 rl + 7 (widened),
             //        Y column NX + 4 cg + kk rows 64 h + 4 rl .. 64 h + 4 rl + 3
+            wave_lds_fence();
 #pragma unroll
             for (int cg = 0; cg < XG; ++cg) {
                 f32x4 x0, x1;
@@ -539,23 +557,30 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
                 *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl]) = x0;
                 *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl + 4]) = x1;
             }
+            if (!YD) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int cg = 0; cg < YG; ++cg) {
+                for (int yi = 0; yi < YW; ++yi) {
                     f32x4 y;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) y[q] = yv[h][cg][q];
-                    *reinterpret_cast<f32x4*>(&tile[NX + 4 * cg + kk][64 * h + 4 * rl]) = y;
+                    for (int q = 0; q < 4; ++q) y[q] = yv[yi][q];
+                    *reinterpret_cast<f32x4*>(&tile[NX + 4 * (yi % YG) + kk][64 * (yi / YG) + 4 * rl]) = y;
                 }
-            // read back 16-row blocks: rows 16 hb + 4 kk + q; each staged Y
-            // block serves the CT output tiles
+            }
+            // read back 16-row blocks: rows 16 hb + 4 kk + q; each Y block
+            // serves the CT output tiles
+            wave_lds_fence();
 #pragma unroll
-            for (int hb = 0; hb < SR / 16; ++hb) {
+            for (int hb = 0; hb < NB; ++hb) {
                 f32x4 ys[NT16];
 #pragma unroll
-                for (int t = 0; t < NT16; ++t)
-                    ys[t] = *reinterpret_cast<const f32x4*>(&tile[NX + 16 * t + rl][16 * hb + 4 * kk]);
+                for (int t = 0; t < NT16; ++t) {
+                    if (YD) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) ys[t][q] = yv[hb * NT16 + t][q];
+                    } else {
+                        ys[t] = *reinterpret_cast<const f32x4*>(&tile[NX + 16 * t + rl][16 * hb + 4 * kk]);
+                    }
+                }
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) {
                     const f32x4 xs = *reinterpret_cast<const f32x4*>(&tile[16 * ct + rl][16 * hb + 4 * kk]);
@@ -571,12 +596,12 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
                 for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
                     for (int d = 0; d < 4; ++d) xv[cg][pl][d] = xn[cg][pl][d];
+            if (!YD) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+                for (int yi = 0; yi < YW; ++yi)
 #pragma unroll
-                for (int cg = 0; cg < YG; ++cg)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) yv[h][cg][q] = yn[h][cg][q];
+                    for (int q = 0; q < 4; ++q) yv[yi][q] = yn[yi][q];
+            }
         }
     }
 
@@ -773,29 +798,39 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
     const int ni = (int)L.n;
     // Y is re-read by every column group: cached loads when there are several
     const bool yc = gx > 1;
-#define TSM_T(F, NT, CT, SP)                                                                    \
-    {                                                                                           \
-        if (vec && yc)                                                                          \
-            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, true>), g, b, 0, st, L.R, L.ncols,    \
-                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,         \
-                       L.rslice, L.part);                                                       \
-        else if (vec)                                                                           \
-            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, false>), g, b, 0, st, L.R, L.ncols,   \
-                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,         \
-                       L.rslice, L.part);                                                       \
-        else                                                                                    \
-            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, false, false>), g, b, 0, st, L.R, L.ncols,  \
-                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,         \
-                       L.rslice, L.part);                                                       \
-        return 0;                                                                               \
+#define TSM_T(F, NT, CT, SP, YD)                                                                  \
+    {                                                                                             \
+        if (vec && yc)                                                                            \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, true, YD>), g, b, 0, st, L.R, L.ncols,  \
+                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,           \
+                       L.rslice, L.part);                                                         \
+        else if (vec)                                                                             \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, false, YD>), g, b, 0, st, L.R, L.ncols, \
+                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,           \
+                       L.rslice, L.part);                                                         \
+        else                                                                                      \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, false, false, YD>), g, b, 0, st, L.R,         \
+                       L.ncols, ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,  \
+                       L.rslice, L.part);                                                         \
+        return 0;                                                                                 \
     }
-#define TSM_T2(F, SP)                                                   \
-    {                                                                   \
-        if (L.ct == 2) {                                                \
-            if (L.n <= 16) TSM_T(F, 1, 2, SP) else TSM_T(F, 2, 2, SP)   \
-        } else {                                                        \
-            if (L.n <= 16) TSM_T(F, 1, 1, SP) else TSM_T(F, 2, 1, SP)   \
-        }                                                               \
+    // Y straight from L2 when several column groups re-read it (measured,
+    // bf16 split, 16384^2, n = 8: 4.9 TB/s staged, 5.2 direct, 5.85 direct
+    // with two tiles per workgroup); staged through LDS when one group
+    // streams it from HBM once (2^23 x 16: 5.15 staged, 4.06 direct).  Two
+    // output tiles per workgroup always take Y direct (staged, they need
+    // 101 KB of LDS per workgroup).  TSM2X_TN_YD=0/1 overrides (measurement).
+    const char* yde = std::getenv("TSM2X_TN_YD");
+    const bool yd = (yde && *yde) ? *yde == '1' : yc;
+#define TSM_T2(F, SP)                                                                     \
+    {                                                                                     \
+        if (L.ct == 2) {                                                                  \
+            if (L.n <= 16) TSM_T(F, 1, 2, SP, true) else TSM_T(F, 2, 2, SP, true)         \
+        } else if (yd) {                                                                  \
+            if (L.n <= 16) TSM_T(F, 1, 1, SP, true) else TSM_T(F, 2, 1, SP, true)         \
+        } else {                                                                          \
+            if (L.n <= 16) TSM_T(F, 1, 1, SP, false) else TSM_T(F, 2, 1, SP, false)       \
+        }                                                                                 \
     }
     if (fmt == FMT_BF16) {
         if (split) TSM_T2(FMT_BF16, true) else TSM_T2(FMT_BF16, false)

@@ -14,9 +14,16 @@ from helpers import dev_matrix, err, host_matrix, host_rows, sample_rows, to_np
 pytestmark = pytest.mark.gpu
 
 FMTS = [("bf16", oracle.BF16), ("f16", oracle.F16)]
-# normwise error bounds against the oracle on the stored values hi (+ lo):
-# float accumulation plus the dropped B terms
-TOL_STORED = 1e-5
+# normwise error bound against the oracle on the stored values hi (+ lo):
+# float accumulation alone (every product of hi (+ lo) and B above 2^-24
+# |a||b| is kept, each pinned exactly below).  Measured at most 1.1e-6 (A
+# 32768^2, n = 32; dB over 2^23 rows); a dropped hi*B3 measured 2.3e-6.
+TOL_STORED = 3e-6
+# componentwise, max |C - C_ref| / (|A||B|), against the stored values: the
+# float sums' error relative to the products' magnitudes; bounded by
+# gamma_L = L u for L sequential float additions (L <= 32 per MFMA chain
+# step); measured at most 2.3e-8 at full size
+TOL_CW_STORED = 1e-6
 # against the float A: the storage error of the form
 TOL_VALUE = {("bf16", False): 4e-3, ("f16", False): 5e-4, ("bf16", True): 2e-5,
              ("f16", True): 2e-5}
@@ -113,10 +120,14 @@ def test_tsm2r_lowp_full_size_sampled(dev, fmt, code):
             B = dev_matrix(seed + n, si.STREAM_B, k, n, torch.float32, dev)
             Bh = host_matrix(seed + n, si.STREAM_B, k, n, torch.float32)
             Cs = to_np(tsm.tsm2r(S, B)[rows])
-            e_s = err(Cs, oracle.matmul(stored, Bh))
+            ref_s = oracle.matmul(stored, Bh)
+            e_s = err(Cs, ref_s)
             e_v = err(Cs, oracle.matmul(Ar, Bh))
-            print(fmt, "split" if with_lo else "single", n, "err stored %.2e value %.2e" % (e_s, e_v))
+            cw = oracle.componentwise_error(Cs, ref_s, stored, Bh)
+            print(fmt, "split" if with_lo else "single", n,
+                  "err stored %.2e (componentwise %.2e) value %.2e" % (e_s, cw, e_v))
             assert e_s <= TOL_STORED and e_v <= TOL_VALUE[(fmt, with_lo)]
+            assert cw <= TOL_CW_STORED
         del S
     del A
     torch.cuda.empty_cache()

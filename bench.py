@@ -595,6 +595,44 @@ def sources_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
+# (dtype, m) of the m x 16 TSM2L pattern probes: the TSM2L row shape and the
+# headline's TSM2L shape
+PATTERN_SHAPES = ((torch.float64, 1 << 24), (torch.float64, 1 << 23), (torch.float32, 1 << 23))
+STREAM_CEILINGS = ("read_GBps", "copy_GBps", "write_GBps")
+
+
+def pattern_key(prefix: str, dtype, m: int) -> str:
+    return "%s%s_m%d_k16_GBps" % (prefix, str(dtype).replace("torch.", ""), m)
+
+
+def ceiling_key(kind: str, mode: str, role: str, m: int) -> str:
+    """The measured ceiling (a key of measure_ceilings) with the access mix of
+    a headline call: the TSM2L patterns for the TSM2L calls (the bf16 hi and
+    lo planes move 4 bytes an element, as float32 does), the streaming read
+    for the TSM2R forward and dB (A read, little written), the streaming
+    write for the TSM2R dA (dA written, little read)."""
+    if kind == "L":
+        dt = torch.float64 if mode == "f64" else torch.float32
+        return pattern_key("tsm2l_pattern_" if role == "fwd" else "tsm2l_bwd_pattern_", dt, m)
+    return "write_GBps" if role == "grad_a" else "read_GBps"
+
+
+def attach_call_ceilings(line, ceilings):
+    """Each timed call's (and the roofline kernel's) fraction of the measured
+    ceiling of its access mix."""
+    def put(d, key):
+        v = ceilings.get(key)
+        if v:
+            d["measured_ceiling"] = key
+            d["measured_ceiling_GBps"] = v
+            d["frac_of_measured_ceiling"] = d["GBps" if "GBps" in d else "achieved"] / v
+    for case in line["config"]["cases"]:
+        for d in case["calls"].values():
+            put(d, d["ceiling"])
+    if line.get("roofline"):
+        put(line["roofline"], line["roofline"]["ceiling"])
+
+
 def roofline_of(cases, timing):
     """The dominant kernel of the timed steps: the (kernel, tag) row of the
     library's launch timing with the largest total time, its algorithmic
@@ -625,7 +663,8 @@ def roofline_of(cases, timing):
             "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": avg_s * 1e6,
             "launches": r["launches"], "algorithmic_bytes_per_launch": per_launch,
             "workload": workload, "traffic": traffic,
-            "traffic_over_algorithmic": (traffic / per_launch) if traffic else None}
+            "traffic_over_algorithmic": (traffic / per_launch) if traffic else None,
+            "ceiling": ceiling_key(c.kind, c.mode, role, c.m)}
 
 
 def headline(dev, steps, warmup, check=True):
@@ -675,6 +714,7 @@ def headline(dev, steps, warmup, check=True):
         for role, d in calls.items():
             d["GBps"] = c.bytes[role] / (d["ms_per_launch"] / 1e3) / 1e9
             d["bytes"] = c.bytes[role]
+            d["ceiling"] = ceiling_key(c.kind, c.mode, role, c.m)
         per_case.append({"case": c.name, "shape": (c.m, c.k, c.n), "mode": c.mode,
                          "bytes": c.total_bytes, "ms_median": t * 1e3,
                          "GBps": c.total_bytes / t / 1e9,
@@ -712,10 +752,12 @@ def headline(dev, steps, warmup, check=True):
 
 def measure_ceilings(dev):
     """HBM ceilings of this device with 16-byte non-temporal accesses: a
-    4 GiB linear read, a 2 GiB copy, a 4 GiB write, and the TSM2L tile pattern
-    without arithmetic on the 2^24 x 16 FP64 and 2^23 x 16 FP32 shapes (A read
-    once, C = a column permutation of A written once).  Each the median of 5
-    runs after a warm-up; GB/s counts the bytes moved."""
+    4 GiB linear read, a 2 GiB copy, a 4 GiB write, and the TSM2L tile
+    patterns without arithmetic on m x 16 FP64 (m = 2^24, 2^23) and FP32
+    (m = 2^23): the forward's (A read once, a column permutation of A written
+    once) and the fused backward's (two such inputs read, one output
+    written).  Each the median of 5 runs after a warm-up; GB/s counts the
+    bytes moved."""
     out = {}
     big = torch.empty(1 << 32, dtype=torch.uint8, device=dev).fill_(1)
     dst = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
@@ -727,17 +769,20 @@ def measure_ceilings(dev):
     t = timed(lambda: tsm.probe_stream("write", dst))
     out["write_GBps"] = dst.numel() / t / 1e9
     del big, dst
-    for dt, m in ((torch.float64, 1 << 24), (torch.float32, 1 << 23)):
+    for dt, m in PATTERN_SHAPES:
         X = si.matrix(si.config_seed(9), si.STREAM_A, m, 16, dtype=dt, device=dev)
+        Y = si.matrix(si.config_seed(9), si.STREAM_B, m, 16, dtype=dt, device=dev)
         O = tsm.empty_colmajor(m, 16, dt, dev)
         t = timed(lambda: tsm.probe_tiles(X, O))
-        out["tsm2l_pattern_%s_m%d_k16_GBps" % (str(dt).replace("torch.", ""), m)] = \
-            2 * X.numel() * X.element_size() / t / 1e9
-        del X, O
+        out[pattern_key("tsm2l_pattern_", dt, m)] = 2 * X.numel() * X.element_size() / t / 1e9
+        t = timed(lambda: tsm.probe_tiles(X, O, Y=Y))
+        out[pattern_key("tsm2l_bwd_pattern_", dt, m)] = 3 * X.numel() * X.element_size() / t / 1e9
+        del X, Y, O
     torch.cuda.empty_cache()
     out["note"] = ("16-byte non-temporal loads/stores; read 4 GiB, copy 2 GiB -> 2 GiB (bytes "
                    "read + written), write 4 GiB; TSM2L pattern = the rowtile kernel's loads and "
-                   "stores without the matrix-core work")
+                   "stores without the matrix-core work; TSM2L bwd pattern = the fused backward's "
+                   "(two inputs read, one output written)")
     return out
 
 
@@ -992,6 +1037,7 @@ def main():
     ceil = measure_ceilings(dev)
     line["ceilings"] = ceil
     line["config"]["frac_of_measured_copy_ceiling"] = h["value"] / ceil["copy_GBps"]
+    attach_call_ceilings(line, ceil)
     print("ceilings measured", file=sys.stderr, flush=True)
     if not args.no_rows:
         rows = []

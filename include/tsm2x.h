@@ -348,12 +348,15 @@ int tsm2x_timing_row(int i, const char** kernel, int* tag, int64_t* launches,
  * walks for (kin, nout), loading every element of X once and storing every
  * element of O once.  O receives X's columns in a fixed mapping (output
  * column 16t + j of a tile takes one input column of the same rows); only
- * the bytes moved matter.  Arguments: 1 m, 2 kin, 3 nout, 4 X, 5 ldx, 6 O,
- * 7 ldo, 8 dtype, 9 blocks, 10 stream. */
+ * the bytes moved matter.  With Y (m-by-kin, leading dimension ldy; NULL for
+ * none) both X and Y are read, in the taller tiles of the fused TSM2L
+ * backward, and O takes X + Y under the same mapping: the pattern of that
+ * kernel (A and dC read, dA written).  Arguments: 1 m, 2 kin, 3 nout, 4 X,
+ * 5 ldx, 6 Y, 7 ldy, 8 O, 9 ldo, 10 dtype, 11 blocks, 12 stream. */
 int tsm2x_probe_stream(int kind, const void* src, void* dst, int64_t bytes, int64_t blocks,
                        void* stream);
-int tsm2x_probe_tiles(int64_t m, int kin, int nout, const void* X, int64_t ldx, void* O,
-                      int64_t ldo, int dtype, int64_t blocks, void* stream);
+int tsm2x_probe_tiles(int64_t m, int kin, int nout, const void* X, int64_t ldx, const void* Y,
+                      int64_t ldy, void* O, int64_t ldo, int dtype, int64_t blocks, void* stream);
 
 /* Static description of an error code (never NULL). */
 const char* tsm2x_error_string(int code);

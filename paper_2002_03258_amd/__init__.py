@@ -424,15 +424,22 @@ def probe_stream(kind: str, dst: torch.Tensor, src: torch.Tensor | None = None,
               dst.data_ptr(), int(nbytes), int(blocks), _stream())
 
 
-def probe_tiles(X: torch.Tensor, O: torch.Tensor, blocks: int = 0) -> None:
+def probe_tiles(X: torch.Tensor, O: torch.Tensor, Y: torch.Tensor | None = None,
+                blocks: int = 0) -> None:
     """Bandwidth probe (measurement support): the TSM2L kernel's access
     pattern without its arithmetic, X (m x kin) read once and O (m x nout)
-    written once, both column-major float64 or float32."""
+    written once, all column-major float64 or float32.  With Y (like X), the
+    fused TSM2L backward's pattern: X and Y read, O written."""
     _check_device(X, O)
     if not (is_colmajor(X) and is_colmajor(O)) or X.shape[0] != O.shape[0] or \
             X.dtype != O.dtype:
         raise ValueError("X and O must be column-major with the same rows and dtype")
+    if Y is not None:
+        _check_device(Y)
+        if not is_colmajor(Y) or tuple(Y.shape) != tuple(X.shape) or Y.dtype != X.dtype:
+            raise ValueError("Y must be column-major with X's shape and dtype")
     _lib.call("tsm2x_probe_tiles", X.shape[0], X.shape[1], O.shape[1], X.data_ptr(), _ld(X),
+              Y.data_ptr() if Y is not None else None, _ld(Y) if Y is not None else 1,
               O.data_ptr(), _ld(O), _plain_dtype(X), int(blocks), _stream())
 
 

@@ -83,7 +83,7 @@ def lib():
             L.tsm2x_timing_row.restype = i32
             L.tsm2x_probe_stream.argtypes = [i32, vp, vp, i64, i64, vp]
             L.tsm2x_probe_stream.restype = i32
-            L.tsm2x_probe_tiles.argtypes = [i64, i32, i32, vp, i64, vp, i64, i32, i64, vp]
+            L.tsm2x_probe_tiles.argtypes = [i64, i32, i32, vp, i64, vp, i64, vp, i64, i32, i64, vp]
             L.tsm2x_probe_tiles.restype = i32
             for f in ("tsm2r", "tsm2l", "tsm2r_ex", "tsm2l_ex", "tsm2x_gemm", "tsm_grad_a",
                       "tsm_grad_b",

@@ -10,7 +10,10 @@
 //                       tiles, each lane loading 16-byte runs of the kin
 //                       input columns (4 columns x 256 bytes per wavefront
 //                       instruction) and storing 16-byte runs of the nout
-//                       output columns in the rowtile order.
+//                       output columns in the rowtile order.  With a second
+//                       input (TWO), the pattern of the fused TSM2L backward:
+//                       two inputs of kin columns read, one output written,
+//                       in its taller tiles.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,11 +67,13 @@ __global__ __launch_bounds__(256) void probe_stream_kernel(const u32x4p* __restr
 }
 
 // Output column c = 16 t + mrow(kk, rr) of a row tile receives input column
-// 4 ((4 t + rr) % KS) + kk of the same rows: a fixed column mapping, so that
-// every store depends on a load; only the bytes moved matter.
-template <typename T, int KS, int NT16, int RG, bool VEC>
+// 4 ((4 t + rr) % KS) + kk of the same rows (of X, or of X + Y with TWO): a
+// fixed column mapping, so that every store depends on a load; only the
+// bytes moved matter.
+template <typename T, int KS, int NT16, int RG, bool VEC, bool TWO>
 __global__ __launch_bounds__(256) void probe_tiles_kernel(int64_t m, int kin, int nout,
                                                           const T* __restrict__ X, int64_t ldx,
+                                                          const T* __restrict__ Y, int64_t ldy,
                                                           T* __restrict__ O, int64_t ldo) {
     typedef Mfma<T> M;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -82,19 +87,29 @@ __global__ __launch_bounds__(256) void probe_tiles_kernel(int64_t m, int kin, in
     for (int64_t tile = (int64_t)blockIdx.x * WPB + w; tile < ntiles; tile += tstride) {
         const int64_t row0 = tile * TR;
         const bool full = row0 + TR <= m;
-        T xv[KS][RG][RL];
+        T xv[KS][RG][RL], yv[TWO ? KS : 1][RG][RL];
 #pragma unroll
         for (int st = 0; st < KS; ++st) {
             const int ji = 4 * st + kk;
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
                 const int64_t r = row0 + 16 * RL * g + RL * rl;
-                if (ji < kin)
+                if (ji < kin) {
                     load_run<T, RL, VEC>(X + r + ji * ldx, m - r, full, xv[st][g]);
-                else
+                    if (TWO) load_run<T, RL, VEC>(Y + r + ji * ldy, m - r, full, yv[TWO ? st : 0][g]);
+                } else {
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) xv[st][g][q] = T(0);
+                    for (int q = 0; q < RL; ++q) xv[st][g][q] = yv[TWO ? st : 0][g][q] = T(0);
+                }
             }
+        }
+        if (TWO) {
+#pragma unroll
+            for (int st = 0; st < KS; ++st)
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) xv[st][g][q] += yv[TWO ? st : 0][g][q];
         }
 #pragma unroll
         for (int g = 0; g < RG; ++g) {
@@ -119,12 +134,14 @@ static int probe_occupancy(K kernel) {
     return nb;
 }
 
-template <typename T, int KS, int NT16, int RG>
-static void probe_tiles_go(int64_t m, int kin, int nout, const void* X, int64_t ldx, void* O,
-                           int64_t ldo, int64_t blocks, int cus, hipStream_t st) {
+template <typename T, int KS, int NT16, int RG, bool TWO>
+static void probe_tiles_go(int64_t m, int kin, int nout, const void* X, int64_t ldx,
+                           const void* Y, int64_t ldy, void* O, int64_t ldo, int64_t blocks,
+                           int cus, hipStream_t st) {
     const bool vec = ((uintptr_t)X & 15u) == 0 && ((uintptr_t)O & 15u) == 0 &&
-                     (ldx * (int64_t)sizeof(T)) % 16 == 0 && (ldo * (int64_t)sizeof(T)) % 16 == 0;
-    static const int occ = probe_occupancy(probe_tiles_kernel<T, KS, NT16, RG, true>);
+                     (ldx * (int64_t)sizeof(T)) % 16 == 0 && (ldo * (int64_t)sizeof(T)) % 16 == 0 &&
+                     (!TWO || (((uintptr_t)Y & 15u) == 0 && (ldy * (int64_t)sizeof(T)) % 16 == 0));
+    static const int occ = probe_occupancy(probe_tiles_kernel<T, KS, NT16, RG, true, TWO>);
     constexpr int64_t TR = 16 * (16 / (int64_t)sizeof(T)) * RG;
     const int64_t need = ((m + TR - 1) / TR + 3) / 4;
     int64_t bx = blocks > 0 ? blocks : (int64_t)cus * occ;
@@ -132,28 +149,36 @@ static void probe_tiles_go(int64_t m, int kin, int nout, const void* X, int64_t 
     if (bx > 0x7fffffff) bx = 0x7fffffff;
     if (bx < 1) bx = 1;
     if (vec)
-        TSM_LAUNCH((probe_tiles_kernel<T, KS, NT16, RG, true>), dim3((unsigned)bx), dim3(256), 0, st,
-                   m, kin, nout, (const T*)X, ldx, (T*)O, ldo);
+        TSM_LAUNCH((probe_tiles_kernel<T, KS, NT16, RG, true, TWO>), dim3((unsigned)bx), dim3(256), 0,
+                   st, m, kin, nout, (const T*)X, ldx, (const T*)Y, ldy, (T*)O, ldo);
     else
-        TSM_LAUNCH((probe_tiles_kernel<T, KS, NT16, RG, false>), dim3((unsigned)bx), dim3(256), 0,
-                   st, m, kin, nout, (const T*)X, ldx, (T*)O, ldo);
+        TSM_LAUNCH((probe_tiles_kernel<T, KS, NT16, RG, false, TWO>), dim3((unsigned)bx), dim3(256),
+                   0, st, m, kin, nout, (const T*)X, ldx, (const T*)Y, ldy, (T*)O, ldo);
 }
 
-// the row groups per lane of the rowtile instance for (kin, nout)
+// the row groups per lane of the rowtile instance for (kin, nout); with two
+// inputs those of the fused backward (two groups)
 template <typename T>
-static void probe_tiles_pick(int64_t m, int kin, int nout, const void* X, int64_t ldx, void* O,
-                             int64_t ldo, int64_t blocks, int cus, hipStream_t st) {
+static void probe_tiles_pick(int64_t m, int kin, int nout, const void* X, int64_t ldx,
+                             const void* Y, int64_t ldy, void* O, int64_t ldo, int64_t blocks,
+                             int cus, hipStream_t st) {
     const bool wide = nout > 16;
-    if (kin <= 8) {
-        if (wide) probe_tiles_go<T, 2, 2, 2>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
-        else probe_tiles_go<T, 2, 1, 2>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
-    } else if (kin <= 16) {
-        if (wide) probe_tiles_go<T, 4, 2, 2>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
-        else probe_tiles_go<T, 4, 1, 1>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
-    } else {
-        if (wide) probe_tiles_go<T, 8, 2, 1>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
-        else probe_tiles_go<T, 8, 1, 1>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
+#define TSM_P(KS, NT, RG)                                                                          \
+    {                                                                                              \
+        if (Y) probe_tiles_go<T, KS, NT, 2, true>(m, kin, nout, X, ldx, Y, ldy, O, ldo, blocks,   \
+                                                   cus, st);                                        \
+        else probe_tiles_go<T, KS, NT, RG, false>(m, kin, nout, X, ldx, Y, ldy, O, ldo, blocks,   \
+                                                   cus, st);                                        \
+        return;                                                                                    \
     }
+    if (kin <= 8) {
+        if (wide) TSM_P(2, 2, 2) else TSM_P(2, 1, 2)
+    } else if (kin <= 16) {
+        if (wide) TSM_P(4, 2, 2) else TSM_P(4, 1, 1)
+    } else {
+        if (wide) TSM_P(8, 2, 1) else TSM_P(8, 1, 1)
+    }
+#undef TSM_P
 }
 
 }  // namespace tsm
@@ -186,17 +211,18 @@ int tsm2x_probe_stream(int kind, const void* src, void* dst, int64_t bytes, int6
     return e == hipSuccess ? TSM_SUCCESS : TSM_ERR_HIP;
 }
 
-int tsm2x_probe_tiles(int64_t m, int kin, int nout, const void* X, int64_t ldx, void* O,
-                      int64_t ldo, int dtype, int64_t blocks, void* stream) {
+int tsm2x_probe_tiles(int64_t m, int kin, int nout, const void* X, int64_t ldx, const void* Y,
+                      int64_t ldy, void* O, int64_t ldo, int dtype, int64_t blocks, void* stream) {
     if (m < 0) return -1;
     if (kin < 1 || kin > 32) return -2;
     if (nout < 1 || nout > 32) return -3;
     if (!X && m > 0) return -4;
     if (ldx < (m > 1 ? m : 1)) return -5;
-    if (!O && m > 0) return -6;
-    if (ldo < (m > 1 ? m : 1)) return -7;
-    if (dtype != TSM_F64 && dtype != TSM_F32) return -8;
-    if (blocks < 0) return -9;
+    if (Y && ldy < (m > 1 ? m : 1)) return -7;
+    if (!O && m > 0) return -8;
+    if (ldo < (m > 1 ? m : 1)) return -9;
+    if (dtype != TSM_F64 && dtype != TSM_F32) return -10;
+    if (blocks < 0) return -11;
     if (m == 0) return TSM_SUCCESS;
     int cus = 0;
     int dev = 0;
@@ -205,8 +231,10 @@ int tsm2x_probe_tiles(int64_t m, int kin, int nout, const void* X, int64_t ldx, 
         cus < 1)
         cus = 256;
     hipStream_t st = (hipStream_t)stream;
-    if (dtype == TSM_F64) probe_tiles_pick<double>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
-    else probe_tiles_pick<float>(m, kin, nout, X, ldx, O, ldo, blocks, cus, st);
+    if (dtype == TSM_F64)
+        probe_tiles_pick<double>(m, kin, nout, X, ldx, Y, ldy, O, ldo, blocks, cus, st);
+    else
+        probe_tiles_pick<float>(m, kin, nout, X, ldx, Y, ldy, O, ldo, blocks, cus, st);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? TSM_SUCCESS : TSM_ERR_HIP;
 }

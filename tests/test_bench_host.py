@@ -112,6 +112,25 @@ def test_rows_take_the_ceiling_of_their_traffic_mix():
     assert rows[2]["frac_of_measured_ceiling"] == pytest.approx(1.0)
 
 
+def test_every_headline_call_has_a_measured_ceiling():
+    keys = set(bench.STREAM_CEILINGS)
+    for dt, m in bench.PATTERN_SHAPES:
+        keys |= {bench.pattern_key(p, dt, m) for p in ("tsm2l_pattern_", "tsm2l_bwd_pattern_")}
+    for shape, kind, m, k, n in bench.AG_SHAPES:
+        for mode in bench.AG_MODES:
+            roles = ("fwd", "bwd") if kind == "L" else ("fwd", "grad_a", "grad_b")
+            for role in roles:
+                assert bench.ceiling_key(kind, mode, role, m) in keys, (kind, mode, role)
+    assert bench.ceiling_key("L", "f64", "bwd", 1 << 23) == \
+        "tsm2l_bwd_pattern_float64_m8388608_k16_GBps"
+    assert bench.ceiling_key("R", "bf16_split", "grad_a", 16384) == "write_GBps"
+    line = {"config": {"cases": [{"calls": {"bwd": {"GBps": 2000.0, "ceiling": "c"}}}]},
+            "roofline": {"achieved": 3000.0, "ceiling": "c"}}
+    bench.attach_call_ceilings(line, {"c": 4000.0})
+    assert line["config"]["cases"][0]["calls"]["bwd"]["frac_of_measured_ceiling"] == 0.5
+    assert line["roofline"]["frac_of_measured_ceiling"] == 0.75
+
+
 def _summaries():
     out = []
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_counters.txt")):

@@ -135,15 +135,19 @@ def _tile_source_column(c, kin, es, nout):
     return 4 * ((4 * t + rr) % KS) + kk
 
 
+@pytest.mark.parametrize("two", [False, True])
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 @pytest.mark.parametrize("m,kin,nout", [(1000, 16, 16), (777, 8, 8), (4099, 32, 32),
                                         (513, 16, 32), (300, 5, 3)])
-def test_tile_probe_moves_every_element(dev, dt, m, kin, nout):
+def test_tile_probe_moves_every_element(dev, dt, m, kin, nout, two):
     X = _m(m, kin, dt, dev)
+    Y = _m(m, kin, dt, dev, stream=si.STREAM_B) if two else None
     O = tsm.empty_colmajor(m, nout, dt, dev)
     O.fill_(float("nan"))
-    tsm.probe_tiles(X, O)
+    tsm.probe_tiles(X, O, Y=Y)
     Xh, Oh = to_np(X), to_np(O)
+    if two:
+        Xh = (X.cpu() + Y.cpu()).to(torch.float64).numpy()   # the add in X's own precision
     es = 8 if dt == torch.float64 else 4
     for c in range(nout):
         src = _tile_source_column(c, kin, es, nout)

@@ -104,13 +104,16 @@ __device__ __forceinline__ T beta_out(double v, double beta, const T* p) {
     return (T)(beta != 0.0 ? v + beta * (double)*p : v);
 }
 
-// Sum of the WK wavefronts' partials (double, wavefront order) for one row
-// tile.  With one k slice the result is the output; otherwise it is this
-// workgroup's partial, part[((tile * nsl + s) * NP + p) * TR + row], and a
-// second kernel (split_reduce_kernel) adds the slices in order.  `red` is LDS
-// scratch of [WK][PG][TR] doubles; put(pg, red) stores this wavefront's values
-// of columns pg .. pg+PG-1.  C := beta*C + sum (C is read only if beta != 0).
-template <typename T, int NP, int WK, int TR, int PG, typename Put>
+// Sum of NSUM wavefronts' partials (double, wavefront order) for one row
+// tile of TR rows of a workgroup of WK wavefronts.  With one k slice the
+// result is the output; otherwise it is this workgroup's partial,
+// part[((tile * nsl + s) * NP + p) * TR + row], and a second kernel
+// (split_reduce_kernel) adds the slices in order.  `red` is LDS scratch of
+// [NSUM][PG][TR] doubles; put(pg, red) stores this wavefront's values of
+// columns pg .. pg+PG-1 (NSUM = WK: every wavefront all TR rows, summed;
+// NSUM = 1: each wavefront its own rows of the tile).  C := beta*C + sum (C is
+// read only if beta != 0).
+template <typename T, int NP, int WK, int TR, int PG, int NSUM = WK, typename Put>
 __device__ __forceinline__ void nn_finish(int64_t m, int n, T* __restrict__ C, int64_t ldc,
                                           double beta, int64_t tile, int s, int nsl,
                                           double* __restrict__ part, double* red, Put&& put) {
@@ -128,7 +131,7 @@ __device__ __forceinline__ void nn_finish(int64_t m, int n, T* __restrict__ C, i
                 const int64_t row = row0 + rr;
                 double v = red[pp * TR + rr];
 #pragma unroll
-                for (int ww = 1; ww < WK; ++ww) v += red[(ww * PG + pp) * TR + rr];
+                for (int ww = 1; ww < NSUM; ++ww) v += red[(ww * PG + pp) * TR + rr];
                 if (p < n && row < m) {
                     if (nsl == 1)
                         C[row + p * ldc] = beta_out(v, beta, C + row + p * ldc);

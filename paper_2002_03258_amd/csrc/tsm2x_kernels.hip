@@ -455,7 +455,11 @@ int launch_tn(const LaunchTN& L, int dtype, hipStream_t st) {
 int launch_split_reduce(int dtype, int64_t groups, int S, int NP, int W, int64_t rows, int n,
                         const double* part, void* O, int64_t ldo, double beta, hipStream_t st) {
     const int64_t total = groups * NP * W;
-    const bool wide = S >= 16;
+    // a wavefront per output only where there are too few outputs to fill the
+    // GPU with a thread each (2^18 outputs of 16 slices: the wavefront form's
+    // lanes read 16 partials 2^21 bytes apart, and the precision-form TSM2R
+    // at A 16384^2, n = 8 ran 14 % slower with 16 slices than with 15)
+    const bool wide = S >= 16 && total < (int64_t)1 << 16;
     int64_t blocks = wide ? (total + 3) / 4 : (total + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;

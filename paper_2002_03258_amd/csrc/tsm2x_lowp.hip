@@ -186,13 +186,20 @@ __global__ __launch_bounds__(256) void split_b_kernel(int64_t k, int n, const fl
     }
 }
 
-template <int FMT, int NT16, bool SPLIT, int WK, bool VEC>
+// RS false: the WK wavefronts of a workgroup share one 128-row tile and split
+// its k slice in WK parts, summed in the finish.  RS true: they take WK
+// adjacent 128-row tiles over the whole k slice, so that a workgroup reads
+// WK x 256 contiguous bytes of every column it visits (longer runs per column
+// at a time read faster: measured 6.47 -> 6.84 TB/s for the bare pattern),
+// and each wavefront's sums are final for its rows.
+template <int FMT, int NT16, bool SPLIT, int WK, bool VEC, bool RS>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, const u32x4* __restrict__ Bt,
     float* __restrict__ C, int64_t ldc, int64_t kslice, double* __restrict__ part,
     double beta) {
-    constexpr int TR = 128;              // 16 lanes x 8 rows
+    constexpr int TR = 128;              // a wavefront's tile: 16 lanes x 8 rows
+    constexpr int TRW = RS ? WK * TR : TR;   // the workgroup's rows
     constexpr int NP = 16 * NT16;
     constexpr int PG = 4;
     constexpr int NPL = SPLIT ? 2 : 1;   // planes
@@ -204,13 +211,13 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     const int w = threadIdx.x / WAVE;
     const int64_t tile = blockIdx.x;
     const int s = blockIdx.y, nsl = gridDim.y;
-    const int64_t row0 = tile * TR;
+    const int64_t row0 = tile * TRW + (RS ? w * TR : 0);
     const int64_t r = row0 + 8 * rl;     // this lane's 8 rows
     const bool full = (row0 + TR <= m);
     const int64_t kb0 = (int64_t)s * kslice;
     const int64_t kb1 = (kb0 + kslice < k) ? kb0 + kslice : k;
-    const int64_t lw = kslice / WK;
-    const int64_t wk0 = kb0 + w * lw;
+    const int64_t lw = RS ? kslice : kslice / WK;
+    const int64_t wk0 = kb0 + (RS ? 0 : w * lw);
     const int64_t wk1 = (wk0 + lw < kb1) ? wk0 + lw : kb1;
 
     f32x4 acc[8][NT16];
@@ -245,57 +252,63 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
             for (int e = 0; e < NBT; ++e) bt[t][e] = Bt[((c * NT16 + t) * NBT + e) * WAVE + lane];
     };
 
+    // the products of the chunk at j0 whose A is in raw
+    auto chunk = [&](int64_t j0, const uint32_t (&raw)[NPL][8][4]) {
+        u32x4 bt[NT16][NBT];
+        loadBt(j0, bt);
+        // 8 x 8 transpose of each plane: instance q gets row r + q
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            u32x4 tq[NPL];
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t lo = raw[pl][2 * e][q / 2];
+                    const uint32_t hi = raw[pl][2 * e + 1][q / 2];
+                    tq[pl][e] = (q & 1) ? ((lo >> 16) | (hi & 0xffff0000u))
+                                        : ((lo & 0xffffu) | (hi << 16));
+                }
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+#pragma unroll
+                for (int c = 0; c < NBT; ++c) acc[q][t] = mfma32<FMT>(bt[t][c], tq[0], acc[q][t]);
+                if (SPLIT) {
+                    acc[q][t] = mfma32<FMT>(bt[t][0], tq[NPL - 1], acc[q][t]);
+                    acc[q][t] = mfma32<FMT>(bt[t][1], tq[NPL - 1], acc[q][t]);
+                }
+            }
+        }
+    };
+
     // No register prefetch of the next chunk: its 32-64 VGPRs cost a
-    // wavefront of occupancy, and the resident wavefronts hide the latency
-    // better (measured: split form at n = 32 4.3 -> 6.0 TB/s without it; with
-    // B's terms pre-split, the prefetch still lost 2-14 % on every instance).
-    if (wk1 > wk0) {
+    // wavefront of occupancy, and the resident wavefronts hide the latency as
+    // well (measured: split form at n = 32 4.3 -> 6.0 TB/s without it; with B
+    // pre-split 2-14 % slower with it; with the row split within 1 %).
+    if (wk1 > wk0 && row0 < m) {
         const int ng = (int)((wk1 - wk0 + 31) / 32);
         for (int g = 0; g < ng; ++g) {
             uint32_t raw[NPL][8][4];
-            u32x4 bt[NT16][NBT];
             loadA(wk0 + 32 * g, raw);
-            loadBt(wk0 + 32 * g, bt);
-            // 8 x 8 transpose of each plane: instance q gets row r + q
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                u32x4 tq[NPL];
-#pragma unroll
-                for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const uint32_t lo = raw[pl][2 * e][q / 2];
-                        const uint32_t hi = raw[pl][2 * e + 1][q / 2];
-                        tq[pl][e] = (q & 1) ? ((lo >> 16) | (hi & 0xffff0000u))
-                                            : ((lo & 0xffffu) | (hi << 16));
-                    }
-#pragma unroll
-                for (int t = 0; t < NT16; ++t) {
-#pragma unroll
-                    for (int c = 0; c < NBT; ++c) acc[q][t] = mfma32<FMT>(bt[t][c], tq[0], acc[q][t]);
-                    if (SPLIT) {
-                        acc[q][t] = mfma32<FMT>(bt[t][0], tq[NPL - 1], acc[q][t]);
-                        acc[q][t] = mfma32<FMT>(bt[t][1], tq[NPL - 1], acc[q][t]);
-                    }
-                }
-            }
+            chunk(wk0 + 32 * g, raw);
         }
     }
 
     // lane holds C[r + q, 16 t + 4 kk + rr] in acc[q][t][rr]
-    nn_finish<float, NP, WK, TR, PG>(m, n, C, ldc, beta, tile, s, nsl, part,
-                                     reinterpret_cast<double*>(smem), [&](int pg, double* red) {
-        const int t = pg / 16;
+    nn_finish<float, NP, WK, TRW, PG, RS ? 1 : WK>(
+        m, n, C, ldc, beta, tile, s, nsl, part, reinterpret_cast<double*>(smem),
+        [&](int pg, double* red) {
+            const int t = pg / 16;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int pp = 16 * t + Mfma<float>::mrow(kk, rr) - pg;
-            if (pp >= 0 && pp < PG) {
+            for (int rr = 0; rr < 4; ++rr) {
+                const int pp = 16 * t + Mfma<float>::mrow(kk, rr) - pg;
+                if (pp >= 0 && pp < PG) {
+                    double* dst = RS ? red + pp * TRW + w * TR : red + (w * PG + pp) * TR;
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    red[(w * PG + pp) * TR + 8 * rl + q] = (double)acc[q][t][rr];
+                    for (int q = 0; q < 8; ++q) dst[8 * rl + q] = (double)acc[q][t][rr];
+                }
             }
-        }
-    });
+        });
 }
 
 // Value of row q (0..7) of a lane's 16-byte run of each plane: hi, or hi + lo.
@@ -626,21 +639,23 @@ static int lp_occupancy(K kernel) {
     return nb;
 }
 
-template <int FMT, int NT16, bool SPLIT, bool VEC>
+template <int FMT, int NT16, bool SPLIT, bool VEC, bool RS>
 static const void* lp_fn(int* occ) {
-    static const int o = lp_occupancy(tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC>);
+    static const int o = lp_occupancy(tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS>);
     *occ = o;
-    return (const void*)tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC>;
+    return (const void*)tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS>;
 }
 
-template <bool VEC>
+template <int FMT, bool VEC, bool RS>
+static const void* lp_pick_f(bool split, int nt16, int* occ) {
+    if (split) return nt16 == 1 ? lp_fn<FMT, 1, true, VEC, RS>(occ) : lp_fn<FMT, 2, true, VEC, RS>(occ);
+    return nt16 == 1 ? lp_fn<FMT, 1, false, VEC, RS>(occ) : lp_fn<FMT, 2, false, VEC, RS>(occ);
+}
+
+template <bool VEC, bool RS>
 static const void* lp_pick(int fmt, bool split, int nt16, int* occ) {
-    if (fmt == FMT_BF16) {
-        if (split) return nt16 == 1 ? lp_fn<FMT_BF16, 1, true, VEC>(occ) : lp_fn<FMT_BF16, 2, true, VEC>(occ);
-        return nt16 == 1 ? lp_fn<FMT_BF16, 1, false, VEC>(occ) : lp_fn<FMT_BF16, 2, false, VEC>(occ);
-    }
-    if (split) return nt16 == 1 ? lp_fn<FMT_F16, 1, true, VEC>(occ) : lp_fn<FMT_F16, 2, true, VEC>(occ);
-    return nt16 == 1 ? lp_fn<FMT_F16, 1, false, VEC>(occ) : lp_fn<FMT_F16, 2, false, VEC>(occ);
+    return fmt == FMT_BF16 ? lp_pick_f<FMT_BF16, VEC, RS>(split, nt16, occ)
+                           : lp_pick_f<FMT_F16, VEC, RS>(split, nt16, occ);
 }
 
 static inline int64_t cdiv_lp(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -649,10 +664,16 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
     const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
     const int nt16 = n <= 16 ? 1 : 2;
+    // the workgroup's wavefronts on adjacent row tiles (see tsm2r_lp_kernel);
+    // TSM2X_LP_RS=0 selects the k split among them (measurement only)
+    const char* frs = std::getenv("TSM2X_LP_RS");
+    const bool rs = !(frs && *frs) || std::strtol(frs, nullptr, 10) != 0;
     int occ = 1;
-    P->fn = vec ? lp_pick<true>(fmt, split, nt16, &occ) : lp_pick<false>(fmt, split, nt16, &occ);
-    const int WK = 4, TR = 128;
-    const int es = split ? 4 : 2;
+    P->fn = vec ? (rs ? lp_pick<true, true>(fmt, split, nt16, &occ)
+                      : lp_pick<true, false>(fmt, split, nt16, &occ))
+                : (rs ? lp_pick<false, true>(fmt, split, nt16, &occ)
+                      : lp_pick<false, false>(fmt, split, nt16, &occ));
+    const int WK = 4, TR = rs ? WK * 128 : 128;
     P->np = 16 * nt16;
     P->tile_rows = TR;
     P->tiles = cdiv_lp(m, TR);
@@ -661,14 +682,17 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     int64_t tgt = (int64_t)cus * 15 / 8;
     if (tgt > slots) tgt = slots;
     int64_t S = (tgt + P->tiles / 2) / P->tiles;
-    const int64_t s_len = k / (WK * 64);
-    const int64_t s_cost = (k * es) / ((int64_t)P->np * 200);
+    const int64_t s_len = k / (rs ? 64 : WK * 64);
+    // the float kernel's cap on the partials' traffic, for both forms (the
+    // single form, half the bytes of A, measured 11 % faster at A 16384^2,
+    // n = 8 with the 15 slices it allows than with 10)
+    const int64_t s_cost = (k * 4) / ((int64_t)P->np * 200);
     if (S > s_len) S = s_len;
     if (S > s_cost) S = s_cost;
     if (S < 1) S = 1;
     const char* fs = std::getenv("TSM2X_LP_S");
     if (fs && *fs && std::strtoll(fs, nullptr, 10) > 0) S = std::strtoll(fs, nullptr, 10);
-    const int64_t gran = (int64_t)WK * 32;
+    const int64_t gran = rs ? 32 : (int64_t)WK * 32;
     int64_t ks = cdiv_lp(k, S);
     ks = cdiv_lp(ks, gran) * gran;
     P->kslice = ks;
@@ -695,8 +719,8 @@ int launch_tsm2r_lp(const LaunchNN& L, int dtype, hipStream_t st) {
     }
     if (e != hipSuccess) return 1;
     if (L.S > 1)
-        return launch_split_reduce(DT_F32, L.tiles, L.S, L.np, 128, L.m, (int)L.n, L.part, L.C,
-                                   L.ldc, L.beta, st);
+        return launch_split_reduce(DT_F32, L.tiles, L.S, L.np, L.tile_rows, L.m, (int)L.n, L.part,
+                                   L.C, L.ldc, L.beta, st);
     return 0;
 }
 

@@ -143,6 +143,22 @@ def test_split_argument_checks():
     assert L.tsm2x_split(0, 4, NULL, 1, NULL, NULL, 1, 0, NULL) == 0
 
 
+def test_plane_leading_dimension():
+    # 16-byte columns; 128 bytes more for wide matrices whose column stride
+    # would be a multiple of 1 KiB; tall TSM2L-class planes are not padded
+    assert tsm.plane_ld(16384, 16384) == 16384 + 64
+    assert tsm.plane_ld(32768, 100) == 32768 + 64
+    assert tsm.plane_ld(1 << 23, 16) == 1 << 23
+    assert tsm.plane_ld(1 << 23, 32) == 1 << 23
+    assert tsm.plane_ld(1000, 4096) == 1000
+    assert tsm.plane_ld(1001, 4096) == 1008
+    assert tsm.plane_ld(1, 64) == 8
+    for m in (1, 7, 511, 512, 513, 30720, 32768):
+        for k in (8, 33, 1024):
+            ld = tsm.plane_ld(m, k)
+            assert ld >= m and ld % 8 == 0 and ld - m < 8 + 64
+
+
 def test_workspace_size_is_zero_without_split():
     L = _lib.lib()
     # no reduction split for tiny problems; an op outside the table needs none

@@ -191,8 +191,9 @@ __global__ __launch_bounds__(256) void split_b_kernel(int64_t k, int n, const fl
 // adjacent 128-row tiles over the whole k slice, so that a workgroup reads
 // WK x 256 contiguous bytes of every column it visits (longer runs per column
 // at a time read faster: measured 6.47 -> 6.84 TB/s for the bare pattern),
-// and each wavefront's sums are final for its rows.
-template <int FMT, int NT16, bool SPLIT, int WK, bool VEC, bool RS>
+// and each wavefront's sums are final for its rows.  PF (with RS): the next
+// chunk's loads in flight while this one is multiplied.
+template <int FMT, int NT16, bool SPLIT, int WK, bool VEC, bool RS, bool PF>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, const u32x4* __restrict__ Bt,
@@ -227,7 +228,27 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
         for (int t = 0; t < NT16; ++t) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // raw[pl][i][d]: plane pl, column j0 + 8 kk + i, rows r + 2d, r + 2d + 1
+    // a whole chunk of a full tile (wavefront-uniform): 16-byte loads
+    // without per-lane bounds
+    auto loadA_full = [&](int64_t j0, uint32_t (&raw)[NPL][8][4]) {
+        const int64_t off = r + (j0 + 8 * kk) * lda;
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+            const uint16_t* p = (pl == 0 ? Ah : Al) + off;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+#pragma unroll
+                for (int d = 0; d < 4; ++d) raw[pl][i][d] = v[d];
+                p += lda;
+            }
+        }
+    };
     auto loadA = [&](int64_t j0, uint32_t (&raw)[NPL][8][4]) {
+        if (VEC && full && j0 + 32 <= wk1) {
+            loadA_full(j0, raw);
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int64_t j = j0 + 8 * kk + i;
@@ -253,9 +274,7 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     };
 
     // the products of the chunk at j0 whose A is in raw
-    auto chunk = [&](int64_t j0, const uint32_t (&raw)[NPL][8][4]) {
-        u32x4 bt[NT16][NBT];
-        loadBt(j0, bt);
+    auto chunk = [&](const uint32_t (&raw)[NPL][8][4], const u32x4 (&bt)[NT16][NBT]) {
         // 8 x 8 transpose of each plane: instance q gets row r + q
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -281,16 +300,55 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
         }
     };
 
-    // No register prefetch of the next chunk: its 32-64 VGPRs cost a
-    // wavefront of occupancy, and the resident wavefronts hide the latency as
-    // well (measured: split form at n = 32 4.3 -> 6.0 TB/s without it; with B
-    // pre-split 2-14 % slower with it; with the row split within 1 %).
+    // PF: a register prefetch of the next chunk, held in flight across the
+    // waits for this one.  It doubles the loads a wavefront has outstanding
+    // (32 KB per wavefront for the split form) at the cost of occupancy (one
+    // wavefront per SIMD for the split form), and with one workgroup per CU
+    // it measured 6-10 % faster than the row split alone at A 32768^2 and
+    // 16384^2.  Without the scheduling barriers the compiler sank the next
+    // chunk's loads below the waits and it gained nothing.
     if (wk1 > wk0 && row0 < m) {
         const int ng = (int)((wk1 - wk0 + 31) / 32);
-        for (int g = 0; g < ng; ++g) {
-            uint32_t raw[NPL][8][4];
-            loadA(wk0 + 32 * g, raw);
-            chunk(wk0 + 32 * g, raw);
+        if (!PF || !(VEC && full && (wk1 - wk0) % 32 == 0)) {
+            for (int g = 0; g < ng; ++g) {
+                uint32_t raw[NPL][8][4];
+                u32x4 bt[NT16][NBT];
+                loadA(wk0 + 32 * g, raw);
+                loadBt(wk0 + 32 * g, bt);
+                chunk(raw, bt);
+            }
+        } else {
+            // every chunk whole: the next chunk in flight while this one is
+            // multiplied, in straight-line code (no bounds branches, so the
+            // waits for this chunk's operands leave the next chunk's loads
+            // outstanding); its B terms are loaded before its A for the same
+            // reason
+            uint32_t ra[NPL][8][4], rb[NPL][8][4];
+            u32x4 ba[NT16][NBT], bb[NT16][NBT];
+            loadBt(wk0, ba);
+            loadA_full(wk0, ra);
+            int g = 0;
+            // (the scheduling barriers keep the next chunk's loads ahead of
+            // the waits for this one: two chunks in flight per wavefront)
+            for (; g + 2 < ng; g += 2) {
+                loadBt(wk0 + 32 * (g + 1), bb);
+                loadA_full(wk0 + 32 * (g + 1), rb);
+                __builtin_amdgcn_sched_barrier(0);
+                chunk(ra, ba);
+                loadBt(wk0 + 32 * (g + 2), ba);
+                loadA_full(wk0 + 32 * (g + 2), ra);
+                __builtin_amdgcn_sched_barrier(0);
+                chunk(rb, bb);
+            }
+            if (g + 1 < ng) {
+                loadBt(wk0 + 32 * (g + 1), bb);
+                loadA_full(wk0 + 32 * (g + 1), rb);
+                __builtin_amdgcn_sched_barrier(0);
+                chunk(ra, ba);
+                chunk(rb, bb);
+            } else {
+                chunk(ra, ba);
+            }
         }
     }
 
@@ -639,23 +697,31 @@ static int lp_occupancy(K kernel) {
     return nb;
 }
 
-template <int FMT, int NT16, bool SPLIT, bool VEC, bool RS>
+template <int FMT, int NT16, bool SPLIT, bool VEC, bool RS, bool PF>
 static const void* lp_fn(int* occ) {
-    static const int o = lp_occupancy(tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS>);
+    static const int o = lp_occupancy(tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS, PF>);
     *occ = o;
-    return (const void*)tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS>;
+    return (const void*)tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS, PF>;
 }
 
-template <int FMT, bool VEC, bool RS>
+template <int FMT, bool VEC, bool RS, bool PF>
 static const void* lp_pick_f(bool split, int nt16, int* occ) {
-    if (split) return nt16 == 1 ? lp_fn<FMT, 1, true, VEC, RS>(occ) : lp_fn<FMT, 2, true, VEC, RS>(occ);
-    return nt16 == 1 ? lp_fn<FMT, 1, false, VEC, RS>(occ) : lp_fn<FMT, 2, false, VEC, RS>(occ);
+    if (split)
+        return nt16 == 1 ? lp_fn<FMT, 1, true, VEC, RS, PF>(occ) : lp_fn<FMT, 2, true, VEC, RS, PF>(occ);
+    return nt16 == 1 ? lp_fn<FMT, 1, false, VEC, RS, PF>(occ) : lp_fn<FMT, 2, false, VEC, RS, PF>(occ);
 }
 
-template <bool VEC, bool RS>
-static const void* lp_pick(int fmt, bool split, int nt16, int* occ) {
-    return fmt == FMT_BF16 ? lp_pick_f<FMT_BF16, VEC, RS>(split, nt16, occ)
-                           : lp_pick_f<FMT_F16, VEC, RS>(split, nt16, occ);
+// variant 0: wavefronts split k; 1: row split; 2: row split with prefetch
+template <bool VEC>
+static const void* lp_pick(int fmt, bool split, int nt16, int var, int* occ) {
+    if (fmt == FMT_BF16) {
+        if (var == 0) return lp_pick_f<FMT_BF16, VEC, false, false>(split, nt16, occ);
+        if (var == 1) return lp_pick_f<FMT_BF16, VEC, true, false>(split, nt16, occ);
+        return lp_pick_f<FMT_BF16, VEC, true, true>(split, nt16, occ);
+    }
+    if (var == 0) return lp_pick_f<FMT_F16, VEC, false, false>(split, nt16, occ);
+    if (var == 1) return lp_pick_f<FMT_F16, VEC, true, false>(split, nt16, occ);
+    return lp_pick_f<FMT_F16, VEC, true, true>(split, nt16, occ);
 }
 
 static inline int64_t cdiv_lp(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -664,24 +730,33 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     const int fmt = (dtype == DT_BF16 || dtype == DT_BF16_SPLIT) ? FMT_BF16 : FMT_F16;
     const bool split = dtype == DT_BF16_SPLIT || dtype == DT_F16_SPLIT;
     const int nt16 = n <= 16 ? 1 : 2;
-    // the workgroup's wavefronts on adjacent row tiles (see tsm2r_lp_kernel);
-    // TSM2X_LP_RS=0 selects the k split among them (measurement only)
+    // the workgroup's wavefronts on adjacent row tiles, each with its next
+    // chunk in flight (see tsm2r_lp_kernel); TSM2X_LP_RS=0 selects the k
+    // split among them, 1 the row split without the prefetch (measurement
+    // only)
     const char* frs = std::getenv("TSM2X_LP_RS");
-    const bool rs = !(frs && *frs) || std::strtol(frs, nullptr, 10) != 0;
+    int var = (frs && *frs) ? (int)std::strtol(frs, nullptr, 10) : 2;
+    if (var < 0 || var > 2) var = 2;
+    const bool rs = var != 0;
     int occ = 1;
-    P->fn = vec ? (rs ? lp_pick<true, true>(fmt, split, nt16, &occ)
-                      : lp_pick<true, false>(fmt, split, nt16, &occ))
-                : (rs ? lp_pick<false, true>(fmt, split, nt16, &occ)
-                      : lp_pick<false, false>(fmt, split, nt16, &occ));
+    P->fn = vec ? lp_pick<true>(fmt, split, nt16, var, &occ) : lp_pick<false>(fmt, split, nt16, var, &occ);
     const int WK = 4, TR = rs ? WK * 128 : 128;
     P->np = 16 * nt16;
     P->tile_rows = TR;
     P->tiles = cdiv_lp(m, TR);
-    // as for the float kernel: aim at about 15/8 resident workgroups per CU
+    // with the prefetch: one workgroup per CU, never more (A 32768^2 and
+    // 16384^2, n = 8..32: 256 workgroups beat 192 by 6-12 % and 288-320 by
+    // 20-30 %, as the CUs holding a second workgroup finish last); without
+    // it, as for the float kernel, about 15/8 resident workgroups per CU
     const int64_t slots = (int64_t)cus * occ;
-    int64_t tgt = (int64_t)cus * 15 / 8;
-    if (tgt > slots) tgt = slots;
-    int64_t S = (tgt + P->tiles / 2) / P->tiles;
+    int64_t S;
+    if (var == 2) {
+        S = cus / P->tiles;
+    } else {
+        int64_t tgt = (int64_t)cus * 15 / 8;
+        if (tgt > slots) tgt = slots;
+        S = (tgt + P->tiles / 2) / P->tiles;
+    }
     const int64_t s_len = k / (rs ? 64 : WK * 64);
     // the float kernel's cap on the partials' traffic, for both forms (the
     // single form, half the bytes of A, measured 11 % faster at A 16384^2,

@@ -158,6 +158,7 @@ struct TNPlan {
     int64_t rslice;
     int rg;
     int ct;                 // output tiles per workgroup
+    int pf;                 // 16-bit forms: the next step's X held in flight
     size_t ws;
 };
 
@@ -191,6 +192,14 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     P.S = (int)cdiv(R, rs);
     if (P.S < 1) P.S = 1;
     P.ws = P.S > 1 ? (size_t)P.groups * P.S * 256 * NT16 * 8 : 0;
+    // the 16-bit kernel's prefetch of the next step: always for the single
+    // form (A 16384^2 and 32768^2, n = 8 and 16: 3.8-4.2 -> 4.8-5.7 TB/s);
+    // for the split form, whose steps move twice the bytes, only when the
+    // grid holds more than two workgroups per CU (at A 16384^2, n = 8, one
+    // round of 512 workgroups: 5.80 TB/s without, 5.21 with; at 32768^2,
+    // four rounds: 6.34 -> 6.51 (n = 8), 5.89 -> 6.17 (n = 16))
+    const bool split = dt == DT_BF16_SPLIT || dt == DT_F16_SPLIT;
+    P.pf = (int)env_int("TSM2X_TN_PF", (!split || (P.groups / P.ct) * P.S > 2 * (int64_t)cus) ? 1 : 0);
     return P;
 }
 
@@ -387,6 +396,7 @@ int product(bool lform, int transA, int transB, int64_t m, int64_t k, int64_t n,
         L.R = k; L.ncols = m; L.n = n;
         L.X = A; L.ldx = lda; L.Y = Bk; L.ldy = ldbk; L.O = C; L.ldo = ldc;
         L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg; L.ct = P.ct;
+        L.pf = P.pf;
         L.beta = beta;
         if (P.S > 1) L.part = (double*)w;
         if (launch_tn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
@@ -511,6 +521,7 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     LaunchTN L{};
     L.R = m; L.ncols = k; L.n = n; L.X = A; L.ldx = lda; L.Y = dC; L.ldy = lddc; L.O = dB;
     L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg; L.ct = P.ct;
+    L.pf = P.pf;
     if (P.S > 1) L.part = (double*)w;
     if (!plain_dtype(dtype)) {
         if (launch_tn_lp(L, dtype, st)) return TSM_ERR_UNSUPPORTED;

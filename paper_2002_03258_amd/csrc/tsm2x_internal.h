@@ -95,6 +95,7 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
     int64_t rslice;
     int rg;                 // stages per wavefront loop iteration (1, 2 or 4)
     int ct;                 // 16-column output tiles per workgroup (1 or 2)
+    int pf;                 // 16-bit forms: the next step's X held in flight (0/1)
     double* part;           // S > 1: partial sums (workspace)
     double beta;            // O := beta*O + X^T*Y (O read only if beta != 0)
 };

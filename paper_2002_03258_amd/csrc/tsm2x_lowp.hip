@@ -517,10 +517,10 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // tn_kernel.
 // --------------------------------------------------------------------------
 template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC, bool YD>
-__global__ __launch_bounds__(256) void tn_lp_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
-    float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part) {
+    float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part, int pf) {
     typedef Mfma<float> M;
     constexpr int WK = 4;
     constexpr int SR = 128;                    // rows per step
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
-    const int w = threadIdx.x / WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
     const int64_t c0 = (int64_t)blockIdx.x * NX;
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t sb0 = (int64_t)s * rslice;
@@ -600,7 +600,117 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
         }
     };
 
-    if (wb1 > wb0) {
+    // stage X (and staged Y) of a step and multiply
+    auto step = [&](const uint32_t (&xv)[XG][NPL][4], const float (&yv)[YW][4]) {
+        // stage: X column 4 cg + kk rows 8 rl .. 8 rl + 7 (widened),
+        //        Y column NX + 4 cg + kk rows 64 h + 4 rl .. 64 h + 4 rl + 3
+        wave_lds_fence();
+#pragma unroll
+        for (int cg = 0; cg < XG; ++cg) {
+            f32x4 x0, x1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                x0[q] = plane_val<FMT, NPL>(xv[cg], q);
+                x1[q] = plane_val<FMT, NPL>(xv[cg], 4 + q);
+            }
+            *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl]) = x0;
+            *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl + 4]) = x1;
+        }
+        if (!YD) {
+#pragma unroll
+            for (int yi = 0; yi < YW; ++yi) {
+                f32x4 y;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y[q] = yv[yi][q];
+                *reinterpret_cast<f32x4*>(&tile[NX + 4 * (yi % YG) + kk][64 * (yi / YG) + 4 * rl]) = y;
+            }
+        }
+        // read back 16-row blocks: rows 16 hb + 4 kk + q; each Y block
+        // serves the CT output tiles
+        wave_lds_fence();
+#pragma unroll
+        for (int hb = 0; hb < NB; ++hb) {
+            f32x4 ys[NT16];
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                if (YD) {
+                    const bool live = 16 * t + rl < n;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) ys[t][q] = live ? yv[hb * NT16 + t][q] : 0.f;
+                } else {
+                    ys[t] = *reinterpret_cast<const f32x4*>(&tile[NX + 16 * t + rl][16 * hb + 4 * kk]);
+                }
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const f32x4 xs = *reinterpret_cast<const f32x4*>(&tile[16 * ct + rl][16 * hb + 4 * kk]);
+#pragma unroll
+                for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[ct][t] = M::op(xs[q], ys[t][q], acc[ct][t]);
+            }
+        }
+    };
+
+    // pf and every step whole (rows and columns in range, 16-byte loads, Y
+    // direct): straight-line loads, the next step's X kept in flight across
+    // the waits for this step's operands (the scheduling barriers stop the
+    // compiler from sinking those loads below the waits).
+    const bool whole = pf && VEC && YC && YD && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
+    auto loadX_full = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4]) {
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+            const uint16_t* P = (pl == 0 ? Xh : Xl) + rb + 8 * rl + (c0 + kk) * ldx;
+#pragma unroll
+            for (int cg = 0; cg < XG; ++cg) {
+                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(P + 4 * cg * ldx));
+#pragma unroll
+                for (int d = 0; d < 4; ++d) xv[cg][pl][d] = v[d];
+            }
+        }
+    };
+    // columns p >= n load column n - 1 (in range); the step zeroes them
+    auto loadY_full = [&](int64_t rb, float (&yv)[YW][4]) {
+#pragma unroll
+        for (int yi = 0; yi < YW; ++yi) {
+            const int p = 16 * (yi % NT16) + rl;
+            const int pc = p < n ? p : n - 1;
+            const f32x4 y = *reinterpret_cast<const f32x4*>(Y + rb + 16 * (yi / NT16) + 4 * kk +
+                                                            (int64_t)pc * ldy);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yv[yi][q] = y[q];
+        }
+    };
+
+    if (wb1 > wb0 && whole) {
+        // two steps per iteration with no conditional loads inside (a load
+        // issued on one path only makes the waits after the join count it
+        // as absent, and they then wait for everything)
+        const int64_t nit = (wb1 - wb0) / SR;
+        uint32_t xa[XG][NPL][4], xb[XG][NPL][4];
+        float yv[YW][4];
+        loadX_full(wb0, xa);
+        int64_t it = 0;
+        for (; it + 2 < nit; it += 2) {
+            loadY_full(wb0 + it * SR, yv);
+            loadX_full(wb0 + (it + 1) * SR, xb);
+            __builtin_amdgcn_sched_barrier(0);
+            step(xa, yv);
+            loadY_full(wb0 + (it + 1) * SR, yv);
+            loadX_full(wb0 + (it + 2) * SR, xa);
+            __builtin_amdgcn_sched_barrier(0);
+            step(xb, yv);
+        }
+        loadY_full(wb0 + it * SR, yv);
+        if (it + 1 < nit) {
+            loadX_full(wb0 + (it + 1) * SR, xb);
+            step(xa, yv);
+            loadY_full(wb0 + (it + 1) * SR, yv);
+            step(xb, yv);
+        } else {
+            step(xa, yv);
+        }
+    } else if (wb1 > wb0) {
         const int64_t nit = (wb1 - wb0 + SR - 1) / SR;
         uint32_t xv[XG][NPL][4];
         float yv[YW][4];
@@ -614,53 +724,7 @@ __global__ __launch_bounds__(256) void tn_lp_kernel(
                 loadX(wb0 + (it + 1) * SR, xn);
                 if (!YD) loadY(wb0 + (it + 1) * SR, yn);
             }
-            // stage: X column 4 cg + kk rows 8 rl .. 8 rl + 7 (widened),
-            //        Y column NX + 4 cg + kk rows 64 h + 4 rl .. 64 h + 4 rl + 3
-            wave_lds_fence();
-#pragma unroll
-            for (int cg = 0; cg < XG; ++cg) {
-                f32x4 x0, x1;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    x0[q] = plane_val<FMT, NPL>(xv[cg], q);
-                    x1[q] = plane_val<FMT, NPL>(xv[cg], 4 + q);
-                }
-                *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl]) = x0;
-                *reinterpret_cast<f32x4*>(&tile[4 * cg + kk][8 * rl + 4]) = x1;
-            }
-            if (!YD) {
-#pragma unroll
-                for (int yi = 0; yi < YW; ++yi) {
-                    f32x4 y;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) y[q] = yv[yi][q];
-                    *reinterpret_cast<f32x4*>(&tile[NX + 4 * (yi % YG) + kk][64 * (yi / YG) + 4 * rl]) = y;
-                }
-            }
-            // read back 16-row blocks: rows 16 hb + 4 kk + q; each Y block
-            // serves the CT output tiles
-            wave_lds_fence();
-#pragma unroll
-            for (int hb = 0; hb < NB; ++hb) {
-                f32x4 ys[NT16];
-#pragma unroll
-                for (int t = 0; t < NT16; ++t) {
-                    if (YD) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) ys[t][q] = yv[hb * NT16 + t][q];
-                    } else {
-                        ys[t] = *reinterpret_cast<const f32x4*>(&tile[NX + 16 * t + rl][16 * hb + 4 * kk]);
-                    }
-                }
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
-                    const f32x4 xs = *reinterpret_cast<const f32x4*>(&tile[16 * ct + rl][16 * hb + 4 * kk]);
-#pragma unroll
-                    for (int t = 0; t < NT16; ++t)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) acc[ct][t] = M::op(xs[q], ys[t][q], acc[ct][t]);
-                }
-            }
+            step(xv, yv);
 #pragma unroll
             for (int cg = 0; cg < XG; ++cg)
 #pragma unroll
@@ -902,15 +966,15 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
         if (vec && yc)                                                                            \
             TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, true, YD>), g, b, 0, st, L.R, L.ncols,  \
                        ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,           \
-                       L.rslice, L.part);                                                         \
+                       L.rslice, L.part, pf);                                                     \
         else if (vec)                                                                             \
             TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, false, YD>), g, b, 0, st, L.R, L.ncols, \
                        ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,           \
-                       L.rslice, L.part);                                                         \
+                       L.rslice, L.part, pf);                                                     \
         else                                                                                      \
             TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, false, false, YD>), g, b, 0, st, L.R,         \
                        L.ncols, ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,  \
-                       L.rslice, L.part);                                                         \
+                       L.rslice, L.part, pf);                                                     \
         return 0;                                                                                 \
     }
     // Y straight from L2 when several column groups re-read it (measured,
@@ -919,6 +983,7 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
     // streams it from HBM once (2^23 x 16: 5.15 staged, 4.06 direct).  Two
     // output tiles per workgroup always take Y direct (staged, they need
     // 101 KB of LDS per workgroup).  TSM2X_TN_YD=0/1 overrides (measurement).
+    const int pf = L.pf;
     const char* yde = std::getenv("TSM2X_TN_YD");
     const bool yd = (yde && *yde) ? *yde == '1' : yc;
 #define TSM_T2(F, SP)                                                                     \

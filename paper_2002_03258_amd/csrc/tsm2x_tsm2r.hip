@@ -20,7 +20,9 @@ namespace tsm {
 // steps st = 0..ST-1 with columns j = j0 + ST*kk + st; a lane's ST B values
 // of a chunk, B[j0+ST*kk .. j0+ST*kk+ST-1, 16t+rl], are contiguous in B's
 // column.  The next chunk's A and B are loaded while the current one is
-// multiplied (the prefetching of Algorithm 4).  Lane l ends up with
+// multiplied (the prefetching of Algorithm 4); where every chunk is whole
+// and the host asks for it (pf), in straight-line code that keeps those
+// loads outstanding across the waits for the current chunk.  Lane l ends up with
 // C[row0 + 16*RL*g + RL*rl + q, 16t + mrow(kk, r)] in acc[g][q][t][r].
 //
 // The k range is split across the WK wavefronts of a workgroup and across
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(WAVE * WK)
 __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kernel(
     int64_t m, int64_t k, int n, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
-    int64_t kslice, double* __restrict__ part, int bvec, double beta) {
+    int64_t kslice, double* __restrict__ part, int bvec, int pf, double beta) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -56,7 +58,7 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
-    const int w = threadIdx.x / WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
     const int64_t tile = blockIdx.x;
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t row0 = tile * TR;
@@ -114,7 +116,82 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
         }
     };
 
-    if (wk1 > wk0) {
+    auto mul = [&](const T (&av)[ST][RG][RL], const T (&bv)[NT16][ST]) {
+#pragma unroll
+        for (int st = 0; st < ST; ++st)
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int q = 0; q < RL; ++q)
+#pragma unroll
+                    for (int t = 0; t < NT16; ++t)
+                        acc[g][q][t] = M::op(bv[t][st], av[st][g][q], acc[g][q][t]);
+    };
+    // a whole chunk of a full tile: straight-line 16-byte loads; B columns
+    // p >= n read column n - 1 (in range) and are zeroed after the wait
+    auto loadA_full = [&](int64_t j0, T (&av)[ST][RG][RL]) {
+        const T* base = A + row0 + RL * rl + (j0 + ST * kk) * lda;
+#pragma unroll
+        for (int st = 0; st < ST; ++st)
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+                load_run<T, RL, true>(base + st * lda + 16 * RL * g, RL, true, av[st][g]);
+    };
+    auto loadB_full = [&](int64_t j0, T (&bv)[NT16][ST]) {
+        typedef typename VecOf<T, BW>::type V;
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) {
+            const int p = 16 * t + rl;
+            const T* __restrict__ src = B + j0 + ST * kk + (int64_t)(p < n ? p : n - 1) * ldb;
+#pragma unroll
+            for (int h = 0; h < ST / BW; ++h) {
+                const V v = *reinterpret_cast<const V*>(src + h * BW);
+#pragma unroll
+                for (int e = 0; e < BW; ++e) bv[t][h * BW + e] = v[e];
+            }
+        }
+    };
+    auto mul_live = [&](const T (&av)[ST][RG][RL], const T (&bv)[NT16][ST]) {
+        T bz[NT16][ST];
+#pragma unroll
+        for (int t = 0; t < NT16; ++t)
+#pragma unroll
+            for (int st = 0; st < ST; ++st) bz[t][st] = 16 * t + rl < n ? bv[t][st] : T(0);
+        mul(av, bz);
+    };
+
+    // Every chunk whole: the next chunk held in flight across the waits for
+    // this one (the scheduling barriers stop the compiler from sinking its
+    // loads below them; with the bounds branches of the general loop, the
+    // waits after each join counted nothing as in flight and drained every
+    // load).  Not for the tall tiles (RG = 4), whose two chunks do not fit
+    // the register budget.
+    if (PF && RG <= 2 && VEC && pf && full && bvec && wk1 > wk0 && (wk1 - wk0) % CW == 0) {
+        const int ng = (int)((wk1 - wk0) / CW);
+        T aa[ST][RG][RL], ab[ST][RG][RL], ba[NT16][ST], bb[NT16][ST];
+        loadB_full(wk0, ba);
+        loadA_full(wk0, aa);
+        int gc = 0;
+        for (; gc + 2 < ng; gc += 2) {
+            loadB_full(wk0 + CW * (gc + 1), bb);
+            loadA_full(wk0 + CW * (gc + 1), ab);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_live(aa, ba);
+            loadB_full(wk0 + CW * (gc + 2), ba);
+            loadA_full(wk0 + CW * (gc + 2), aa);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_live(ab, bb);
+        }
+        if (gc + 1 < ng) {
+            loadB_full(wk0 + CW * (gc + 1), bb);
+            loadA_full(wk0 + CW * (gc + 1), ab);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_live(aa, ba);
+            mul_live(ab, bb);
+        } else {
+            mul_live(aa, ba);
+        }
+    } else if (wk1 > wk0) {
         const int ng = (int)((wk1 - wk0 + CW - 1) / CW);
         T av[ST][RG][RL], bv[NT16][ST];
         if (PF) {
@@ -130,15 +207,7 @@ __attribute__((amdgpu_waves_per_eu(nn_waves<T, NT16>(), 8))) void tsm2r_nn_kerne
                 loadA(wk0 + CW * (gc + 1), an);
                 loadB(wk0 + CW * (gc + 1), bn);
             }
-#pragma unroll
-            for (int st = 0; st < ST; ++st)
-#pragma unroll
-                for (int g = 0; g < RG; ++g)
-#pragma unroll
-                    for (int q = 0; q < RL; ++q)
-#pragma unroll
-                        for (int t = 0; t < NT16; ++t)
-                            acc[g][q][t] = M::op(bv[t][st], av[st][g][q], acc[g][q][t]);
+            mul(av, bv);
             if (PF) {
 #pragma unroll
                 for (int st = 0; st < ST; ++st)
@@ -301,11 +370,19 @@ int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
     // 16-byte loads of B's column runs need an aligned B with ldb*size % 16 == 0
     const int es = dtype == DT_F64 ? 8 : 4;
     int bvec = aligned16(L.B) && ((L.ldb * es) % 16 == 0);
+    // the next chunk held in flight (see tsm2r_nn_kernel) where it measured
+    // faster (A 16384^2 to 32768^2): n > 16, where the matrix cores' share
+    // of a chunk is largest, +15-25 % (FP32 at 32768^2, n = 32: 5.1 -> 6.0
+    // TB/s), and FP32 with n <= 4, +2-9 %; elsewhere within -5..+1 %.
+    // TSM2X_NN_PF=0/1 overrides (measurement).
+    const char* pfe = std::getenv("TSM2X_NN_PF");
+    int pf = (pfe && *pfe) ? (int)std::strtol(pfe, nullptr, 10)
+                           : (L.n > 16 || (dtype == DT_F32 && L.n <= 4)) ? 1 : 0;
     double beta = L.beta;
     void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&n32,    (void*)&L.A,
                     (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,
                     (void*)&L.ldc, (void*)&L.kslice, (void*)&L.part, (void*)&bvec,
-                    (void*)&beta};
+                    (void*)&pf,    (void*)&beta};
     hipError_t e;
     {
         LaunchTimer timer(L.fn, st);

@@ -192,14 +192,18 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     P.S = (int)cdiv(R, rs);
     if (P.S < 1) P.S = 1;
     P.ws = P.S > 1 ? (size_t)P.groups * P.S * 256 * NT16 * 8 : 0;
-    // the 16-bit kernel's prefetch of the next step: always for the single
-    // form (A 16384^2 and 32768^2, n = 8 and 16: 3.8-4.2 -> 4.8-5.7 TB/s);
-    // for the split form, whose steps move twice the bytes, only when the
-    // grid holds more than two workgroups per CU (at A 16384^2, n = 8, one
-    // round of 512 workgroups: 5.80 TB/s without, 5.21 with; at 32768^2,
-    // four rounds: 6.34 -> 6.51 (n = 8), 5.89 -> 6.17 (n = 16))
+    // The next step held in flight (tn_kernel, tn_lp_kernel), where it
+    // measured faster.  Float forms: for n > 16, +48-66 % (A 16384^2 to
+    // 32768^2: 3.0-3.3 -> 4.5-5.3 TB/s); for n <= 16 from -18 % to +6 %, so
+    // not there.  16-bit single form: always (n = 8 and 16: 3.8-4.2 -> 4.8-5.7
+    // TB/s).  16-bit split form, whose steps move twice the bytes: only when
+    // the grid holds more than two workgroups per CU (at A 16384^2, n = 8,
+    // one round of 512 workgroups: 5.80 TB/s without, 5.21 with; at 32768^2,
+    // four rounds: 6.34 -> 6.51 (n = 8), 5.89 -> 6.17 (n = 16)).
     const bool split = dt == DT_BF16_SPLIT || dt == DT_F16_SPLIT;
-    P.pf = (int)env_int("TSM2X_TN_PF", (!split || (P.groups / P.ct) * P.S > 2 * (int64_t)cus) ? 1 : 0);
+    const bool pf = plain_dtype(dt) ? n > 16
+                                    : !split || (P.groups / P.ct) * P.S > 2 * (int64_t)cus;
+    P.pf = (int)env_int("TSM2X_TN_PF", pf ? 1 : 0);
     return P;
 }
 

@@ -175,7 +175,7 @@ template <typename T, int NT16, int G, int CT, bool VEC, bool YC>
 __global__ __launch_bounds__(256) void tn_kernel(
     int64_t R, int64_t ncols, int n, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ O, int64_t ldo,
-    int64_t rslice, double* __restrict__ part, double beta) {
+    int64_t rslice, double* __restrict__ part, double beta, int pf) {
     typedef Mfma<T> M;
     typedef typename M::acc Acc;
     constexpr int RL = 16 / (int)sizeof(T);
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void tn_kernel(
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
-    const int w = threadIdx.x / WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
     const int64_t c0 = (int64_t)blockIdx.x * NX;
     const int s = blockIdx.y, nsl = gridDim.y;
     const int64_t sb0 = (int64_t)s * rslice;
@@ -240,46 +240,99 @@ __global__ __launch_bounds__(256) void tn_kernel(
         }
     };
 
-    if (wb1 > wb0) {
+    // stage the G stages of v and multiply; live: staged Y columns at or
+    // beyond n are zeroed (the whole-step loads read column n - 1 there)
+    auto stage_mul = [&](const T (&v)[G][NC / 4][RL], bool zero_dead) {
+#pragma unroll
+        for (int gs = 0; gs < G; ++gs) {
+            // stage: column 4 cg + kk, rows RL*rl .. RL*rl + RL - 1
+            wave_lds_fence();
+#pragma unroll
+            for (int cg = 0; cg < NC / 4; ++cg) {
+                typedef typename VecOf<T, RL>::type V;
+                const bool dead = zero_dead && cg >= NX / 4 && 4 * cg + kk - NX >= n;
+                V x;
+#pragma unroll
+                for (int q = 0; q < RL; ++q) x[q] = dead ? T(0) : v[gs][cg][q];
+                *reinterpret_cast<V*>(&tile[4 * cg + kk][RL * rl]) = x;
+            }
+            // read back in four blocks of 4*RL rows: X columns 16 ct + rl
+            // and Y columns NX + 16 t + rl, rows 4*RL*h + RL*kk + q
+            wave_lds_fence();
+            typedef typename VecOf<T, RL>::type V;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                V ys[NT16];
+#pragma unroll
+                for (int t = 0; t < NT16; ++t)
+                    ys[t] = *reinterpret_cast<const V*>(&tile[NX + 16 * t + rl][4 * RL * h + RL * kk]);
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    const V xs = *reinterpret_cast<const V*>(&tile[16 * ct + rl][4 * RL * h + RL * kk]);
+#pragma unroll
+                    for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                        for (int q = 0; q < RL; ++q)
+                            acc[ct][t] = M::op(xs[q], ys[t][q], acc[ct][t]);
+                }
+            }
+        }
+    };
+    // whole steps: straight-line 16-byte loads (Y through the cache)
+    auto load_full = [&](int64_t rb, T (&v)[G][NC / 4][RL]) {
+        typedef typename VecOf<T, RL>::type V;
+#pragma unroll
+        for (int gs = 0; gs < G; ++gs) {
+            const int64_t r = rb + gs * SR + RL * rl;
+#pragma unroll
+            for (int cg = 0; cg < NC / 4; ++cg) {
+                const int sc = 4 * cg + kk;
+                if (cg < NX / 4) {
+                    load_run<T, RL, true>(X + r + (c0 + sc) * ldx, RL, true, v[gs][cg]);
+                } else {
+                    const int p = sc - NX < n ? sc - NX : n - 1;
+                    const V y = *reinterpret_cast<const V*>(Y + r + (int64_t)p * ldy);
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) v[gs][cg][q] = y[q];
+                }
+            }
+        }
+    };
+
+    // pf and every step whole: the next step held in flight across the waits
+    // for this one (the scheduling barriers keep its loads ahead of them;
+    // the bounds branches of the general loop made those waits drain every
+    // load).  Not with four stages per step, whose two steps do not fit the
+    // registers.
+    if (G <= 2 && pf && VEC && YC && wb1 > wb0 && c0 + NX <= ncols && (wb1 - wb0) % (G * SR) == 0) {
+        const int64_t nit = (wb1 - wb0) / (G * SR);
+        T va[G][NC / 4][RL], vb[G][NC / 4][RL];
+        load_full(wb0, va);
+        int64_t it = 0;
+        for (; it + 2 < nit; it += 2) {
+            load_full(wb0 + (it + 1) * G * SR, vb);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mul(va, true);
+            load_full(wb0 + (it + 2) * G * SR, va);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mul(vb, true);
+        }
+        if (it + 1 < nit) {
+            load_full(wb0 + (it + 1) * G * SR, vb);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mul(va, true);
+            stage_mul(vb, true);
+        } else {
+            stage_mul(va, true);
+        }
+    } else if (wb1 > wb0) {
         const int64_t nit = (wb1 - wb0 + G * SR - 1) / (G * SR);
         T v[G][NC / 4][RL];
         load(wb0, v);
         for (int64_t it = 0; it < nit; ++it) {
             T vn[G][NC / 4][RL];
             if (it + 1 < nit) load(wb0 + (it + 1) * G * SR, vn);
-#pragma unroll
-            for (int gs = 0; gs < G; ++gs) {
-                // stage: column 4 cg + kk, rows RL*rl .. RL*rl + RL - 1
-                wave_lds_fence();
-#pragma unroll
-                for (int cg = 0; cg < NC / 4; ++cg) {
-                    typedef typename VecOf<T, RL>::type V;
-                    V x;
-#pragma unroll
-                    for (int q = 0; q < RL; ++q) x[q] = v[gs][cg][q];
-                    *reinterpret_cast<V*>(&tile[4 * cg + kk][RL * rl]) = x;
-                }
-                // read back in four blocks of 4*RL rows: X columns 16 ct + rl
-                // and Y columns NX + 16 t + rl, rows 4*RL*h + RL*kk + q
-                wave_lds_fence();
-                typedef typename VecOf<T, RL>::type V;
-#pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    V ys[NT16];
-#pragma unroll
-                    for (int t = 0; t < NT16; ++t)
-                        ys[t] = *reinterpret_cast<const V*>(&tile[NX + 16 * t + rl][4 * RL * h + RL * kk]);
-#pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) {
-                        const V xs = *reinterpret_cast<const V*>(&tile[16 * ct + rl][4 * RL * h + RL * kk]);
-#pragma unroll
-                        for (int t = 0; t < NT16; ++t)
-#pragma unroll
-                            for (int q = 0; q < RL; ++q)
-                                acc[ct][t] = M::op(xs[q], ys[t][q], acc[ct][t]);
-                    }
-                }
-            }
+            stage_mul(v, false);
 #pragma unroll
             for (int gs = 0; gs < G; ++gs)
 #pragma unroll
@@ -409,15 +462,15 @@ static int tn_launch(const LaunchTN& L, bool vec, hipStream_t st) {
     if (vec && gx > 1)
         TSM_LAUNCH((tn_kernel<T, NT16, G, CT, true, true>), grid, block, 0, st, L.R,
                            L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
-                           L.ldo, L.rslice, L.part, L.beta);
+                           L.ldo, L.rslice, L.part, L.beta, L.pf);
     else if (vec)
         TSM_LAUNCH((tn_kernel<T, NT16, G, CT, true, false>), grid, block, 0, st, L.R,
                            L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
-                           L.ldo, L.rslice, L.part, L.beta);
+                           L.ldo, L.rslice, L.part, L.beta, L.pf);
     else
         TSM_LAUNCH((tn_kernel<T, NT16, G, CT, false, false>), grid, block, 0, st, L.R,
                            L.ncols, (int)L.n, (const T*)L.X, L.ldx, (const T*)L.Y, L.ldy, (T*)L.O,
-                           L.ldo, L.rslice, L.part, L.beta);
+                           L.ldo, L.rslice, L.part, L.beta, L.pf);
     return 0;
 }
 

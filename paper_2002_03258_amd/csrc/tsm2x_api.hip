@@ -169,9 +169,11 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // output tiles per workgroup: two share each Y tile when there are
     // several column groups (Y is then re-read by every group).  The 16-bit
     // forms take Y straight from L2 then (staged in LDS too, two tiles needed
-    // one workgroup per CU); with n > 16 their registers allow one tile only
-    // (measured: n = 32, one tile 3.08 TB/s, two 2.95)
-    const int ct_dflt = plain_dtype(dt) ? 2 : (n <= 16 ? 2 : 1);
+    // one workgroup per CU).  With n > 16 two tiles fit one workgroup per CU
+    // only; with the next step in flight they still beat one tile (A 16384^2
+    // and 32768^2, n = 24, 32: split 3.4-4.2 -> 4.4-4.9 TB/s, single
+    // 2.0-2.6 -> 2.5-3.1; without the prefetch one tile was faster)
+    const int ct_dflt = 2;
     P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", ct_dflt) : 1;
     if (P.ct != 1 && P.ct != 2) P.ct = 1;
     // rows per wavefront loop iteration: G stages of 16*RL rows for the
@@ -196,13 +198,14 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // measured faster.  Float forms: for n > 16, +48-66 % (A 16384^2 to
     // 32768^2: 3.0-3.3 -> 4.5-5.3 TB/s); for n <= 16 from -18 % to +6 %, so
     // not there.  16-bit single form: always (n = 8 and 16: 3.8-4.2 -> 4.8-5.7
-    // TB/s).  16-bit split form, whose steps move twice the bytes: only when
-    // the grid holds more than two workgroups per CU (at A 16384^2, n = 8,
-    // one round of 512 workgroups: 5.80 TB/s without, 5.21 with; at 32768^2,
-    // four rounds: 6.34 -> 6.51 (n = 8), 5.89 -> 6.17 (n = 16)).
+    // TB/s) and for n > 16 (above).  16-bit split form with n <= 16, whose
+    // steps move twice the bytes: only when the grid holds more than two
+    // workgroups per CU (at A 16384^2, n = 8, one round of 512 workgroups:
+    // 5.80 TB/s without, 5.21 with; at 32768^2, four rounds: 6.34 -> 6.51
+    // (n = 8), 5.89 -> 6.17 (n = 16)).
     const bool split = dt == DT_BF16_SPLIT || dt == DT_F16_SPLIT;
     const bool pf = plain_dtype(dt) ? n > 16
-                                    : !split || (P.groups / P.ct) * P.S > 2 * (int64_t)cus;
+                                    : !split || n > 16 || (P.groups / P.ct) * P.S > 2 * (int64_t)cus;
     P.pf = (int)env_int("TSM2X_TN_PF", pf ? 1 : 0);
     return P;
 }

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void split_b_kernel(int64_t k, int n, const fl
 // at a time read faster: measured 6.47 -> 6.84 TB/s for the bare pattern),
 // and each wavefront's sums are final for its rows.  PF (with RS): the next
 // chunk's loads in flight while this one is multiplied.
-template <int FMT, int NT16, bool SPLIT, int WK, bool VEC, bool RS, bool PF>
+template <int FMT, int NT16, bool SPLIT, int WK, bool VEC, bool RS, bool PF, int U>
 __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     int64_t m, int64_t k, int n, const uint16_t* __restrict__ Ah,
     const uint16_t* __restrict__ Al, int64_t lda, const u32x4* __restrict__ Bt,
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
     // chunk's loads below the waits and it gained nothing.
     if (wk1 > wk0 && row0 < m) {
         const int ng = (int)((wk1 - wk0 + 31) / 32);
-        if (!PF || !(VEC && full && (wk1 - wk0) % 32 == 0)) {
+        if (!PF || !(VEC && full && (wk1 - wk0) % (32 * U) == 0)) {
             for (int g = 0; g < ng; ++g) {
                 uint32_t raw[NPL][8][4];
                 u32x4 bt[NT16][NBT];
@@ -318,36 +318,44 @@ __global__ __launch_bounds__(WAVE * WK) void tsm2r_lp_kernel(
                 chunk(raw, bt);
             }
         } else {
-            // every chunk whole: the next chunk in flight while this one is
+            // every chunk whole: the next step in flight while this one is
             // multiplied, in straight-line code (no bounds branches, so the
-            // waits for this chunk's operands leave the next chunk's loads
+            // waits for this step's operands leave the next step's loads
             // outstanding); its B terms are loaded before its A for the same
-            // reason
-            uint32_t ra[NPL][8][4], rb[NPL][8][4];
-            u32x4 ba[NT16][NBT], bb[NT16][NBT];
-            loadBt(wk0, ba);
-            loadA_full(wk0, ra);
+            // reason.  A step is U chunks: the single form takes two, so
+            // that a wavefront has as many bytes in flight as the split form.
+            uint32_t ra[U][NPL][8][4], rb[U][NPL][8][4];
+            u32x4 ba[U][NT16][NBT], bb[U][NT16][NBT];
+            auto load_step = [&](int64_t j0, uint32_t (&r)[U][NPL][8][4], u32x4 (&b)[U][NT16][NBT]) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) loadBt(j0 + 32 * u, b[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) loadA_full(j0 + 32 * u, r[u]);
+            };
+            auto mul_step = [&](const uint32_t (&r)[U][NPL][8][4], const u32x4 (&b)[U][NT16][NBT]) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) chunk(r[u], b[u]);
+            };
+            const int ns = (int)((wk1 - wk0) / (32 * U));
+            load_step(wk0, ra, ba);
             int g = 0;
-            // (the scheduling barriers keep the next chunk's loads ahead of
-            // the waits for this one: two chunks in flight per wavefront)
-            for (; g + 2 < ng; g += 2) {
-                loadBt(wk0 + 32 * (g + 1), bb);
-                loadA_full(wk0 + 32 * (g + 1), rb);
+            // (the scheduling barriers keep the next step's loads ahead of
+            // the waits for this one: two steps in flight per wavefront)
+            for (; g + 2 < ns; g += 2) {
+                load_step(wk0 + 32 * U * (g + 1), rb, bb);
                 __builtin_amdgcn_sched_barrier(0);
-                chunk(ra, ba);
-                loadBt(wk0 + 32 * (g + 2), ba);
-                loadA_full(wk0 + 32 * (g + 2), ra);
+                mul_step(ra, ba);
+                load_step(wk0 + 32 * U * (g + 2), ra, ba);
                 __builtin_amdgcn_sched_barrier(0);
-                chunk(rb, bb);
+                mul_step(rb, bb);
             }
-            if (g + 1 < ng) {
-                loadBt(wk0 + 32 * (g + 1), bb);
-                loadA_full(wk0 + 32 * (g + 1), rb);
+            if (g + 1 < ns) {
+                load_step(wk0 + 32 * U * (g + 1), rb, bb);
                 __builtin_amdgcn_sched_barrier(0);
-                chunk(ra, ba);
-                chunk(rb, bb);
+                mul_step(ra, ba);
+                mul_step(rb, bb);
             } else {
-                chunk(ra, ba);
+                mul_step(ra, ba);
             }
         }
     }
@@ -761,31 +769,36 @@ static int lp_occupancy(K kernel) {
     return nb;
 }
 
-template <int FMT, int NT16, bool SPLIT, bool VEC, bool RS, bool PF>
+template <int FMT, int NT16, bool SPLIT, bool VEC, bool RS, bool PF, int U>
 static const void* lp_fn(int* occ) {
-    static const int o = lp_occupancy(tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS, PF>);
+    static const int o = lp_occupancy(tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS, PF, U>);
     *occ = o;
-    return (const void*)tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS, PF>;
+    return (const void*)tsm2r_lp_kernel<FMT, NT16, SPLIT, 4, VEC, RS, PF, U>;
 }
 
-template <int FMT, bool VEC, bool RS, bool PF>
+// the split form steps one 32-column chunk at a time; the single form SU
+template <int FMT, bool VEC, bool RS, bool PF, int SU>
 static const void* lp_pick_f(bool split, int nt16, int* occ) {
     if (split)
-        return nt16 == 1 ? lp_fn<FMT, 1, true, VEC, RS, PF>(occ) : lp_fn<FMT, 2, true, VEC, RS, PF>(occ);
-    return nt16 == 1 ? lp_fn<FMT, 1, false, VEC, RS, PF>(occ) : lp_fn<FMT, 2, false, VEC, RS, PF>(occ);
+        return nt16 == 1 ? lp_fn<FMT, 1, true, VEC, RS, PF, 1>(occ) : lp_fn<FMT, 2, true, VEC, RS, PF, 1>(occ);
+    return nt16 == 1 ? lp_fn<FMT, 1, false, VEC, RS, PF, SU>(occ) : lp_fn<FMT, 2, false, VEC, RS, PF, SU>(occ);
 }
 
-// variant 0: wavefronts split k; 1: row split; 2: row split with prefetch
+// variant 0: wavefronts split k; 1: row split; 2: row split with the next
+// step in flight (single form: two chunks per step); 3: as 2 with one chunk
+// per step for the single form
 template <bool VEC>
 static const void* lp_pick(int fmt, bool split, int nt16, int var, int* occ) {
     if (fmt == FMT_BF16) {
-        if (var == 0) return lp_pick_f<FMT_BF16, VEC, false, false>(split, nt16, occ);
-        if (var == 1) return lp_pick_f<FMT_BF16, VEC, true, false>(split, nt16, occ);
-        return lp_pick_f<FMT_BF16, VEC, true, true>(split, nt16, occ);
+        if (var == 0) return lp_pick_f<FMT_BF16, VEC, false, false, 1>(split, nt16, occ);
+        if (var == 1) return lp_pick_f<FMT_BF16, VEC, true, false, 1>(split, nt16, occ);
+        if (var == 3) return lp_pick_f<FMT_BF16, VEC, true, true, 1>(split, nt16, occ);
+        return lp_pick_f<FMT_BF16, VEC, true, true, 2>(split, nt16, occ);
     }
-    if (var == 0) return lp_pick_f<FMT_F16, VEC, false, false>(split, nt16, occ);
-    if (var == 1) return lp_pick_f<FMT_F16, VEC, true, false>(split, nt16, occ);
-    return lp_pick_f<FMT_F16, VEC, true, true>(split, nt16, occ);
+    if (var == 0) return lp_pick_f<FMT_F16, VEC, false, false, 1>(split, nt16, occ);
+    if (var == 1) return lp_pick_f<FMT_F16, VEC, true, false, 1>(split, nt16, occ);
+    if (var == 3) return lp_pick_f<FMT_F16, VEC, true, true, 1>(split, nt16, occ);
+    return lp_pick_f<FMT_F16, VEC, true, true, 2>(split, nt16, occ);
 }
 
 static inline int64_t cdiv_lp(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -800,7 +813,7 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     // only)
     const char* frs = std::getenv("TSM2X_LP_RS");
     int var = (frs && *frs) ? (int)std::strtol(frs, nullptr, 10) : 2;
-    if (var < 0 || var > 2) var = 2;
+    if (var < 0 || var > 3) var = 2;
     const bool rs = var != 0;
     int occ = 1;
     P->fn = vec ? lp_pick<true>(fmt, split, nt16, var, &occ) : lp_pick<false>(fmt, split, nt16, var, &occ);
@@ -814,7 +827,7 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     // it, as for the float kernel, about 15/8 resident workgroups per CU
     const int64_t slots = (int64_t)cus * occ;
     int64_t S;
-    if (var == 2) {
+    if (var >= 2) {
         S = cus / P->tiles;
     } else {
         int64_t tgt = (int64_t)cus * 15 / 8;

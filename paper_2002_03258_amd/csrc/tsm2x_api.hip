@@ -416,6 +416,7 @@ int product(bool lform, int transA, int transB, int64_t m, int64_t k, int64_t n,
     L.m = m; L.k = k; L.n = n; L.A = A; L.lda = lda; L.B = Bk; L.ldb = ldbk; L.C = C; L.ldc = ldc;
     L.np = P.np; L.tile_rows = P.tile_rows; L.tiles = P.tiles; L.S = P.S; L.kslice = P.kslice;
     L.beta = beta;
+    L.pf = P.pf;
     if (P.S > 1) L.part = (double*)w;
     if (launch_tsm2r_nn(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
     return check_launch("tsm2r_nn_kernel");

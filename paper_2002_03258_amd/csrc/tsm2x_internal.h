@@ -41,6 +41,7 @@ struct NNPlan {             // TSM2R launch plan (column-major A)
     size_t ws;              // workspace bytes (0 when S == 1)
     int tall;               // 1: the taller of the two tile heights
     int occ;                // resident workgroups per CU of the instance
+    int pf;                 // float TSM2R: the next chunk held in flight (0/1)
 };
 
 // A plan fixed by the caller for one shape: S >= 1 forces the k split (rounded
@@ -70,6 +71,7 @@ struct LaunchNN {           // tsm2r_nn: C = A*B, column-major A
     int64_t kslice;         // columns per k slice
     double* part;           // S > 1: partial sums (workspace)
     double beta;            // C := beta*C + A*B (C read only if beta != 0)
+    int pf;                 // float TSM2R: the next chunk held in flight (0/1)
 };
 
 struct LaunchRT {           // rowtile: O = X*Y, X m x kin (kin <= 32)

@@ -305,6 +305,20 @@ static inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // target; the tile height whose grid lands closer wins, ties going to fewer
 // slices (longer streams per wavefront).  A pin from the caller (an
 // autotuner) replaces either choice.
+//
+// With the next chunk held in flight (tsm2r_nn_kernel, pf) one workgroup per
+// CU streams faster than 15/8 without it: where the shorter tiles can fill
+// 7/8 to all of the CUs exactly once (tiles * S in [7/8, 1] x CUs), that plan
+// is taken (A 10240^2 to 30720^2, n = 2..32: 0 to +14 %; grids of 320 on 256
+// CUs, two rounds with a third of the CUs holding two, lost 14-24 %, and are
+// never formed).  pf is also on for n > 16 and FP32 with n <= 4, with any
+// grid (tsm2r_nn_kernel).
+static int nn_pf(int64_t n, int dtype, int tall, int64_t W, int cus) {
+    if (tall) return 0;
+    if (n > 16 || (dtype == DT_F32 && n <= 4)) return 1;
+    return (W <= cus && 8 * W >= 7 * (int64_t)cus) ? 1 : 0;
+}
+
 int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NNPlan* P,
                const NNPin* pin) {
     // partial sums are stored at the kernel's padded width (16 or 32 columns)
@@ -362,7 +376,40 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
             P->occ = I.occ;
         }
     }
-    return found ? 0 : 1;
+    if (!found) return 1;
+    // one workgroup per CU with the prefetch, unless the caller or an
+    // override fixed the plan
+    const bool free_plan = s_pin <= 0 && tall_force < 0 && !(ft && *ft);
+    if (free_plan) {
+        NNInstance I{};
+        if (vec ? nn_pick<true>(dtype, np, false, &I) : nn_pick<false>(dtype, np, false, &I)) {
+            const int64_t tiles = cdiv64(m, I.tile_rows);
+            int64_t S = cus / tiles;
+            const int64_t s_len = k / (WK * 64);
+            const int64_t s_cost = (k * es) / ((int64_t)np * 200);
+            if (S > s_len) S = s_len;
+            if (S > s_cost) S = s_cost;
+            if (S < 1) S = 1;
+            const int64_t gran = (int64_t)WK * I.chunk;
+            int64_t ks = cdiv64(k, S);
+            ks = cdiv64(ks, gran) * gran;
+            S = cdiv64(k, ks);
+            const int64_t W = tiles * S;
+            if (W <= cus && 8 * W >= 7 * (int64_t)cus && I.occ >= 1) {
+                P->fn = I.fn;
+                P->name = I.name;
+                P->tiles = tiles;
+                P->tile_rows = I.tile_rows;
+                P->kslice = ks;
+                P->S = (int)S;
+                P->ws = S > 1 ? (size_t)tiles * S * np * I.tile_rows * 8 : 0;
+                P->tall = 0;
+                P->occ = I.occ;
+            }
+        }
+    }
+    P->pf = nn_pf(n, dtype, P->tall, P->tiles * P->S, cus);
+    return 0;
 }
 
 int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
@@ -371,13 +418,13 @@ int launch_tsm2r_nn(const LaunchNN& L, int dtype, hipStream_t st) {
     const int es = dtype == DT_F64 ? 8 : 4;
     int bvec = aligned16(L.B) && ((L.ldb * es) % 16 == 0);
     // the next chunk held in flight (see tsm2r_nn_kernel) where it measured
-    // faster (A 16384^2 to 32768^2): n > 16, where the matrix cores' share
-    // of a chunk is largest, +15-25 % (FP32 at 32768^2, n = 32: 5.1 -> 6.0
-    // TB/s), and FP32 with n <= 4, +2-9 %; elsewhere within -5..+1 %.
-    // TSM2X_NN_PF=0/1 overrides (measurement).
+    // faster (the plan's choice, plan_tsm2r): one workgroup per CU; n > 16,
+    // where the matrix cores' share of a chunk is largest, +15-25 % (FP32 at
+    // 32768^2, n = 32: 5.1 -> 6.0 TB/s); FP32 with n <= 4, +2-9 %; with the
+    // 15/8 grid and n = 8, 16 it measured -5..+1 %.  TSM2X_NN_PF=0/1
+    // overrides (measurement).
     const char* pfe = std::getenv("TSM2X_NN_PF");
-    int pf = (pfe && *pfe) ? (int)std::strtol(pfe, nullptr, 10)
-                           : (L.n > 16 || (dtype == DT_F32 && L.n <= 4)) ? 1 : 0;
+    int pf = (pfe && *pfe) ? (int)std::strtol(pfe, nullptr, 10) : L.pf;
     double beta = L.beta;
     void* args[] = {(void*)&L.m,   (void*)&L.k,      (void*)&n32,    (void*)&L.A,
                     (void*)&L.lda, (void*)&L.B,      (void*)&L.ldb,  (void*)&L.C,

@@ -149,7 +149,7 @@ def gpu_clocks():
 def _plan_prediction(c):
     p = tsm.tsm2r_plan(c["m"], c["k"], c["n"], tsm.F64 if c["dtype"] == torch.float64 else tsm.F32)
     return perf_model.predict_tsm2r(c["m"], c["k"], c["n"], es(c["dtype"]), p["slices"],
-                                    p["tiles"], p["tile_rows"], p["occupancy"])
+                                    p["tiles"], p["tile_rows"], p["occupancy"], tall=p["tall"])
 
 
 def model_summary(calls, evs, step_bytes, value):
@@ -175,13 +175,17 @@ def model_report(calls):
     then the model's constants fitted to all of them."""
     print("%-14s %4s %3s %5s %6s %9s %9s %7s" % ("workload", "tall", "S", "WGs", "rounds",
                                                  "pred GB/s", "meas GB/s", "pred/meas"))
-    samples = []
+    samples, top_frac, planner_frac, planner_best = [], [], [], 0
     for c in calls:
         r = tune.autotune_tsm2r(c["A"], c["B"], top=1000, pin=False)
         d = r["default"]
+        top_frac.append(r["report"][0]["gbs"] / r["best"]["gbs"])
+        planner_frac.append(d["gbs"] / r["best"]["gbs"])
+        planner_best += d is r["best"]
         for e in sorted(r["report"], key=lambda e: (e["tall"], e["slices"])):
             pr = perf_model.predict_tsm2r(c["m"], c["k"], c["n"], es(c["dtype"]), e["slices"],
-                                          e["tiles"], e["tile_rows"], e["occupancy"])
+                                          e["tiles"], e["tile_rows"], e["occupancy"],
+                                          tall=e["tall"])
             mark = " planner" if (e["tall"], e["slices"]) == (d["tall"], d["slices"]) else ""
             mark += " best" if e is r["best"] else ""
             print("%-14s %4d %3d %5d %6d %9.0f %9.0f %7.2f%s" % (
@@ -189,15 +193,33 @@ def model_report(calls):
                 e["pred_gbs"], e["gbs"], e["pred_gbs"] / e["gbs"], mark), flush=True)
             samples.append(dict(m=c["m"], k=c["k"], n=c["n"], es=es(c["dtype"]),
                                 slices=e["slices"], tiles=e["tiles"], tile_rows=e["tile_rows"],
-                                occupancy=e["occupancy"], seconds=e["seconds"]))
+                                occupancy=e["occupancy"], tall=e["tall"], seconds=e["seconds"]))
 
     def rms(dev):
         return float(np.sqrt(np.mean([np.log(perf_model.predict_tsm2r(
             s["m"], s["k"], s["n"], s["es"], s["slices"], s["tiles"], s["tile_rows"],
-            s["occupancy"], dev).seconds / s["seconds"]) ** 2 for s in samples])))
+            s["occupancy"], dev, s["tall"]).seconds / s["seconds"]) ** 2 for s in samples])))
     fitted = perf_model.fit(samples)
     print("plans %d; rms log(pred/meas) with the built-in constants %.3f, refitted %.3f: %s"
           % (len(samples), rms(perf_model.MI355X), rms(fitted), fitted), flush=True)
+
+    def worst(dev, sel):
+        return float(np.max([abs(np.log(perf_model.predict_tsm2r(
+            s["m"], s["k"], s["n"], s["es"], s["slices"], s["tiles"], s["tile_rows"],
+            s["occupancy"], dev, s["tall"]).seconds / s["seconds"])) for s in sel]))
+    f64 = [s for s in samples if s["es"] == 8]
+    f32 = [s for s in samples if s["es"] == 4]
+    fit64 = perf_model.fit(f64)
+    rms32 = float(np.sqrt(np.mean([np.log(perf_model.predict_tsm2r(
+        s["m"], s["k"], s["n"], s["es"], s["slices"], s["tiles"], s["tile_rows"],
+        s["occupancy"], fit64, s["tall"]).seconds / s["seconds"]) ** 2 for s in f32])))
+    print("worst |log(pred/meas)|: built-in %.3f, refitted %.3f; fitted on FP64 only, rms on FP32 "
+          "%.3f (worst %.3f)" % (worst(perf_model.MI355X, samples), worst(fitted, samples), rms32,
+                                 worst(fit64, f32)), flush=True)
+    print("model's top plan / best measured: mean %.4f, worst %.4f; planner's plan / best: mean "
+          "%.4f, worst %.4f; planner's plan the measured best on %d of %d workloads"
+          % (np.mean(top_frac), np.min(top_frac), np.mean(planner_frac), np.min(planner_frac),
+             planner_best, len(calls)), flush=True)
 
 
 def check_calls(calls):

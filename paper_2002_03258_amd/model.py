@@ -16,8 +16,9 @@ The same terms, counted the gfx950 way:
 - occupancy is the runtime's occupancy query of the compiled kernel (the
   plan query reports it), not a register estimate;
 - concurrency is counted in bytes: a wavefront keeps one 8 KB chunk of A in
-  flight (RG * ST 16-byte loads per lane, prefetched one chunk ahead), a
-  workgroup 4 wavefronts;
+  flight (RG * ST 16-byte loads per lane), or two where the kernel holds the
+  next chunk in flight across its waits (the library turns that on per plan;
+  `chunks_in_flight` restates its rule), a workgroup 4 wavefronts;
 - the grid is finite: W = tiles * S workgroups run in rounds of at most
   CUs * occupancy, and a last partial round runs at the concurrency it has;
 - a k split S > 1 adds its double partials (written by the kernel, read back
@@ -45,12 +46,12 @@ class Device:
     stream_gbs: float = 7090.0         # measured: 16-byte streaming read of one large buffer
     # fitted by `fit` to the measured rates of every candidate plan of the 24
     # square TSM2R products (m = k in {10240, 20480, 30720}, n in {2, 4, 8, 16},
-    # FP64 and FP32; 788 plans, timed after a warm-up in shuffled rounds):
-    latency_us: float = 1.53           # loaded memory latency
-    eta: float = 0.955                 # fraction of the streaming rate reached at full concurrency
-    balance_exp: float = 0.43          # weight of the per-CU balance term
-    t0_us: float = 7.7                 # fixed cost per product (launches, ramp-up, drain)
-    round_us: float = 8.2              # cost of each round of resident workgroups
+    # FP64 and FP32; 816 plans, timed after a warm-up in shuffled rounds):
+    latency_us: float = 1.51           # loaded memory latency
+    eta: float = 0.946                 # fraction of the streaming rate reached at full concurrency
+    balance_exp: float = 0.53          # weight of the per-CU balance term
+    t0_us: float = 7.4                 # fixed cost per product (launches, ramp-up, drain)
+    round_us: float = 3.4              # cost of each round of resident workgroups
 
 
 MI355X = Device()
@@ -84,6 +85,18 @@ def util_mem(bytes_in_flight_per_cu: float, dev: Device = MI355X) -> float:
     return min(1.0, bytes_in_flight_per_cu / concurrent_max_mem(dev))
 
 
+def chunks_in_flight(n: int, es: int, tall: int, workgroups: int, cus: int) -> int:
+    """Chunks of A a wavefront of the library's TSM2R kernel keeps in flight:
+    two where the library holds the next chunk in flight (the shorter tiles
+    only; n > 16, FP32 with n <= 4, or a grid of 7/8 to all of the CUs), one
+    otherwise."""
+    if tall:
+        return 1
+    if n > 16 or (es == 4 and n <= 4):
+        return 2
+    return 2 if workgroups <= cus and 8 * workgroups >= 7 * cus else 1
+
+
 def algorithmic_bytes(m: int, k: int, n: int, es: int) -> int:
     """A and B read once, C written once."""
     return es * (m * k + k * n + m * n)
@@ -107,9 +120,9 @@ def balance(a: int, cus: int) -> float:
 
 
 def predict_tsm2r(m: int, k: int, n: int, es: int, slices: int, tiles: int, tile_rows: int,
-                  occupancy: int, dev: Device = MI355X) -> Prediction:
+                  occupancy: int, dev: Device = MI355X, tall: int = 0) -> Prediction:
     """Time of one TSM2R product with a given plan (k split `slices`, `tiles`
-    row tiles of `tile_rows`, `occupancy` workgroups per CU).
+    row tiles of `tile_rows`, `occupancy` workgroups per CU, `tall` tiles).
 
     Each round of resident workgroups streams its share of A at
     eta * stream * util_mem * balance ** balance_exp; a split adds its
@@ -125,8 +138,9 @@ def predict_tsm2r(m: int, k: int, n: int, es: int, slices: int, tiles: int, tile
     rounds = [slots] * full + ([rem] if rem else [])
     t = dev.t0_us * 1e-6
     u = 0.0
+    chunks = chunks_in_flight(n, es, tall, W, dev.cus)
     for a in rounds:
-        u = util_mem(a * WAVES_PER_WG * INFLIGHT_PER_WAVE / dev.cus, dev)
+        u = util_mem(a * WAVES_PER_WG * INFLIGHT_PER_WAVE * chunks / dev.cus, dev)
         t += a * per_wg / (dev.eta * bw * u * balance(a, dev.cus) ** dev.balance_exp)
         t += dev.round_us * 1e-6
     if slices > 1:
@@ -137,8 +151,8 @@ def predict_tsm2r(m: int, k: int, n: int, es: int, slices: int, tiles: int, tile
 def fit(samples, dev: Device = MI355X) -> Device:
     """Fit latency_us, eta, balance_exp, t0_us and round_us to measured plans.
 
-    samples: dicts with m, k, n, es, slices, tiles, tile_rows, occupancy and
-    the measured `seconds`.  Minimises the squared log ratio of predicted to
+    samples: dicts with m, k, n, es, slices, tiles, tile_rows, occupancy,
+    optionally tall, and the measured `seconds`.  Minimises the squared log ratio of predicted to
     measured time (scipy's bounded least squares)."""
     from dataclasses import replace
 
@@ -147,7 +161,8 @@ def fit(samples, dev: Device = MI355X) -> Device:
     def resid(x):
         d = replace(dev, latency_us=x[0], eta=x[1], balance_exp=x[2], t0_us=x[3], round_us=x[4])
         return [math.log(predict_tsm2r(s["m"], s["k"], s["n"], s["es"], s["slices"], s["tiles"],
-                                       s["tile_rows"], s["occupancy"], d).seconds / s["seconds"])
+                                       s["tile_rows"], s["occupancy"], d,
+                                       s.get("tall", 0)).seconds / s["seconds"])
                 for s in samples]
 
     r = least_squares(resid, [dev.latency_us, dev.eta, dev.balance_exp, dev.t0_us, dev.round_us],
@@ -157,12 +172,12 @@ def fit(samples, dev: Device = MI355X) -> Device:
 
 
 def rank(m: int, k: int, n: int, es: int, plans, dev: Device = MI355X):
-    """Plans (dicts with slices, tiles, tile_rows, occupancy) sorted by
-    predicted time, each with its prediction attached as 'pred'."""
+    """Plans (dicts with slices, tiles, tile_rows, occupancy, optionally tall)
+    sorted by predicted time, each with its prediction attached as 'pred'."""
     out = []
     for p in plans:
         pr = predict_tsm2r(m, k, n, es, p["slices"], p["tiles"], p["tile_rows"], p["occupancy"],
-                           dev)
+                           dev, p.get("tall", 0))
         out.append(dict(p, pred=pr))
     return sorted(out, key=lambda p: (p["pred"].seconds, p["slices"]))
 

@@ -110,3 +110,27 @@ def test_rank_orders_by_predicted_time():
     assert r[0]["slices"] == 3
     ts = [p["pred"].seconds for p in r]
     assert ts == sorted(ts)
+
+
+def test_chunks_in_flight_follows_the_library_rule():
+    # the shorter tiles hold two chunks for n > 16, FP32 with n <= 4, and a
+    # grid of 7/8 to all of the CUs; the tall tiles never
+    assert M.chunks_in_flight(8, 8, 0, 256, 256) == 2
+    assert M.chunks_in_flight(8, 8, 0, 224, 256) == 2
+    assert M.chunks_in_flight(8, 8, 0, 223, 256) == 1
+    assert M.chunks_in_flight(8, 8, 0, 257, 256) == 1
+    assert M.chunks_in_flight(8, 8, 0, 480, 256) == 1
+    assert M.chunks_in_flight(32, 8, 0, 480, 256) == 2
+    assert M.chunks_in_flight(4, 4, 0, 480, 256) == 2
+    assert M.chunks_in_flight(4, 8, 0, 480, 256) == 1
+    assert M.chunks_in_flight(32, 8, 1, 256, 256) == 1
+
+
+def test_two_chunks_in_flight_raise_the_concurrency():
+    dev = M.Device(cus=256, stream_gbs=7000.0, latency_us=2.0, **PLAIN)
+    m, k, n, es = 256 * 64, 16384, 8, 8
+    one = M.predict_tsm2r(m, k, n, es, 1, 256, 64, 4, dev, tall=1)
+    two = M.predict_tsm2r(m, k, n, es, 1, 256, 64, 4, dev, tall=0)
+    assert two.seconds < one.seconds
+    assert two.tail_util == pytest.approx(min(1.0, 2 * one.tail_util))
+

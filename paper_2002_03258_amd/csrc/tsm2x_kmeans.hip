@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int rl = lane & 15, kk = lane >> 4;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
+    const int w = threadIdx.x / WAVE;
     typedef T Raw[NP][RL];
 
     T yv[KS][NT16], cn[NT16][4];
@@ -318,79 +318,9 @@ __global__ __launch_bounds__(256) void kmeans_assign_kernel(
         }
     };
 
-    // every tile whole: fetch without bounds (the points of a tile in range,
-    // every chunk column below k)
-    auto fetch_full = [&](int64_t tile, Raw& raw) {
-        const int64_t row0 = tile * TR;
-        typedef typename VecOf<T, RL>::type V;
-        if (!ROWX) {
-#pragma unroll
-            for (int st = 0; st < KS; ++st)
-#pragma unroll
-                for (int g = 0; g < RG; ++g)
-                    load_run<T, RL, true>(X + row0 + 16 * RL * g + RL * rl +
-                                              (int64_t)(4 * st + kk) * ldx,
-                                          RL, true, raw[st * RG + g]);
-        } else {
-#pragma unroll
-            for (int i = 0; i < NP; ++i) {
-                const int pc = lane + WAVE * i;
-                const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(
-                    X + (row0 + pc / PPP) * ldx + (pc % PPP) * RL));
-#pragma unroll
-                for (int e = 0; e < RL; ++e) raw[i][e] = v[e];
-            }
-        }
-    };
-    auto process = [&](int64_t tile, const Raw& raw) {
-        T xv[KS][RG][RL];
-        stage(raw, xv);
-        T bv[R], x2[R];
-        int bc[R];
-        init(bv, bc, x2);
-        Acc acc[RG][RL][NT16];
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int q = 0; q < RL; ++q)
-#pragma unroll
-                for (int t = 0; t < NT16; ++t) acc[g][q][t] = Acc{0, 0, 0, 0};
-        accumulate(xv, acc, x2, true);
-        panel_min(acc, 0, bv, bc);
-        finish(tile, bv, bc, x2);
-    };
-
     const int64_t ntiles = (m + TR - 1) / TR;
     const int64_t stride = (int64_t)gridDim.x * WPB;
     int64_t tile = (int64_t)blockIdx.x * WPB + w;
-    // Resident centroids and every tile whole: the next tile's points held
-    // in flight across the waits for this one, in straight-line code (a
-    // load issued on one path of a branch made the waits after the join
-    // drain every load, so the prefetch of the general loop hid nothing).
-    // The last fetch of a wavefront re-reads its own tile instead of
-    // branching around it.
-    if (RES && VEC && m % TR == 0 && k == KC && (!ROWX || k % RL == 0)) {
-        if (tile >= ntiles) return;
-        loadY(0, 0);
-        loadN(0);
-        Raw ra, rb;
-        fetch_full(tile, ra);
-        for (;;) {
-            int64_t t1 = tile + stride;
-            fetch_full(t1 < ntiles ? t1 : tile, rb);
-            __builtin_amdgcn_sched_barrier(0);
-            process(tile, ra);
-            if (t1 >= ntiles) break;
-            tile = t1;
-            t1 = tile + stride;
-            fetch_full(t1 < ntiles ? t1 : tile, ra);
-            __builtin_amdgcn_sched_barrier(0);
-            process(tile, rb);
-            if (t1 >= ntiles) break;
-            tile = t1;
-        }
-        return;
-    }
     if (RES) {
         loadY(0, 0);
         loadN(0);

@@ -814,6 +814,7 @@ int plan_tsm2r_lp(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec,
     const char* frs = std::getenv("TSM2X_LP_RS");
     int var = (frs && *frs) ? (int)std::strtol(frs, nullptr, 10) : 2;
     if (var < 0 || var > 3) var = 2;
+    if (!vec && var >= 2) var = 1;      // the prefetch needs 16-byte loads of the planes
     const bool rs = var != 0;
     int occ = 1;
     P->fn = vec ? lp_pick<true>(fmt, split, nt16, var, &occ) : lp_pick<false>(fmt, split, nt16, var, &occ);

@@ -378,11 +378,11 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
     }
     if (!found) return 1;
     // one workgroup per CU with the prefetch, unless the caller or an
-    // override fixed the plan
-    const bool free_plan = s_pin <= 0 && tall_force < 0 && !(ft && *ft);
+    // override fixed the plan (the prefetch needs 16-byte loads of A)
+    const bool free_plan = vec && s_pin <= 0 && tall_force < 0 && !(ft && *ft);
     if (free_plan) {
         NNInstance I{};
-        if (vec ? nn_pick<true>(dtype, np, false, &I) : nn_pick<false>(dtype, np, false, &I)) {
+        if (nn_pick<true>(dtype, np, false, &I)) {
             const int64_t tiles = cdiv64(m, I.tile_rows);
             int64_t S = cus / tiles;
             const int64_t s_len = k / (WK * 64);
@@ -408,7 +408,7 @@ int plan_tsm2r(int64_t m, int64_t k, int64_t n, int dtype, int cus, bool vec, NN
             }
         }
     }
-    P->pf = nn_pf(n, dtype, P->tall, P->tiles * P->S, cus);
+    P->pf = vec ? nn_pf(n, dtype, P->tall, P->tiles * P->S, cus) : 0;
     return 0;
 }
 

@@ -131,8 +131,12 @@ def test_caller_workspace_transposed_b(dev, dtype):
     ref = oracle.matmul(host_matrix(21, si.STREAM_A, m, k, dtype),
                         host_matrix(21, si.STREAM_B, k, n, dtype))
     assert err(to_np(C), ref) <= TOL[dtype]
+    # the size covers every plan of the shape: also that of an A whose
+    # leading dimension rules out 16-byte loads (a different grid)
+    A1 = dev_matrix(21, si.STREAM_A, m, k, dtype, dev, ld=m + 1)
+    assert err(to_np(tsm.tsm2r(A1, B, workspace=ws)), ref) <= TOL[dtype]
     with pytest.raises(tsm.TSMError):
-        tsm.tsm2r(A, B, workspace=ws[: nb - 256])
+        tsm.tsm2r(A, B, workspace=ws[:256])
 
 
 # the precision form: beta, a transposed B, TSM2L with k > 32, panels
@@ -240,7 +244,7 @@ def test_workspace_errors_leave_outputs_untouched(dev):
 def test_caller_workspace_precision_form(dev, lo, rowB):
     """The precision form's workspace holds the split partials and B's packed
     terms; tsm2x_workspace_size covers both, with B in either order, and a
-    smaller workspace is refused before any launch."""
+    workspace too small for them is refused before any launch."""
     m, k, n = 3000, 20000, 24
     A = dev_matrix(23, si.STREAM_A, m, k, torch.float32, dev)
     B = _rowmajor(23, si.STREAM_B, k, n, torch.float32, dev) if rowB else \
@@ -253,6 +257,6 @@ def test_caller_workspace_precision_form(dev, lo, rowB):
     assert torch.equal(C, tsm.tsm2r(S, B))
     C2 = tsm.empty_colmajor(m, n, torch.float32, dev).fill_(7.0)
     with pytest.raises(tsm.TSMError):
-        tsm.tsm2r(S, B, out=C2, workspace=ws[: nb - 256])
+        tsm.tsm2r(S, B, out=C2, workspace=ws[:256])
     torch.cuda.synchronize()
     assert bool((C2 == 7.0).all())

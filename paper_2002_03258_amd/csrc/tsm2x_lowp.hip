@@ -55,6 +55,31 @@ __device__ __forceinline__ f32x4 mfma32(u32x4 s, u32x4 t, f32x4 d) {
                                                   __builtin_bit_cast(f16x8, t), d, 0, 0, 0);
 }
 
+// Eight floats as three bf16 terms t1 + t2 + t3, packed two per dword
+// (value 2d in the low half of dword d): t1 = RNE(y), t2 = RNE(y - t1),
+// t3 = RNE(y - t1 - t2), each difference exact in float (the same terms as
+// the split of B; the hardware conversion rounds to nearest even).
+__device__ __forceinline__ void bf16_terms8(const float (&y)[8], u32x4& t1, u32x4& t2, u32x4& t3) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    auto pk = [](float a, float b) {
+        const bf16x2 v = {(__bf16)a, (__bf16)b};
+        return __builtin_bit_cast(uint32_t, v);
+    };
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const float a = y[2 * d], b = y[2 * d + 1];
+        const uint32_t p1 = pk(a, b);
+        const float ra = a - __uint_as_float(p1 << 16);
+        const float rb = b - __uint_as_float(p1 & 0xffff0000u);
+        const uint32_t p2 = pk(ra, rb);
+        const float sa = ra - __uint_as_float(p2 << 16);
+        const float sb = rb - __uint_as_float(p2 & 0xffff0000u);
+        t1[d] = p1;
+        t2[d] = p2;
+        t3[d] = pk(sa, sb);
+    }
+}
+
 // --------------------------------------------------------------------------
 // split
 // --------------------------------------------------------------------------
@@ -523,6 +548,18 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // it, so the loads hit L2 and need no LDS; CT output tiles per workgroup then
 // share each Y word).  Reduction across wavefronts and workgroups as in
 // tn_kernel.
+//
+// The bf16 single form with Y direct (MX) runs its whole wavefronts on the
+// 16x16x32 bf16 matrix cores instead: X is staged in LDS as loaded (16-bit,
+// no widening) and read back as the S operand (lane (rl, kk): column
+// 16 ct + rl, 8 consecutive rows 32 blk + 8 kk ..), Y is loaded in the
+// matching T operand order (column 16 t + rl, the same 8 rows) and split
+// into three bf16 terms in registers, and each 32-row block takes
+// hi*(Y1 + Y2 + Y3): three matrix-core instructions where the float path
+// takes eight, and no widening.  The products of 16-bit values are exact in
+// float, so the error against the stored values is that of float
+// accumulation, as on the float path.  Y columns beyond n read column n - 1;
+// their output columns are never stored.
 // --------------------------------------------------------------------------
 template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC, bool YD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void tn_lp_kernel(
@@ -553,6 +590,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     const int64_t wb0 = sb0 + w * lw;
     const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
     float (*tile)[SROW] = lds[w];
+    constexpr bool MX = FMT == FMT_BF16 && !SPLIT && YD;
+    constexpr int SROW16 = SR + 8;             // padded 16-bit LDS column (16 more bytes)
+    static_assert(!MX || NX * SROW16 * 2 <= NC * SROW * 4, "16-bit tile fits the float one");
+    uint16_t (*tile16)[SROW16] = reinterpret_cast<uint16_t (*)[SROW16]>(&lds[w][0][0]);
 
     f32x4 acc[CT][NT16];
 #pragma unroll
@@ -664,7 +705,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // direct): straight-line loads, the next step's X kept in flight across
     // the waits for this step's operands (the scheduling barriers stop the
     // compiler from sinking those loads below the waits).
-    const bool whole = pf && VEC && YC && YD && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
+    const bool whole = !MX && pf && VEC && YC && YD && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
+    // MX: the same whole-wavefront test without pf (pf only picks one or two
+    // steps in flight, with the same arithmetic)
+    const bool mx_whole = MX && VEC && YC && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
     auto loadX_full = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4]) {
 #pragma unroll
         for (int pl = 0; pl < NPL; ++pl) {
@@ -690,7 +734,90 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         }
     };
 
-    if (wb1 > wb0 && whole) {
+    // MX: Y rows rb + 32 blk + 8 kk .. + 7 of column 16 t + rl (n - 1 beyond n)
+    auto loadY_mx = [&](int64_t rb, f32x4 (&ym)[4][NT16][2]) {
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                const int p = 16 * t + rl;
+                const int pc = p < n ? p : n - 1;
+                const f32x4* src = reinterpret_cast<const f32x4*>(Y + rb + 32 * blk + 8 * kk +
+                                                                  (int64_t)pc * ldy);
+                ym[blk][t][0] = src[0];
+                ym[blk][t][1] = src[1];
+            }
+    };
+    auto step_mx = [&](const uint32_t (&xv)[XG][NPL][4], const f32x4 (&ym)[4][NT16][2]) {
+        wave_lds_fence();
+#pragma unroll
+        for (int cg = 0; cg < XG; ++cg)
+            *reinterpret_cast<u32x4*>(&tile16[4 * cg + kk][8 * rl]) =
+                u32x4{xv[cg][0][0], xv[cg][0][1], xv[cg][0][2], xv[cg][0][3]};
+        wave_lds_fence();
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            u32x4 y1[NT16], y2[NT16], y3[NT16];
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                float y[8];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    y[q] = ym[blk][t][0][q];
+                    y[4 + q] = ym[blk][t][1][q];
+                }
+                bf16_terms8(y, y1[t], y2[t], y3[t]);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const u32x4 xs = *reinterpret_cast<const u32x4*>(&tile16[16 * ct + rl][32 * blk + 8 * kk]);
+#pragma unroll
+                for (int t = 0; t < NT16; ++t) {
+                    acc[ct][t] = mfma32<FMT_BF16>(xs, y1[t], acc[ct][t]);
+                    acc[ct][t] = mfma32<FMT_BF16>(xs, y2[t], acc[ct][t]);
+                    acc[ct][t] = mfma32<FMT_BF16>(xs, y3[t], acc[ct][t]);
+                }
+            }
+        }
+    };
+
+    if (MX && wb1 > wb0 && mx_whole) {
+        const int64_t nit = (wb1 - wb0) / SR;
+        uint32_t xa[XG][NPL][4], xb[XG][NPL][4];
+        f32x4 ym[4][NT16][2];
+        if (!pf) {
+            // one step at a time, no conditional loads (measured faster for
+            // n <= 8, where the step is short)
+            for (int64_t it = 0; it < nit; ++it) {
+                loadX_full(wb0 + it * SR, xa);
+                loadY_mx(wb0 + it * SR, ym);
+                step_mx(xa, ym);
+            }
+        } else {
+            // two steps per iteration, the next step's X in flight (as below)
+            loadX_full(wb0, xa);
+            int64_t it = 0;
+            for (; it + 2 < nit; it += 2) {
+                loadY_mx(wb0 + it * SR, ym);
+                loadX_full(wb0 + (it + 1) * SR, xb);
+                __builtin_amdgcn_sched_barrier(0);
+                step_mx(xa, ym);
+                loadY_mx(wb0 + (it + 1) * SR, ym);
+                loadX_full(wb0 + (it + 2) * SR, xa);
+                __builtin_amdgcn_sched_barrier(0);
+                step_mx(xb, ym);
+            }
+            loadY_mx(wb0 + it * SR, ym);
+            if (it + 1 < nit) {
+                loadX_full(wb0 + (it + 1) * SR, xb);
+                step_mx(xa, ym);
+                loadY_mx(wb0 + (it + 1) * SR, ym);
+                step_mx(xb, ym);
+            } else {
+                step_mx(xa, ym);
+            }
+        }
+    } else if (wb1 > wb0 && whole) {
         // two steps per iteration with no conditional loads inside (a load
         // issued on one path only makes the waits after the join count it
         // as absent, and they then wait for everything)

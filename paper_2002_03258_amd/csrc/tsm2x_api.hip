@@ -173,17 +173,24 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // only; with the next step in flight they still beat one tile (A 16384^2
     // and 32768^2, n = 24, 32: split 3.4-4.2 -> 4.4-4.9 TB/s, single
     // 2.0-2.6 -> 2.5-3.1; without the prefetch one tile was faster)
-    const int ct_dflt = 2;
+    // bfloat16 planes with n <= 16 and more than four tiles: four tiles per
+    // workgroup and one workgroup per CU on the 16-bit matrix cores
+    // (tn_lp_kernel, MX; A 16384^2, n = 8: split 5.8 -> 6.6 TB/s, single
+    // 5.4 -> 6.5 in the access-pattern probe of this grid)
+    const bool bf = dt == DT_BF16 || dt == DT_BF16_SPLIT;
+    const bool four = bf && n <= 16 && cdiv(ncols, 16) > 4;
+    const int ct_dflt = four ? 4 : 2;
     P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", ct_dflt) : 1;
-    if (P.ct != 1 && P.ct != 2) P.ct = 1;
+    if (P.ct == 4 && !(bf && n <= 16)) P.ct = 2;
+    if (P.ct != 1 && P.ct != 2 && P.ct != 4) P.ct = 1;
     // rows per wavefront loop iteration: G stages of 16*RL rows for the
     // float kernels (one stage with two output tiles), 128 for the 16-bit form
-    P.rg = P.ct == 2 ? 1 : (int)env_int("TSM2X_TN_G", 2);
+    P.rg = P.ct >= 2 ? 1 : (int)env_int("TSM2X_TN_G", 2);
     if (P.rg != 1 && P.rg != 2 && P.rg != 4) P.rg = 2;
     const int64_t RB = plain_dtype(dt) ? 16 * (16 / esize(dt)) * P.rg : 128;
     const int NT16 = n <= 16 ? 1 : 2;
     P.groups = cdiv(cdiv(ncols, 16), P.ct) * P.ct;
-    const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * 2);
+    const int64_t target = env_int("TSM2X_TN_TARGET_BLOCKS", (int64_t)cus * (P.ct == 4 ? 1 : 2));
     int64_t S = cdiv(target, P.groups / P.ct);
     const int64_t s_len = R / (RB * 4 * 8);   // >= 8 steps per wavefront
     if (S > s_len) S = s_len;
@@ -207,9 +214,9 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // for n <= 8 one step at a time measured faster than two (A 16384^2,
     // bf16 single, n = 8: 5.2 TB/s with two steps, 5.8 with one).
     const bool split = dt == DT_BF16_SPLIT || dt == DT_F16_SPLIT;
-    const bool mx = dt == DT_BF16 && P.groups / P.ct > 1;
+    const bool mx = bf && (!split || n <= 16) && P.groups / P.ct > 1;
     const bool pf = plain_dtype(dt) ? n > 16
-                    : mx            ? n > 8
+                    : mx            ? P.ct == 4 || n > 8
                                     : !split || n > 16 || (P.groups / P.ct) * P.S > 2 * (int64_t)cus;
     P.pf = (int)env_int("TSM2X_TN_PF", pf ? 1 : 0);
     return P;

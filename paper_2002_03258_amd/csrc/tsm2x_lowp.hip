@@ -549,17 +549,21 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // share each Y word).  Reduction across wavefronts and workgroups as in
 // tn_kernel.
 //
-// The bf16 single form with Y direct (MX) runs its whole wavefronts on the
+// bfloat16 planes with Y direct (MX; the split form for n <= 16) run on the
 // 16x16x32 bf16 matrix cores instead: X is staged in LDS as loaded (16-bit,
 // no widening) and read back as the S operand (lane (rl, kk): column
 // 16 ct + rl, 8 consecutive rows 32 blk + 8 kk ..), Y is loaded in the
 // matching T operand order (column 16 t + rl, the same 8 rows) and split
 // into three bf16 terms in registers, and each 32-row block takes
-// hi*(Y1 + Y2 + Y3): three matrix-core instructions where the float path
-// takes eight, and no widening.  The products of 16-bit values are exact in
-// float, so the error against the stored values is that of float
-// accumulation, as on the float path.  Y columns beyond n read column n - 1;
-// their output columns are never stored.
+// hi*(Y1 + Y2 + Y3) (+ lo*(Y1 + Y2)), the products the TSM2R form keeps:
+// three (five) matrix-core instructions where the float path takes eight,
+// and no widening.  Products of 16-bit values are exact in float, so the
+// error against the stored values is that of float accumulation, as on the
+// float path.  Whole wavefronts load straight-line; ragged ones (rows, X
+// columns, unaligned Y) take the same step with bounds-checked loads.
+// Y columns beyond n read column n - 1; their output columns are never
+// stored.  With four output tiles per workgroup (n <= 16) the split form's
+// 16-bit tiles take 136 KB of LDS: one workgroup per CU.
 // --------------------------------------------------------------------------
 template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC, bool YD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void tn_lp_kernel(
@@ -576,7 +580,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     constexpr int YG = 4 * NT16;               // Y column groups of 4 (staged Y)
     constexpr int NB = SR / 16;                // 16-row blocks per step
     constexpr int NPL = SPLIT ? 2 : 1;
-    __shared__ __align__(16) float lds[WK][NC][SROW];
+    // bfloat16 planes with Y direct run on the 16-bit matrix cores (MX): all
+    // of their wavefronts, whole or ragged; the split form with n > 16 keeps
+    // the float path (its registers would not hold the MX step)
+    constexpr bool MX = FMT == FMT_BF16 && YD && (!SPLIT || NT16 == 1);
+    constexpr int SROW16 = SR + 8;             // padded 16-bit LDS column (16 more bytes)
+    __shared__ __align__(16) float lds[WK][MX ? 1 : NC][SROW];
+    __shared__ __align__(16) uint16_t lds16[WK][MX ? NPL : 1][MX ? NX : 1][SROW16];
     __shared__ double red[WK][WAVE][4 * NT16];
 
     const int lane = threadIdx.x & (WAVE - 1);
@@ -590,10 +600,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     const int64_t wb0 = sb0 + w * lw;
     const int64_t wb1 = (wb0 + lw < sb1) ? wb0 + lw : sb1;
     float (*tile)[SROW] = lds[w];
-    constexpr bool MX = FMT == FMT_BF16 && !SPLIT && YD;
-    constexpr int SROW16 = SR + 8;             // padded 16-bit LDS column (16 more bytes)
-    static_assert(!MX || NX * SROW16 * 2 <= NC * SROW * 4, "16-bit tile fits the float one");
-    uint16_t (*tile16)[SROW16] = reinterpret_cast<uint16_t (*)[SROW16]>(&lds[w][0][0]);
+    uint16_t (*tile16)[MX ? NX : 1][SROW16] = lds16[w];
 
     f32x4 acc[CT][NT16];
 #pragma unroll
@@ -707,8 +714,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // compiler from sinking those loads below the waits).
     const bool whole = !MX && pf && VEC && YC && YD && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
     // MX: the same whole-wavefront test without pf (pf only picks one or two
-    // steps in flight, with the same arithmetic)
+    // steps in flight, with the same arithmetic); ragged wavefronts take the
+    // MX step too, with bounds-checked loads
     const bool mx_whole = MX && VEC && YC && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
+    // two steps in flight need two X steps in registers: not with four split tiles
+    constexpr bool MX_TWO = MX && !(SPLIT && CT >= 4);
     auto loadX_full = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4]) {
 #pragma unroll
         for (int pl = 0; pl < NPL; ++pl) {
@@ -748,12 +758,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 ym[blk][t][1] = src[1];
             }
     };
+    // the same rows with bounds: rows at or beyond wb1 and columns beyond n
+    // are zero (ragged wavefronts, unaligned Y)
+    auto loadY_mx_gen = [&](int64_t rb, f32x4 (&ym)[4][NT16][2]) {
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+            for (int t = 0; t < NT16; ++t) {
+                const int p = 16 * t + rl;
+                const int64_t r = rb + 32 * blk + 8 * kk;
+                const int64_t valid = wb1 - r;
+                float v0[4], v1[4];
+                if (p < n) {
+                    load_run<float, 4, VEC>(Y + r + (int64_t)p * ldy, valid, valid >= 4, v0);
+                    load_run<float, 4, VEC>(Y + r + 4 + (int64_t)p * ldy, valid - 4, valid >= 8, v1);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v0[q] = v1[q] = 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ym[blk][t][0][q] = v0[q];
+                    ym[blk][t][1][q] = v1[q];
+                }
+            }
+    };
+    // products kept: hi*(Y1 + Y2 + Y3) (+ lo*(Y1 + Y2)), as in tsm2r_lp
     auto step_mx = [&](const uint32_t (&xv)[XG][NPL][4], const f32x4 (&ym)[4][NT16][2]) {
         wave_lds_fence();
 #pragma unroll
         for (int cg = 0; cg < XG; ++cg)
-            *reinterpret_cast<u32x4*>(&tile16[4 * cg + kk][8 * rl]) =
-                u32x4{xv[cg][0][0], xv[cg][0][1], xv[cg][0][2], xv[cg][0][3]};
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl)
+                *reinterpret_cast<u32x4*>(&tile16[pl][4 * cg + kk][8 * rl]) =
+                    u32x4{xv[cg][pl][0], xv[cg][pl][1], xv[cg][pl][2], xv[cg][pl][3]};
         wave_lds_fence();
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) {
@@ -770,12 +808,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             }
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const u32x4 xs = *reinterpret_cast<const u32x4*>(&tile16[16 * ct + rl][32 * blk + 8 * kk]);
+                u32x4 xs[NPL];
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl)
+                    xs[pl] = *reinterpret_cast<const u32x4*>(&tile16[pl][16 * ct + rl][32 * blk + 8 * kk]);
 #pragma unroll
                 for (int t = 0; t < NT16; ++t) {
-                    acc[ct][t] = mfma32<FMT_BF16>(xs, y1[t], acc[ct][t]);
-                    acc[ct][t] = mfma32<FMT_BF16>(xs, y2[t], acc[ct][t]);
-                    acc[ct][t] = mfma32<FMT_BF16>(xs, y3[t], acc[ct][t]);
+                    acc[ct][t] = mfma32<FMT_BF16>(xs[0], y1[t], acc[ct][t]);
+                    acc[ct][t] = mfma32<FMT_BF16>(xs[0], y2[t], acc[ct][t]);
+                    acc[ct][t] = mfma32<FMT_BF16>(xs[0], y3[t], acc[ct][t]);
+                    if (SPLIT) {
+                        acc[ct][t] = mfma32<FMT_BF16>(xs[NPL - 1], y1[t], acc[ct][t]);
+                        acc[ct][t] = mfma32<FMT_BF16>(xs[NPL - 1], y2[t], acc[ct][t]);
+                    }
                 }
             }
         }
@@ -785,7 +830,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int64_t nit = (wb1 - wb0) / SR;
         uint32_t xa[XG][NPL][4], xb[XG][NPL][4];
         f32x4 ym[4][NT16][2];
-        if (!pf) {
+        if (!MX_TWO || !pf) {
             // one step at a time, no conditional loads (measured faster for
             // n <= 8, where the step is short)
             for (int64_t it = 0; it < nit; ++it) {
@@ -817,7 +862,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                 step_mx(xa, ym);
             }
         }
-    } else if (wb1 > wb0 && whole) {
+    } else if (MX && wb1 > wb0) {
+        // ragged or unaligned: one step at a time, loads bounds-checked
+        const int64_t nit = (wb1 - wb0 + SR - 1) / SR;
+        for (int64_t it = 0; it < nit; ++it) {
+            uint32_t xv[XG][NPL][4];
+            f32x4 ym[4][NT16][2];
+            loadX(wb0 + it * SR, xv);
+            loadY_mx_gen(wb0 + it * SR, ym);
+            step_mx(xv, ym);
+        }
+    } else if (!MX && wb1 > wb0 && whole) {
         // two steps per iteration with no conditional loads inside (a load
         // issued on one path only makes the waits after the join count it
         // as absent, and they then wait for everything)
@@ -845,7 +900,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         } else {
             step(xa, yv);
         }
-    } else if (wb1 > wb0) {
+    } else if (!MX && wb1 > wb0) {
         const int64_t nit = (wb1 - wb0 + SR - 1) / SR;
         uint32_t xv[XG][NPL][4];
         float yv[YW][4];
@@ -1138,6 +1193,9 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
         }                                                                                 \
     }
     if (fmt == FMT_BF16) {
+        if (L.ct == 4 && L.n <= 16) {
+            if (split) TSM_T(FMT_BF16, 1, 4, true, true) else TSM_T(FMT_BF16, 1, 4, false, true)
+        }
         if (split) TSM_T2(FMT_BF16, true) else TSM_T2(FMT_BF16, false)
     } else {
         if (split) TSM_T2(FMT_F16, true) else TSM_T2(FMT_F16, false)

@@ -103,8 +103,12 @@ def test_lowp_tsm2r_in_flight_path(dev, monkeypatch, fmt, lo, m, k, n):
 
 
 @pytest.mark.parametrize("lo", [False, True])
-@pytest.mark.parametrize("m,k,n", [(8192, 4096, 8), (8192, 4096, 32), (8200, 1000, 24)])
+@pytest.mark.parametrize("m,k,n", [(8192, 4096, 8), (8192, 4096, 32), (8200, 1000, 24),
+                                   (8200, 1000, 16)])
 def test_lowp_grad_b_in_flight_path(dev, monkeypatch, lo, m, k, n):
+    """The 16-bit matrix-core dB: one or two steps in flight (single form),
+    four tiles per workgroup for n <= 16; (8200, 1000) leaves ragged rows and
+    a ragged last column group to the bounds-checked step."""
     seed = 950 + n
     A = dev_matrix(seed, si.STREAM_A, m, k, torch.float32, dev)
     dC = dev_matrix(seed, si.STREAM_DC, m, n, torch.float32, dev)

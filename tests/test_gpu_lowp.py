@@ -307,15 +307,16 @@ def test_grad_b_keeps_the_lo_plane(dev, fmt, code, m, n):
 
 
 @pytest.mark.parametrize("fmt,code", FMTS)
-@pytest.mark.parametrize("m,n", [(2048, 8), (2048, 16), (2048, 32), (2000, 24)])
+@pytest.mark.parametrize("m,n", [(2048, 8), (2048, 16), (2048, 32), (2000, 24), (2000, 16)])
 def test_grad_b_keeps_every_term_of_dC(dev, fmt, code, m, n):
     """dB = A^T*dC with A = diag(+-1) (hi = +-1, lo = 0) and dC in [1, 2) with
     full 24-bit significands: dB[j, p] = +-dC[j, p] exactly in both forms.
-    On the bf16 matrix-core path of the single form dC enters as three bf16
-    terms (8 + 8 + 8 bits), so dropping or misplacing any of them changes the
-    last bits.  m = 2048 puts every wavefront on the straight-line paths
-    (one step in flight for n = 8, two for n = 16 and 32); m = 2000 leaves
-    ragged row ranges to the general loop."""
+    On the bf16 matrix-core path (single form; split form for n <= 16) dC
+    enters as three bf16 terms (8 + 8 + 8 bits), so dropping or misplacing
+    any of them changes the last bits.  m = 2048 puts every wavefront on the straight-line paths
+    (four 16-column tiles per workgroup for n <= 16); m = 2000 leaves
+    ragged row ranges and a ragged last column group to the bounds-checked
+    step."""
     A = _one_hot_rows(m, m, 1.0, 59 + m)
     dC = (1.0 + np.abs(si.matrix(61 + n, si.STREAM_DC, m, n).numpy())).astype(np.float32)
     assert np.any(dC != dC.astype(np.float64).round(4))        # not short significands

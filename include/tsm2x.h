@@ -170,7 +170,10 @@ int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc,
  * m is split across wavefronts and workgroups and finished in double
  * precision in a fixed order.
  * dtype: TSM_F64, TSM_F32 (A, dC, dB all of it), or a 16-bit form of A as in
- * tsm2r (dC and dB float).
+ * tsm2r (dC and dB float).  With bfloat16 planes and more than one group of
+ * 16 columns of A, dC enters the bf16 matrix cores as three bf16 terms per
+ * value (exact for finite dC in bfloat16's normal range), with the products
+ * tsm2r keeps; a non-finite dC entry then gives NaN in its column of dB.
  * Arguments: 1 m, 2 k, 3 n, 4 A, 5 lda, 6 dC, 7 lddc, 8 dB, 9 lddb,
  * 10 dtype, 11 ws, 12 ws_bytes, 13 stream (ws may be NULL: library buffer). */
 int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,

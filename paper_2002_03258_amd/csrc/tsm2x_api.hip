@@ -159,6 +159,8 @@ struct TNPlan {
     int rg;
     int ct;                 // output tiles per workgroup
     int pf;                 // 16-bit forms: the next step's X held in flight
+    bool yt;                // bf16 planes, n > 16: Y split once into packed terms
+    size_t yt_off;          // their offset in the workspace
     size_t ws;
 };
 
@@ -177,11 +179,16 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // workgroup and one workgroup per CU on the 16-bit matrix cores
     // (tn_lp_kernel, MX; A 16384^2, n = 8: split 5.8 -> 6.6 TB/s, single
     // 5.4 -> 6.5 in the access-pattern probe of this grid)
+    // For n > 16 the four tiles take Y's bf16 terms split once per call into
+    // the workspace (their registers would not hold the split in the step;
+    // A 16384^2, n = 32, probe of this grid: split 4.4 -> 5.6 TB/s, single
+    // 3.4 -> 4.2), while Y's terms stay below 256 MB (R up to 2.7 M rows).
     const bool bf = dt == DT_BF16 || dt == DT_BF16_SPLIT;
-    const bool four = bf && n <= 16 && cdiv(ncols, 16) > 4;
+    const size_t yt_bytes = lp_bterms_bytes(R, n);
+    const bool four = bf && cdiv(ncols, 16) > 4 && (n <= 16 || yt_bytes <= ((size_t)256 << 20));
     const int ct_dflt = four ? 4 : 2;
     P.ct = ncols > 16 ? (int)env_int("TSM2X_TN_CT", ct_dflt) : 1;
-    if (P.ct == 4 && !(bf && n <= 16)) P.ct = 2;
+    if (P.ct == 4 && !bf) P.ct = 2;
     if (P.ct != 1 && P.ct != 2 && P.ct != 4) P.ct = 1;
     // rows per wavefront loop iteration: G stages of 16*RL rows for the
     // float kernels (one stage with two output tiles), 128 for the 16-bit form
@@ -201,6 +208,11 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     P.S = (int)cdiv(R, rs);
     if (P.S < 1) P.S = 1;
     P.ws = P.S > 1 ? (size_t)P.groups * P.S * 256 * NT16 * 8 : 0;
+    P.yt = P.ct == 4 && n > 16;
+    if (P.yt) {
+        P.yt_off = (P.ws + 255) / 256 * 256;
+        P.ws = P.yt_off + yt_bytes;
+    }
     // The next step held in flight (tn_kernel, tn_lp_kernel), where it
     // measured faster.  Float forms: for n > 16, +48-66 % (A 16384^2 to
     // 32768^2: 3.0-3.3 -> 4.5-5.3 TB/s); for n <= 16 from -18 % to +6 %, so
@@ -543,6 +555,7 @@ int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda, cons
     L.ldo = lddb; L.groups = P.groups; L.S = P.S; L.rslice = P.rslice; L.rg = P.rg; L.ct = P.ct;
     L.pf = P.pf;
     if (P.S > 1) L.part = (double*)w;
+    if (P.yt) L.yt = (char*)w + P.yt_off;
     if (!plain_dtype(dtype)) {
         if (launch_tn_lp(L, dtype, st)) return TSM_ERR_UNSUPPORTED;
         return check_launch("tn_lp_kernel");

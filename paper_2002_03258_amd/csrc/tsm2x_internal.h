@@ -100,6 +100,7 @@ struct LaunchTN {           // tn: O = X^T*Y, X R x ncols, Y R x n
     int pf;                 // 16-bit forms: the next step's X held in flight (0/1)
     double* part;           // S > 1: partial sums (workspace)
     double beta;            // O := beta*O + X^T*Y (O read only if beta != 0)
+    const void* yt;         // bf16 planes, n > 16: Y's packed bf16 terms (workspace, or null)
 };
 
 // Low-precision storage forms of A (bf16 / f16, single or split planes).

@@ -36,6 +36,7 @@
 #include <stdint.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "tsm2x_device.h"
 #include "tsm2x_half.h"
@@ -562,14 +563,17 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // float path.  Whole wavefronts load straight-line; ragged ones (rows, X
 // columns, unaligned Y) take the same step with bounds-checked loads.
 // Y columns beyond n read column n - 1; their output columns are never
-// stored.  With four output tiles per workgroup (n <= 16) the split form's
-// 16-bit tiles take 136 KB of LDS: one workgroup per CU.
+// stored.  With four output tiles per workgroup the split form's 16-bit
+// tiles take 136 KB of LDS: one workgroup per CU.  For n > 16 (YT) Y's
+// terms are split once per call into the workspace, packed in the operand
+// order, and the step loads them instead of splitting Y in registers.
 // --------------------------------------------------------------------------
-template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC, bool YD>
+template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC, bool YD, bool YT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
-    float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part, int pf) {
+    float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part,
+    const u32x4* __restrict__ Yt, int pf) {
     typedef Mfma<float> M;
     constexpr int WK = 4;
     constexpr int SR = 128;                    // rows per step
@@ -583,7 +587,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // bfloat16 planes with Y direct run on the 16-bit matrix cores (MX): all
     // of their wavefronts, whole or ragged; the split form with n > 16 keeps
     // the float path (its registers would not hold the MX step)
-    constexpr bool MX = FMT == FMT_BF16 && YD && (!SPLIT || NT16 == 1);
+    constexpr bool MX = FMT == FMT_BF16 && YD && (!SPLIT || NT16 == 1 || YT);
+    static_assert(!YT || (FMT == FMT_BF16 && YD), "packed Y terms feed the bf16 matrix cores");
     constexpr int SROW16 = SR + 8;             // padded 16-bit LDS column (16 more bytes)
     __shared__ __align__(16) float lds[WK][MX ? 1 : NC][SROW];
     __shared__ __align__(16) uint16_t lds16[WK][MX ? NPL : 1][MX ? NX : 1][SROW16];
@@ -718,7 +723,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // MX step too, with bounds-checked loads
     const bool mx_whole = MX && VEC && YC && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
     // two steps in flight need two X steps in registers: not with four split tiles
-    constexpr bool MX_TWO = MX && !(SPLIT && CT >= 4);
+    constexpr bool MX_TWO = MX && !YT && !(SPLIT && CT >= 4);
     auto loadX_full = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4]) {
 #pragma unroll
         for (int pl = 0; pl < NPL; ++pl) {
@@ -745,46 +750,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     };
 
     // MX: Y rows rb + 32 blk + 8 kk .. + 7 of column 16 t + rl (n - 1 beyond n)
-    auto loadY_mx = [&](int64_t rb, f32x4 (&ym)[4][NT16][2]) {
+    // YT: the three bf16 terms of Y, split once per call (split_b_kernel on
+    // Y), packed in the operand order: 32-row block b, column group t, term
+    // e at Yt[((b * NT16 + t) * 3 + e) * 64 + lane], zero beyond R and n
+    typedef typename std::conditional<YT, u32x4[4][NT16][3], f32x4[4][NT16][2]>::type YBuf;
+    const int64_t nblk = (R + 31) / 32;
+    auto loadY_mx = [&](int64_t rb, YBuf& ym) {
+        if constexpr (YT) {
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk)
+            for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
-            for (int t = 0; t < NT16; ++t) {
-                const int p = 16 * t + rl;
-                const int pc = p < n ? p : n - 1;
-                const f32x4* src = reinterpret_cast<const f32x4*>(Y + rb + 32 * blk + 8 * kk +
-                                                                  (int64_t)pc * ldy);
-                ym[blk][t][0] = src[0];
-                ym[blk][t][1] = src[1];
-            }
+                for (int t = 0; t < NT16; ++t)
+#pragma unroll
+                    for (int e = 0; e < 3; ++e)
+                        ym[blk][t][e] = Yt[(((rb >> 5) + blk) * NT16 + t) * 3 * WAVE + e * WAVE + lane];
+        } else {
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+                for (int t = 0; t < NT16; ++t) {
+                    const int p = 16 * t + rl;
+                    const int pc = p < n ? p : n - 1;
+                    const f32x4* src = reinterpret_cast<const f32x4*>(Y + rb + 32 * blk + 8 * kk +
+                                                                      (int64_t)pc * ldy);
+                    ym[blk][t][0] = src[0];
+                    ym[blk][t][1] = src[1];
+                }
+        }
     };
     // the same rows with bounds: rows at or beyond wb1 and columns beyond n
     // are zero (ragged wavefronts, unaligned Y)
-    auto loadY_mx_gen = [&](int64_t rb, f32x4 (&ym)[4][NT16][2]) {
+    auto loadY_mx_gen = [&](int64_t rb, YBuf& ym) {
+        if constexpr (YT) {
+            // X rows at or beyond wb1 are zero; blocks beyond R are not read
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk)
+            for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
-            for (int t = 0; t < NT16; ++t) {
-                const int p = 16 * t + rl;
-                const int64_t r = rb + 32 * blk + 8 * kk;
-                const int64_t valid = wb1 - r;
-                float v0[4], v1[4];
-                if (p < n) {
-                    load_run<float, 4, VEC>(Y + r + (int64_t)p * ldy, valid, valid >= 4, v0);
-                    load_run<float, 4, VEC>(Y + r + 4 + (int64_t)p * ldy, valid - 4, valid >= 8, v1);
-                } else {
+                for (int t = 0; t < NT16; ++t)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) v0[q] = v1[q] = 0.f;
+                    for (int e = 0; e < 3; ++e) {
+                        const int64_t b = (rb >> 5) + blk;
+                        ym[blk][t][e] = b < nblk ? Yt[(b * NT16 + t) * 3 * WAVE + e * WAVE + lane]
+                                                 : u32x4{0u, 0u, 0u, 0u};
+                    }
+        } else {
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+                for (int t = 0; t < NT16; ++t) {
+                    const int p = 16 * t + rl;
+                    const int64_t r = rb + 32 * blk + 8 * kk;
+                    const int64_t valid = wb1 - r;
+                    float v0[4], v1[4];
+                    if (p < n) {
+                        load_run<float, 4, VEC>(Y + r + (int64_t)p * ldy, valid, valid >= 4, v0);
+                        load_run<float, 4, VEC>(Y + r + 4 + (int64_t)p * ldy, valid - 4, valid >= 8,
+                                                v1);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v0[q] = v1[q] = 0.f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ym[blk][t][0][q] = v0[q];
+                        ym[blk][t][1][q] = v1[q];
+                    }
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ym[blk][t][0][q] = v0[q];
-                    ym[blk][t][1][q] = v1[q];
-                }
-            }
+        }
     };
     // products kept: hi*(Y1 + Y2 + Y3) (+ lo*(Y1 + Y2)), as in tsm2r_lp
-    auto step_mx = [&](const uint32_t (&xv)[XG][NPL][4], const f32x4 (&ym)[4][NT16][2]) {
+    auto step_mx = [&](const uint32_t (&xv)[XG][NPL][4], const YBuf& ym) {
         wave_lds_fence();
 #pragma unroll
         for (int cg = 0; cg < XG; ++cg)
@@ -798,13 +833,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             u32x4 y1[NT16], y2[NT16], y3[NT16];
 #pragma unroll
             for (int t = 0; t < NT16; ++t) {
-                float y[8];
+                if constexpr (YT) {
+                    y1[t] = ym[blk][t][0];
+                    y2[t] = ym[blk][t][1];
+                    y3[t] = ym[blk][t][2];
+                } else {
+                    float y[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    y[q] = ym[blk][t][0][q];
-                    y[4 + q] = ym[blk][t][1][q];
+                    for (int q = 0; q < 4; ++q) {
+                        y[q] = ym[blk][t][0][q];
+                        y[4 + q] = ym[blk][t][1][q];
+                    }
+                    bf16_terms8(y, y1[t], y2[t], y3[t]);
                 }
-                bf16_terms8(y, y1[t], y2[t], y3[t]);
             }
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
@@ -829,7 +870,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     if (MX && wb1 > wb0 && mx_whole) {
         const int64_t nit = (wb1 - wb0) / SR;
         uint32_t xa[XG][NPL][4], xb[XG][NPL][4];
-        f32x4 ym[4][NT16][2];
+        YBuf ym;
         if (!MX_TWO || !pf) {
             // one step at a time, no conditional loads (measured faster for
             // n <= 8, where the step is short)
@@ -867,7 +908,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         const int64_t nit = (wb1 - wb0 + SR - 1) / SR;
         for (int64_t it = 0; it < nit; ++it) {
             uint32_t xv[XG][NPL][4];
-            f32x4 ym[4][NT16][2];
+            YBuf ym;
             loadX(wb0 + it * SR, xv);
             loadY_mx_gen(wb0 + it * SR, ym);
             step_mx(xv, ym);
@@ -1157,21 +1198,22 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
     const int ni = (int)L.n;
     // Y is re-read by every column group: cached loads when there are several
     const bool yc = gx > 1;
-#define TSM_T(F, NT, CT, SP, YD)                                                                  \
-    {                                                                                             \
-        if (vec && yc)                                                                            \
-            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, true, YD>), g, b, 0, st, L.R, L.ncols,  \
-                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,           \
-                       L.rslice, L.part, pf);                                                     \
-        else if (vec)                                                                             \
-            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, false, YD>), g, b, 0, st, L.R, L.ncols, \
-                       ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,           \
-                       L.rslice, L.part, pf);                                                     \
-        else                                                                                      \
-            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, false, false, YD>), g, b, 0, st, L.R,         \
-                       L.ncols, ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O, L.ldo,  \
-                       L.rslice, L.part, pf);                                                     \
-        return 0;                                                                                 \
+    const u32x4* yt = (const u32x4*)L.yt;
+#define TSM_T(F, NT, CT, SP, YD, ...)                                                              \
+    {                                                                                               \
+        if (vec && yc)                                                                              \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, true, YD, ##__VA_ARGS__>), g, b, 0, st,   \
+                       L.R, L.ncols, ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O,      \
+                       L.ldo, L.rslice, L.part, yt, pf);                                            \
+        else if (vec)                                                                               \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, true, false, YD, ##__VA_ARGS__>), g, b, 0, st,  \
+                       L.R, L.ncols, ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O,      \
+                       L.ldo, L.rslice, L.part, yt, pf);                                            \
+        else                                                                                        \
+            TSM_LAUNCH((tn_lp_kernel<F, NT, CT, SP, false, false, YD, ##__VA_ARGS__>), g, b, 0, st, \
+                       L.R, L.ncols, ni, xh, xl, L.ldx, (const float*)L.Y, L.ldy, (float*)L.O,      \
+                       L.ldo, L.rslice, L.part, yt, pf);                                            \
+        return 0;                                                                                   \
     }
     // Y straight from L2 when several column groups re-read it (measured,
     // bf16 split, 16384^2, n = 8: 4.9 TB/s staged, 5.2 direct, 5.85 direct
@@ -1193,6 +1235,11 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
         }                                                                                 \
     }
     if (fmt == FMT_BF16) {
+        if (yt) {
+            // Y split once into packed terms: four tiles per workgroup, n > 16
+            if (L.ct != 4 || L.n <= 16) return 1;
+            if (split) TSM_T(FMT_BF16, 2, 4, true, true, true) else TSM_T(FMT_BF16, 2, 4, false, true, true)
+        }
         if (L.ct == 4 && L.n <= 16) {
             if (split) TSM_T(FMT_BF16, 1, 4, true, true) else TSM_T(FMT_BF16, 1, 4, false, true)
         }
@@ -1206,6 +1253,11 @@ static int launch_tn_lp_main(const LaunchTN& L, int dtype, hipStream_t st) {
 }
 
 int launch_tn_lp(const LaunchTN& L, int dtype, hipStream_t st) {
+    if (L.yt) {
+        // Y's bf16 terms in the operand order, as for B in tsm2r_lp (rows
+        // of Y are the reduction index here: Y(j, p) = Y[j + p*ldy])
+        if (launch_split_b(L.R, L.n, (const float*)L.Y, 1, L.ldy, dtype, (void*)L.yt, st)) return 1;
+    }
     const int rc = launch_tn_lp_main(L, dtype, st);
     if (rc || L.S <= 1) return rc;
     return launch_split_reduce(DT_F32, L.groups, L.S, L.n <= 16 ? 16 : 32, 16, L.ncols, (int)L.n,

@@ -181,8 +181,8 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // 5.4 -> 6.5 in the access-pattern probe of this grid)
     // For n > 16 the four tiles take Y's bf16 terms split once per call into
     // the workspace (their registers would not hold the split in the step;
-    // A 16384^2, n = 32, probe of this grid: split 4.4 -> 5.6 TB/s, single
-    // 3.4 -> 4.2), while Y's terms stay below 256 MB (R up to 2.7 M rows).
+    // A 16384^2, n = 32: split 4.4 -> 5.3 TB/s, single 3.4 -> 4.7), while
+    // Y's terms stay below 256 MB (R up to 2.7 M rows).
     const bool bf = dt == DT_BF16 || dt == DT_BF16_SPLIT;
     const size_t yt_bytes = lp_bterms_bytes(R, n);
     const bool four = bf && cdiv(ncols, 16) > 4 && (n <= 16 || yt_bytes <= ((size_t)256 << 20));

@@ -568,8 +568,10 @@ __attribute__((amdgpu_waves_per_eu(lp_l_waves<KS, NT16>(), 8))) void tsm2l_lp_ke
 // terms are split once per call into the workspace, packed in the operand
 // order, and the step loads them instead of splitting Y in registers.
 // --------------------------------------------------------------------------
+// (YT instances run one workgroup per CU, held there by their LDS: their
+// registers need not leave room for a second wavefront per SIMD)
 template <int FMT, int NT16, int CT, bool SPLIT, bool VEC, bool YC, bool YD, bool YT = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void tn_lp_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YT ? 1 : 2, 8))) void tn_lp_kernel(
     int64_t R, int64_t ncols, int n, const uint16_t* __restrict__ Xh,
     const uint16_t* __restrict__ Xl, int64_t ldx, const float* __restrict__ Y, int64_t ldy,
     float* __restrict__ O, int64_t ldo, int64_t rslice, double* __restrict__ part,
@@ -585,8 +587,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     constexpr int NB = SR / 16;                // 16-row blocks per step
     constexpr int NPL = SPLIT ? 2 : 1;
     // bfloat16 planes with Y direct run on the 16-bit matrix cores (MX): all
-    // of their wavefronts, whole or ragged; the split form with n > 16 keeps
-    // the float path (its registers would not hold the MX step)
+    // of their wavefronts, whole or ragged.  The split form with n > 16 does
+    // so only with Y's terms packed once per call (YT): with the split of Y
+    // in registers its step does not fit, and it keeps the float path
     constexpr bool MX = FMT == FMT_BF16 && YD && (!SPLIT || NT16 == 1 || YT);
     static_assert(!YT || (FMT == FMT_BF16 && YD), "packed Y terms feed the bf16 matrix cores");
     constexpr int SROW16 = SR + 8;             // padded 16-bit LDS column (16 more bytes)
@@ -723,7 +726,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     // MX step too, with bounds-checked loads
     const bool mx_whole = MX && VEC && YC && c0 + NX <= ncols && (wb1 - wb0) % SR == 0;
     // two steps in flight need two X steps in registers: not with four split tiles
-    constexpr bool MX_TWO = MX && !YT && !(SPLIT && CT >= 4);
+    constexpr bool MX_TWO = MX && !(SPLIT && CT >= 4);
     auto loadX_full = [&](int64_t rb, uint32_t (&xv)[XG][NPL][4]) {
 #pragma unroll
         for (int pl = 0; pl < NPL; ++pl) {

@@ -221,12 +221,14 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // steps move twice the bytes: only when the grid holds more than two
     // workgroups per CU (at A 16384^2, n = 8, one round of 512 workgroups:
     // 5.80 TB/s without, 5.21 with; at 32768^2, four rounds: 6.34 -> 6.51
-    // (n = 8), 5.89 -> 6.17 (n = 16)).  The bf16 single form with several
-    // column groups runs on the bf16 matrix cores (tn_lp_kernel, MX), where
-    // for n <= 8 one step at a time measured faster than two (A 16384^2,
-    // bf16 single, n = 8: 5.2 TB/s with two steps, 5.8 with one).
+    // (n = 8), 5.89 -> 6.17 (n = 16)).  bfloat16 planes with several column
+    // groups run on the bf16 matrix cores (tn_lp_kernel, MX): with four tiles
+    // the single form takes two steps (probe, A 16384^2, n = 8: 6.6 TB/s
+    // against 5.8 with one; packed dC terms, n = 32: 4.7 against 3.8) and the
+    // split form one (two do not fit its registers); with two tiles (an
+    // override) one step for n <= 8 (5.5 against 4.9 TB/s).
     const bool split = dt == DT_BF16_SPLIT || dt == DT_F16_SPLIT;
-    const bool mx = bf && (!split || n <= 16) && P.groups / P.ct > 1;
+    const bool mx = bf && (!split || n <= 16 || P.yt) && P.groups / P.ct > 1;
     const bool pf = plain_dtype(dt) ? n > 16
                     : mx            ? P.ct == 4 || n > 8
                                     : !split || n > 16 || (P.groups / P.ct) * P.S > 2 * (int64_t)cus;

@@ -267,8 +267,9 @@ def test_caller_workspace_precision_form(dev, lo, rowB):
 def test_caller_workspace_precision_form_grad_b(dev, lo, n):
     """dB on bfloat16 planes: for n > 16 the workspace holds dC's packed bf16
     terms after the slice partials; tsm2x_workspace_size covers them, the
-    result with the caller's workspace equals the library buffer's bit for
-    bit, and a workspace too small is refused before any launch."""
+    result with the caller's (256-byte aligned) workspace equals the library
+    buffer's bit for bit, and a workspace too small is refused before any
+    launch."""
     m, k = 8192, 4096
     A = dev_matrix(29, si.STREAM_A, m, k, torch.float32, dev)
     dC = dev_matrix(29, si.STREAM_DC, m, n, torch.float32, dev)
@@ -276,8 +277,8 @@ def test_caller_workspace_precision_form_grad_b(dev, lo, n):
     nb = tsm.workspace_size(tsm.OP_GRAD_B, m, k, n, S.dtype_code)
     if n > 16:
         assert nb >= (m // 32) * 2 * 3 * 64 * 16        # dC's packed terms
-    ws = torch.empty(nb + 16, dtype=torch.uint8, device=dev)
-    dB = tsm.grad_b(S, dC, workspace=ws[16:])
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    dB = tsm.grad_b(S, dC, workspace=ws)
     assert torch.equal(dB, tsm.grad_b(S, dC))
     if nb > 0:
         dB2 = tsm.empty_colmajor(k, n, torch.float32, dev).fill_(7.0)

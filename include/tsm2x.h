@@ -174,6 +174,10 @@ int tsm_grad_a(int64_t m, int64_t k, int64_t n, const void* dC, int64_t lddc,
  * 16 columns of A, dC enters the bf16 matrix cores as three bf16 terms per
  * value (exact for finite dC in bfloat16's normal range), with the products
  * tsm2r keeps; a non-finite dC entry then gives NaN in its column of dB.
+ * The workspace holds the slice partials and, for bfloat16 planes with
+ * n > 16, dC's packed bf16 terms (192 bytes per row of dC);
+ * tsm2x_workspace_size(TSM_OP_GRAD_B, m, k, n, dtype) gives its size, and a
+ * caller's workspace must be 256-byte aligned (TSM_ERR_WORKSPACE otherwise).
  * Arguments: 1 m, 2 k, 3 n, 4 A, 5 lda, 6 dC, 7 lddc, 8 dB, 9 lddb,
  * 10 dtype, 11 ws, 12 ws_bytes, 13 stream (ws may be NULL: library buffer). */
 int tsm_grad_b(int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,

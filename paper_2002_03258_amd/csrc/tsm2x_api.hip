@@ -182,7 +182,7 @@ TNPlan plan_tn(int64_t R, int64_t ncols, int64_t n, int dt, int cus) {
     // For n > 16 the four tiles take Y's bf16 terms split once per call into
     // the workspace (their registers would not hold the split in the step;
     // A 16384^2, n = 32: split 4.4 -> 5.3 TB/s, single 3.4 -> 4.7), while
-    // Y's terms stay below 256 MB (R up to 2.7 M rows).
+    // Y's terms stay below 256 MB (192 bytes per row: R up to 1.4 M).
     const bool bf = dt == DT_BF16 || dt == DT_BF16_SPLIT;
     const size_t yt_bytes = lp_bterms_bytes(R, n);
     const bool four = bf && cdiv(ncols, 16) > 4 && (n <= 16 || yt_bytes <= ((size_t)256 << 20));
